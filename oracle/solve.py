@@ -1,0 +1,33 @@
+"""End-to-end oracle solve: build, precondition, FGMRES (test infrastructure)."""
+import numpy as np
+
+from . import discretisation as dsc
+from . import krylov, network
+
+
+class Problem:
+    """Oracle view of one problem: discretisation, RHS and (optionally) the network."""
+
+    def __init__(self, prob, blob=None):
+        self.D = dsc.Discretisation(prob)
+        self.b = dsc.rhs(self.D)
+        self.diag = dsc.diagonal(self.D)
+        self.net = network.Net(blob) if blob is not None else None
+        self.fields = network.coeffnet(self.net, self.D) if self.net is not None else None
+
+    def apply(self, x):
+        return dsc.apply_L(self.D, x).reshape(-1)
+
+    def precond(self, v):
+        return network.vcycle(self.net, self.fields, self.diag, v, self.D).reshape(-1)
+
+    def solve(self, rtol=1e-10, restart=30, max_iters=20000, use_net=True, record=None):
+        M = self.precond if (use_net and self.net is not None) else None
+        x, st = krylov.fgmres(self.apply, self.b.reshape(-1), M, restart, rtol, max_iters,
+                              record=record)
+        return x.reshape(self.D.N, self.D.cells), st
+
+
+def relative_residual(P, x):
+    r = P.b.reshape(-1) - P.apply(np.asarray(x).reshape(-1))
+    return float(np.linalg.norm(r) / np.linalg.norm(P.b))
