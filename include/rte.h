@@ -1,0 +1,248 @@
+/*
+ * rte.h -- C ABI of librte: MgNet-preconditioned flexible GMRES for the steady
+ * discrete-ordinates radiative transfer equation on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Problem (paper Sec. 1, eq. (RTE), eq. (hg), eq. (boundary_condition); Sec. 2.1,
+ * eq. (DORTE_2d)): on the unit square or cube with I cubic cells per axis,
+ * find psi_{m,c} (direction m, cell c) with
+ *
+ *   sum_a |u_{m,a}|/h (psi_{m,c} - psi_{m,c-s_a e_a}) + sT_c psi_{m,c}
+ *        - sS_c sum_n S_mn psi_{n,c} = b_{m,c}
+ *
+ * (first-order upwind finite volumes, s_a = sign(u_{m,a})), sT = sigma_T/eps,
+ * sS = sigma_T/eps - eps sigma_a, b = eps q plus the inflow carried in across
+ * boundary faces, and S = K W the Henyey-Greenstein kernel matrix, scaled
+ * symmetrically so that its quadrature-weighted rows and columns sum to one.
+ * The learned preconditioner is the CoeffNet + MgNet pair of Sec. 3.
+ *
+ * Conventions for every function:
+ *   - the return value is an rte_status; RTE_OK is 0; on any other value a
+ *     message is available from rte_last_error() on the calling thread;
+ *   - no output is modified on error, except where a function says otherwise;
+ *   - "device" pointers are HIP device memory on the current device (for
+ *     example a torch tensor's data_ptr()); "host" pointers are ordinary
+ *     memory; the library never takes ownership of caller memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     functions that take a stream enqueue their work on it and return
+ *     without waiting unless they say otherwise;
+ *   - vectors over the discretisation are direction-major: element
+ *     [m * cells + c], with cells ordered x fastest then y then z.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RTE_OK = 0,
+  RTE_EINVAL = -1,      /* invalid argument or input data                    */
+  RTE_ENOMEM = -2,      /* workspace too small, allocation failed, budget   */
+  RTE_EDEVICE = -3,     /* a HIP runtime call failed                         */
+  RTE_ENOCONV = -4,     /* solve stopped before the tolerance; x and stats valid */
+  RTE_EBREAKDOWN = -5,  /* non-finite values appeared in the Krylov process  */
+  RTE_EAGAIN = -6,      /* poll: not finished yet / submit: server full      */
+  RTE_EFORMAT = -7,     /* malformed MGN1 weights blob                       */
+  RTE_ENOTFOUND = -8    /* unknown ticket                                    */
+} rte_status;
+
+/* Scattering kernel choice (eq. (hg)).  FLATLAND: (1-g^2)/(1+g^2-2g mu), the
+ * circle analogue, whose mean cosine is g.  SPHERE: eq. (hg) as printed,
+ * (1-g^2)/(1+g^2-2g mu)^{3/2}.  AUTO: FLATLAND when every direction has
+ * z = 0, else SPHERE. */
+enum { RTE_HG_AUTO = 0, RTE_HG_FLATLAND = 1, RTE_HG_SPHERE = 2 };
+enum { RTE_FP32 = 0, RTE_FP64 = 1 };
+/* Preconditioner of rte_solve: none, MgNet with BF16 MFMA convolutions, or
+ * MgNet with FP32 MFMA convolutions (FP32 accumulation in both). */
+enum { RTE_PC_NONE = 0, RTE_PC_MGNET_BF16 = 1, RTE_PC_MGNET_FP32 = 2 };
+
+typedef struct rte_operator rte_operator;
+typedef struct mgnet_model mgnet_model;
+typedef struct rte_server rte_server;
+
+/* Angular and spatial discretisation (Sec. 2.1; Sec. 2.2 first paragraph). */
+typedef struct {
+  int dim;                /* 2 or 3; domain [0,1]^dim                            */
+  int n[3];               /* cells per axis x, y, z (n[2] = 1 in 2D); all equal  */
+  int ndir;               /* number of directions N, 1..256                      */
+  const double* dirs;     /* host [ndir][3] unit vectors (z ignored in 2D)        */
+  const double* weights;  /* host [ndir], positive, summing to 1 (+-1e-12)        */
+  double g;               /* HG anisotropy, |g| < 1                              */
+  int kernel;             /* RTE_HG_*                                            */
+} rte_geometry;
+
+/* Per-cell medium (eq. (RTE): sigma_T, sigma_a, q, eps; Sec. 2.2 cell values).
+ * All arrays are host [cells] in cell order.  The library copies what it
+ * needs before rte_build_operator returns. */
+typedef struct {
+  const double* sigma_t;  /* > 0                                                 */
+  const double* sigma_a;  /* >= 0, with sigma_t/eps - eps*sigma_a >= 0           */
+  const double* q;        /* >= 0                                                */
+  const double* eps;      /* 0 < eps <= 1, or NULL to use eps_scalar everywhere  */
+  double eps_scalar;
+  /* Inflow data Psi (eq. (boundary_condition_2d)): host array
+   * [2*dim faces][ndir][face_stride] doubles, faces x-, x+, y-, y+, z-, z+;
+   * face cells ordered with the lower remaining axis fastest.  Only entries
+   * of directions entering through that face (u.n < 0) are read.  NULL means
+   * zero inflow.  face_stride = 0 means the largest face's cell count. */
+  const double* inflow;
+  size_t inflow_face_stride;
+} rte_medium;
+
+typedef struct {
+  int dim, nx, ny, nz, ndir;
+  int kernel;             /* resolved RTE_HG_FLATLAND or RTE_HG_SPHERE            */
+  int64_t cells, n;       /* n = ndir * cells                                    */
+  double h, g;
+  int has_fields;         /* CoeffNet fields were built for a model              */
+} rte_operator_info;
+
+/* Build the operator: validate inputs, form S, the scaled coefficients and
+ * the right-hand side b in FP64 on the host, upload them, and -- when
+ * `model` is not NULL -- run CoeffNet on the device to produce the per-level
+ * fields a^[l], a^{-1,[l]} that MgNet reads (Sec. 3.2).  The model must
+ * match the geometry (dim, ndir; every extent divisible by 2^(levels-1)).
+ * The returned handle is immutable and may be shared by concurrent solves;
+ * the model must outlive it.  Errors: RTE_EINVAL (bad geometry or medium),
+ * RTE_ENOMEM, RTE_EDEVICE.  Synchronises `stream` before returning. */
+rte_status rte_build_operator(const rte_geometry* geom, const rte_medium* med,
+                              const mgnet_model* model, void* stream, rte_operator** out);
+rte_status rte_operator_free(rte_operator* op);
+rte_status rte_operator_get_info(const rte_operator* op, rte_operator_info* info);
+
+/* Copy an internal array of the operator into caller device memory, for
+ * inspection and testing.  which / layout / bytes:
+ *   RTE_ARR_RHS     b,            FP64 [ndir][cells]
+ *   RTE_ARR_SCATTER S,            FP64 [ndir][ndir] row-major
+ *   RTE_ARR_SIGMA   (sT, sA),     FP64 [2][cells]   (sA = eps sigma_a)
+ *   RTE_ARR_FIELD_A a^[level],    FP32 [cells_l][C_l] (channels fastest)
+ *   RTE_ARR_FIELD_AINV a^{-1,[level]}, same layout
+ * `bytes` must equal the array size.  Errors: RTE_EINVAL. */
+enum { RTE_ARR_RHS = 0, RTE_ARR_SCATTER = 1, RTE_ARR_SIGMA = 2,
+       RTE_ARR_FIELD_A = 3, RTE_ARR_FIELD_AINV = 4 };
+rte_status rte_operator_copy_array(const rte_operator* op, int which, int level,
+                                   void* dst, size_t bytes, void* stream);
+
+/* Parse and validate an MGN1 weights blob (CoeffNet + MgNet of Sec. 3.2-3.3;
+ * FP32 tensors; layout documented with the weights writer).  Host-only: the
+ * weights are uploaded to a device on first use.  The blob may be freed
+ * after return.  Errors: RTE_EFORMAT (bad magic, version, truncation,
+ * missing/duplicate/misshapen tensors, trailing bytes), RTE_EINVAL. */
+rte_status mgnet_load(const void* blob, size_t bytes, mgnet_model** out);
+rte_status mgnet_free(mgnet_model* model);
+/* dims_out[8] = {dim, ndir, c0, levels, nu_pre, nu_post, nu_coarse, coef_ch}. */
+rte_status mgnet_describe(const mgnet_model* model, int* dims_out);
+
+/* y = L x (paper eq. (DORTE_2d), discretised as above).  precision RTE_FP32:
+ * x, y are float [n]; RTE_FP64: double [n].  x and y must not overlap.
+ * Errors: RTE_EINVAL. */
+rte_status rte_apply(const rte_operator* op, const void* x, void* y, int precision, void* stream);
+
+/* r = b - L x in FP64 (double [n] each; may not overlap).  Errors: RTE_EINVAL. */
+rte_status rte_residual(const rte_operator* op, const double* x, double* r, void* stream);
+
+/* z = M(v): one MgNet V-cycle (Sec. 3.3) with the operator's CoeffNet
+ * fields.  v: device double [n]; z: device float [n].  precond is
+ * RTE_PC_MGNET_BF16 or RTE_PC_MGNET_FP32.  The workspace (device memory of
+ * at least rte_precond_workspace_bytes) holds the level activations.
+ * Errors: RTE_EINVAL (no fields built, model mismatch), RTE_ENOMEM (small
+ * workspace). */
+rte_status rte_precond_workspace_bytes(const rte_operator* op, const mgnet_model* model,
+                                       size_t* bytes);
+rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, int precond,
+                             const double* v, float* z, void* workspace, size_t ws_bytes,
+                             void* stream);
+
+typedef struct {
+  int restart;            /* Krylov cycle length k, 1..64 (paper: GMRES)          */
+  double rtol;            /* stop when ||b - L x||_2 <= rtol ||b||_2, checked in FP64 */
+  int max_iters;          /* total inner iterations, >= 1                         */
+  int precond;            /* RTE_PC_*                                             */
+  const double* x0;       /* device double [n] initial guess, or NULL for zero    */
+  const double* b;        /* device double [n] right-hand side, or NULL for the built b */
+} rte_solve_opts;
+
+typedef struct {
+  int iterations;         /* inner FGMRES steps taken                             */
+  int restarts;           /* completed cycles                                     */
+  int converged;          /* 1 if the FP64 true residual met rtol                 */
+  int status;             /* the rte_status the solve ended with                  */
+  double rel_residual;    /* ||b - L x||_2 / ||b||_2 in FP64 at exit              */
+  double ms_total;        /* wall time of the solve                               */
+} rte_solve_stats;
+
+/* Workspace for rte_solve: Krylov bases V (FP64, k+1 vectors), Z (FP32, k
+ * vectors), reduction scratch and, for MgNet, the level activations.
+ * Errors: RTE_EINVAL. */
+rte_status rte_workspace_bytes(const rte_operator* op, const mgnet_model* model,
+                               const rte_solve_opts* opts, size_t* bytes);
+
+/* Right-preconditioned flexible GMRES(k) (Krylov solve of Sec. 3 and Sec. 4.2,
+ * flexible because the preconditioner runs in reduced precision): inner
+ * operator applies and preconditioning in FP32 (or BF16 convolutions),
+ * orthogonalisation (two-pass classical Gram-Schmidt), Hessenberg least
+ * squares and the restart residual b - L x in FP64 on the device.
+ * psi_out: device double [n], the solution x (also used as the iterate).
+ * stats (host) is filled on RTE_OK, RTE_ENOCONV and RTE_EBREAKDOWN.
+ * Blocks the calling thread until the solve ends.
+ * Errors: RTE_EINVAL, RTE_ENOMEM (workspace smaller than required),
+ * RTE_ENOCONV, RTE_EBREAKDOWN, RTE_EDEVICE. */
+rte_status rte_solve(const rte_operator* op, const mgnet_model* model, const rte_solve_opts* opts,
+                     void* workspace, size_t ws_bytes, double* psi_out, rte_solve_stats* stats,
+                     void* stream);
+
+/* ---- serving: continuous batching of independent solves ----
+ * A server owns a worker thread and `max_slots` HIP streams.  Requests are
+ * admitted in arrival order when a slot is free and their workspace fits in
+ * the caller-provided device arena (admission by HBM footprint); admitted
+ * solves advance concurrently, one Krylov step per slot per scheduling
+ * round, and retire as they finish, freeing slot and arena space for the
+ * next request.  Each solve runs exactly the kernels rte_solve runs, so its
+ * result does not depend on what else is in flight. */
+typedef struct {
+  int64_t submitted, completed, active, queued;
+  size_t arena_bytes, arena_in_use, arena_peak;
+} rte_server_stats;
+
+/* arena: device memory of arena_bytes owned by the caller, which must
+ * outlive the server.  max_slots: 1..64.  Errors: RTE_EINVAL, RTE_EDEVICE. */
+rte_status rte_server_create(void* arena, size_t arena_bytes, int max_slots, rte_server** out);
+/* Queue a solve.  op, model and psi_out (device double [n]) must stay valid
+ * until the ticket is polled as finished.  Errors: RTE_EINVAL, RTE_ENOMEM
+ * (the request can never fit the arena), RTE_EAGAIN (queue of 4096 full). */
+rte_status rte_submit(rte_server* srv, const rte_operator* op, const mgnet_model* model,
+                      const rte_solve_opts* opts, double* psi_out, uint64_t* ticket);
+/* RTE_EAGAIN while queued or running; once finished, fills *stats (host,
+ * may be NULL), forgets the ticket and returns the solve's own status.
+ * Errors: RTE_ENOTFOUND for an unknown or already collected ticket. */
+rte_status rte_poll(rte_server* srv, uint64_t ticket, rte_solve_stats* stats);
+rte_status rte_server_query(rte_server* srv, rte_server_stats* out);
+/* Finish every queued and running request, then free the server. */
+rte_status rte_server_destroy(rte_server* srv);
+
+/* ---- kernel timing: HIP events around launches of one kernel class ----
+ * When enabled, every launch of the class records an event pair on the
+ * stream it is launched on; rte_prof_query synchronises those events and
+ * returns, since the last reset, the summed duration, the launch count and
+ * the summed algorithmic work of those launches: FLOPs for RTE_K_CONV
+ * (2 x rows x cout x cin x taps), bytes that must cross HBM for the
+ * bandwidth-bound classes (operands read once, results written once), and
+ * 0 for RTE_K_PRECOND (a composite: the whole V-cycle). */
+enum { RTE_K_APPLY = 0, RTE_K_RESIDUAL = 1, RTE_K_CONV = 2, RTE_K_ORTH = 3,
+       RTE_K_PRECOND = 4, RTE_K_COUNT = 5 };
+rte_status rte_prof_enable(int kernel_class, int on);
+rte_status rte_prof_query(int kernel_class, double* total_ms, int64_t* launches, double* work);
+rte_status rte_prof_reset(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* rte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

@@ -1,0 +1,310 @@
+// extern "C" entry points of librte: argument checks, error mapping and the
+// kernel-class event timer.
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace rte {
+
+Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Model* model, hipStream_t stream);
+Model* parse_mgn1(const void* blob, size_t bytes);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(rte_status code, const std::string& msg) { throw Error(code, msg); }
+
+// ------------------------------------------------------------- profiler ---
+namespace {
+struct Prof {
+  std::mutex mu;
+  bool on[RTE_K_COUNT] = {};
+  struct Rec {
+    hipEvent_t e0, e1;
+    double work;
+  };
+  std::vector<Rec> pending[RTE_K_COUNT];
+  std::vector<hipEvent_t> pool;
+  double ms[RTE_K_COUNT] = {};
+  double work[RTE_K_COUNT] = {};
+  int64_t count[RTE_K_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    RTE_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void drain(int c) {
+    for (auto& pr : pending[c]) {
+      RTE_HIP(hipEventSynchronize(pr.e1));
+      float t = 0;
+      RTE_HIP(hipEventElapsedTime(&t, pr.e0, pr.e1));
+      ms[c] += t;
+      work[c] += pr.work;
+      count[c] += 1;
+      pool.push_back(pr.e0);
+      pool.push_back(pr.e1);
+    }
+    pending[c].clear();
+  }
+};
+Prof& prof() {
+  static Prof* p = new Prof();  // never destroyed: events outlive static teardown order
+  return *p;
+}
+}  // namespace
+
+ProfScope::ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+  Prof& P = prof();
+  if (!P.on[c]) return;
+  std::lock_guard<std::mutex> lk(P.mu);
+  e0 = P.get();
+  RTE_HIP(hipEventRecord(e0, s));
+}
+
+ProfScope::~ProfScope() {
+  if (!e0) return;
+  Prof& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  try {
+    e1 = P.get();
+    (void)hipEventRecord(e1, s);
+    P.pending[cls].push_back({e0, e1, work});
+    if (P.pending[cls].size() >= 65536) P.drain(cls);
+  } catch (...) {
+  }
+}
+
+}  // namespace rte
+
+using namespace rte;
+
+namespace {
+
+template <class F>
+rte_status guarded(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return RTE_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return RTE_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return RTE_EDEVICE;
+  }
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+
+extern "C" {
+
+const char* rte_last_error(void) { return g_last_error.c_str(); }
+
+rte_status mgnet_load(const void* blob, size_t bytes, mgnet_model** out) {
+  return guarded([&] {
+    RTE_REQUIRE(out != nullptr, RTE_EINVAL, "mgnet_load: null output");
+    std::unique_ptr<Model> m(parse_mgn1(blob, bytes));
+    auto* h = new mgnet_model();
+    h->m = std::move(m);
+    *out = h;
+  });
+}
+
+rte_status mgnet_free(mgnet_model* model) {
+  return guarded([&] { delete model; });
+}
+
+rte_status mgnet_describe(const mgnet_model* h, int* d) {
+  return guarded([&] {
+    RTE_REQUIRE(h && d, RTE_EINVAL, "mgnet_describe: null argument");
+    const Model& m = *h->m;
+    int v[8] = {m.dim, m.ndir, m.c0, m.levels, m.nu_pre, m.nu_post, m.nu_coarse, m.coef_ch};
+    std::memcpy(d, v, sizeof(v));
+  });
+}
+
+rte_status rte_build_operator(const rte_geometry* geom, const rte_medium* med, const mgnet_model* model,
+                              void* stream, rte_operator** out) {
+  return guarded([&] {
+    RTE_REQUIRE(out != nullptr, RTE_EINVAL, "rte_build_operator: null output");
+    std::unique_ptr<Operator> op(build_operator(geom, med, model ? model->m.get() : nullptr, S(stream)));
+    auto* h = new rte_operator();
+    h->op = std::move(op);
+    *out = h;
+  });
+}
+
+rte_status rte_operator_free(rte_operator* op) {
+  return guarded([&] { delete op; });
+}
+
+rte_status rte_operator_get_info(const rte_operator* h, rte_operator_info* info) {
+  return guarded([&] {
+    RTE_REQUIRE(h && info, RTE_EINVAL, "rte_operator_get_info: null argument");
+    const Operator& o = *h->op;
+    info->dim = o.dim; info->nx = o.nx; info->ny = o.ny; info->nz = o.nz; info->ndir = o.ndir;
+    info->kernel = o.kernel; info->cells = o.cells; info->n = o.n; info->h = o.h; info->g = o.g;
+    info->has_fields = o.model != nullptr;
+  });
+}
+
+rte_status rte_operator_copy_array(const rte_operator* h, int which, int level, void* dst, size_t bytes,
+                                   void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(h && dst, RTE_EINVAL, "rte_operator_copy_array: null argument");
+    const Operator& o = *h->op;
+    const void* src = nullptr;
+    size_t need = 0;
+    DevArena tmp;
+    switch (which) {
+      case RTE_ARR_RHS: src = o.b64; need = size_t(o.n) * 8; break;
+      case RTE_ARR_SCATTER: src = o.S64; need = size_t(o.ndir) * o.ndir * 8; break;
+      case RTE_ARR_SIGMA: {
+        need = size_t(o.cells) * 16;
+        RTE_REQUIRE(bytes == need, RTE_EINVAL, "rte_operator_copy_array: wrong size");
+        RTE_HIP(hipMemcpyAsync(dst, o.sT64, size_t(o.cells) * 8, hipMemcpyDeviceToDevice, S(stream)));
+        RTE_HIP(hipMemcpyAsync(static_cast<char*>(dst) + size_t(o.cells) * 8, o.sA64, size_t(o.cells) * 8,
+                               hipMemcpyDeviceToDevice, S(stream)));
+        return;
+      }
+      case RTE_ARR_FIELD_A:
+      case RTE_ARR_FIELD_AINV: {
+        RTE_REQUIRE(o.model != nullptr, RTE_EINVAL, "operator has no CoeffNet fields");
+        RTE_REQUIRE(level >= 0 && level < o.model->levels, RTE_EINVAL, "level out of range");
+        src = which == RTE_ARR_FIELD_A ? o.fa[level] : o.fainv[level];
+        need = size_t(o.level_cells(level)) * (o.model->c0 << level) * 4;
+        break;
+      }
+      default: fail(RTE_EINVAL, "unknown array");
+    }
+    RTE_REQUIRE(bytes == need, RTE_EINVAL, "rte_operator_copy_array: wrong size");
+    RTE_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, S(stream)));
+  });
+}
+
+rte_status rte_apply(const rte_operator* h, const void* x, void* y, int precision, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(h && x && y, RTE_EINVAL, "rte_apply: null argument");
+    RTE_REQUIRE(x != y, RTE_EINVAL, "rte_apply: x and y must not alias");
+    RTE_REQUIRE(precision == RTE_FP32 || precision == RTE_FP64, RTE_EINVAL, "rte_apply: bad precision");
+    const int t = precision == RTE_FP64 ? 1 : 0;
+    launch_apply(*h->op, x, t, y, t, nullptr, precision == RTE_FP64, S(stream));
+  });
+}
+
+rte_status rte_residual(const rte_operator* h, const double* x, double* r, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(h && x && r, RTE_EINVAL, "rte_residual: null argument");
+    RTE_REQUIRE(static_cast<const void*>(x) != static_cast<const void*>(r), RTE_EINVAL,
+                "rte_residual: x and r must not alias");
+    launch_apply(*h->op, x, 1, r, 1, h->op->b64, true, S(stream));
+  });
+}
+
+rte_status rte_precond_workspace_bytes(const rte_operator* h, const mgnet_model* model, size_t* bytes) {
+  return guarded([&] {
+    RTE_REQUIRE(h && model && bytes, RTE_EINVAL, "rte_precond_workspace_bytes: null argument");
+    *bytes = precond_bytes(*h->op, *model->m);
+  });
+}
+
+rte_status rte_precond_apply(const rte_operator* h, const mgnet_model* model, int precond, const double* v,
+                             float* z, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(h && model && v && z && ws, RTE_EINVAL, "rte_precond_apply: null argument");
+    RTE_REQUIRE(precond == RTE_PC_MGNET_BF16 || precond == RTE_PC_MGNET_FP32, RTE_EINVAL,
+                "rte_precond_apply: precond must be an MgNet mode");
+    const Operator& o = *h->op;
+    Model& m = *model->m;
+    RTE_REQUIRE(o.model == &m, RTE_EINVAL, "operator was not built with this model");
+    RTE_REQUIRE(ws_bytes >= precond_bytes(o, m), RTE_ENOMEM, "rte_precond_apply: workspace too small");
+    RTE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL, "workspace must be 256-byte aligned");
+    m.ensure_on_device();
+    precond_apply(o, m, precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16, v, z, static_cast<char*>(ws),
+                  S(stream));
+  });
+}
+
+rte_status rte_workspace_bytes(const rte_operator* h, const mgnet_model* model, const rte_solve_opts* opts,
+                               size_t* bytes) {
+  return guarded([&] {
+    RTE_REQUIRE(h && opts && bytes, RTE_EINVAL, "rte_workspace_bytes: null argument");
+    const Model* m = model ? model->m.get() : nullptr;
+    validate_opts(*h->op, m, opts);
+    *bytes = solve_layout(*h->op, m, opts->restart, opts->precond != RTE_PC_NONE).total;
+  });
+}
+
+rte_status rte_solve(const rte_operator* h, const mgnet_model* model, const rte_solve_opts* opts, void* ws,
+                     size_t ws_bytes, double* psi, rte_solve_stats* stats, void* stream) {
+  rte_status solve_status = RTE_OK;
+  rte_status st = guarded([&] {
+    RTE_REQUIRE(h != nullptr && opts != nullptr, RTE_EINVAL, "rte_solve: null argument");
+    SolveRun run(*h->op, model ? model->m.get() : nullptr, *opts, static_cast<char*>(ws), ws_bytes, psi,
+                 S(stream));
+    run.start();
+    while (!run.done()) {
+      run.wait();
+      run.advance();
+    }
+    run.fill_stats(stats);
+    solve_status = run.status();
+  });
+  if (st != RTE_OK) return st;
+  if (solve_status != RTE_OK)
+    set_last_error(solve_status == RTE_ENOCONV ? "solve stopped before reaching rtol"
+                                               : "non-finite values in the Krylov process");
+  return solve_status;
+}
+
+rte_status rte_prof_enable(int c, int on) {
+  return guarded([&] {
+    RTE_REQUIRE(c >= 0 && c < RTE_K_COUNT, RTE_EINVAL, "unknown kernel class");
+    Prof& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.on[c] = on != 0;
+  });
+}
+
+rte_status rte_prof_query(int c, double* total_ms, int64_t* launches, double* work) {
+  return guarded([&] {
+    RTE_REQUIRE(c >= 0 && c < RTE_K_COUNT, RTE_EINVAL, "unknown kernel class");
+    Prof& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.drain(c);
+    if (total_ms) *total_ms = P.ms[c];
+    if (launches) *launches = P.count[c];
+    if (work) *work = P.work[c];
+  });
+}
+
+rte_status rte_prof_reset(void) {
+  return guarded([&] {
+    Prof& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (int c = 0; c < RTE_K_COUNT; ++c) {
+      P.drain(c);
+      P.ms[c] = 0;
+      P.work[c] = 0;
+      P.count[c] = 0;
+    }
+  });
+}
+
+}  // extern "C"

@@ -125,7 +125,7 @@ def p0(s=0, regime="diffusion", n=32, seed=6001):
         Y, X = media.cell_centres((n, n))
         inside = (np.abs(X - 0.5) < 0.25) & (np.abs(Y - 0.5) < 0.25)
         eps = np.where(inside, 0.01, 1.0)
-    mg = dict(c0=4, levels=3, nu_pre=2, nu_post=2, nu_coarse=2, coef_ch=3, seed=seed)
+    mg = dict(c0=16, levels=3, nu_pre=2, nu_post=2, nu_coarse=2, coef_ch=3, seed=seed)
     return _problem("P0", 2, (n, n, 1), dirs, w, 0.0, "sphere", st, sa, q, eps,
                     left_unit_inflow((n, n, 1), 2, dirs), mg,
                     dict(restart=30, rtol=1e-6, max_iters=5000))
