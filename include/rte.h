@@ -226,16 +226,18 @@ rte_status rte_server_query(rte_server* srv, rte_server_stats* out);
 rte_status rte_server_destroy(rte_server* srv);
 
 /* ---- kernel timing: HIP events around launches of one kernel class ----
- * When enabled, every launch of the class records an event pair on the
- * stream it is launched on; rte_prof_query synchronises those events and
- * returns, since the last reset, the summed duration, the launch count and
- * the summed algorithmic work of those launches: FLOPs for RTE_K_CONV
+ * rte_prof_enable(cls, every): every > 0 brackets every `every`-th launch of
+ * the class with an event pair on the stream it is launched on (1 = all
+ * launches; sampling keeps the events' own cost out of the timed work);
+ * 0 disables.  rte_prof_query synchronises the recorded events and returns,
+ * since the last reset, the summed duration, the number of timed launches
+ * and their summed algorithmic work: FLOPs for RTE_K_CONV
  * (2 x rows x cout x cin x taps), bytes that must cross HBM for the
  * bandwidth-bound classes (operands read once, results written once), and
  * 0 for RTE_K_PRECOND (a composite: the whole V-cycle). */
 enum { RTE_K_APPLY = 0, RTE_K_RESIDUAL = 1, RTE_K_CONV = 2, RTE_K_ORTH = 3,
        RTE_K_PRECOND = 4, RTE_K_COUNT = 5 };
-rte_status rte_prof_enable(int kernel_class, int on);
+rte_status rte_prof_enable(int kernel_class, int every);
 rte_status rte_prof_query(int kernel_class, double* total_ms, int64_t* launches, double* work);
 rte_status rte_prof_reset(void);
 

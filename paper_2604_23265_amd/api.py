@@ -254,8 +254,9 @@ class Server:
             pass
 
 
-def prof_enable(cls, on=True):
-    check(lib().rte_prof_enable(int(cls), 1 if on else 0))
+def prof_enable(cls, every=1):
+    """Time every `every`-th launch of a kernel class with HIP events (0 = off)."""
+    check(lib().rte_prof_enable(int(cls), int(every)))
 
 
 def prof_query(cls):

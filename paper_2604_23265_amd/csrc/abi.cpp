@@ -22,7 +22,8 @@ void fail(rte_status code, const std::string& msg) { throw Error(code, msg); }
 namespace {
 struct Prof {
   std::mutex mu;
-  bool on[RTE_K_COUNT] = {};
+  int every[RTE_K_COUNT] = {};
+  int64_t seen[RTE_K_COUNT] = {};
   struct Rec {
     hipEvent_t e0, e1;
     double work;
@@ -64,8 +65,9 @@ Prof& prof() {
 
 ProfScope::ProfScope(int c, hipStream_t st) : cls(c), s(st) {
   Prof& P = prof();
-  if (!P.on[c]) return;
+  if (P.every[c] <= 0) return;
   std::lock_guard<std::mutex> lk(P.mu);
+  if (P.every[c] <= 0 || (P.seen[c]++ % P.every[c]) != 0) return;
   e0 = P.get();
   RTE_HIP(hipEventRecord(e0, s));
 }
@@ -273,12 +275,14 @@ rte_status rte_solve(const rte_operator* h, const mgnet_model* model, const rte_
   return solve_status;
 }
 
-rte_status rte_prof_enable(int c, int on) {
+rte_status rte_prof_enable(int c, int every) {
   return guarded([&] {
     RTE_REQUIRE(c >= 0 && c < RTE_K_COUNT, RTE_EINVAL, "unknown kernel class");
+    RTE_REQUIRE(every >= 0, RTE_EINVAL, "sampling stride must be >= 0");
     Prof& P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
-    P.on[c] = on != 0;
+    P.every[c] = every;
+    P.seen[c] = 0;
   });
 }
 

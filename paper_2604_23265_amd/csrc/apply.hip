@@ -1,91 +1,118 @@
 // Discrete-ordinates operator apply (eq. (DORTE_2d), step-upwind finite
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
-// Layout: x, y direction-major [N][cells].  A 256-thread block owns 64
-// consecutive cells and all N directions.  The block stages x[:, tile] in
-// LDS (coalesced rows of 64 cells per direction); each wave then takes four
-// directions at a time, one cell per lane: the scatter sum_n S_mn x_n reads
-// S through wave-uniform (scalar) loads and x_n from LDS, reusing each LDS
-// read for four directions; the upwind neighbour comes from global memory
-// (the same or an adjacent row, cached).  Collision uses the
+// Layout: x, y direction-major [N][cells].  A 256-thread block owns 16
+// consecutive cells and all N directions (1024 blocks for a 128^2 grid, so
+// the chip holds many waves in flight).  The block stages x[:, tile] in LDS
+// (rows of 16 cells per direction); each thread then owns one cell and the
+// directions d, d + 16, ...: the scatter sum_n S_mn x_n reads S from LDS and
+// reuses each x_n read for all of the thread's directions; the upwind
+// neighbours come from global memory (the same or an adjacent row, cached)
+// and are requested before the scatter loop so their latency overlaps it.  Collision uses the
 // cancellation-free form sT (x - Sx) + sA Sx = sT x - sS Sx.
 #include "common.h"
 
 namespace rte {
 namespace {
 
-constexpr int TILE = 64;
-constexpr int MB = 4;  // directions per lane per pass
+constexpr int TILE = 16;   // cells per block
+constexpr int DSLOTS = 16; // direction slots per block: thread t -> cell t % 16, slot t / 16
 
-template <class T, class TI, class TO, bool RES, bool LDS>
+// Thread (cell c, slot d) computes directions m = d, d + 16, ... (< N, at
+// most DPT of them).  The block stages x[:, tile] (and S when it fits) in
+// LDS; the scatter sum_n S_mn x_n then reuses each x_n read for all of the
+// thread's directions.  Upwind neighbours are requested before the scatter.
+template <class T, class TI, class TO, bool RES, bool LDS_S, int DPT>
 __global__ __launch_bounds__(256) void apply_kernel(const TI* __restrict__ x, TO* __restrict__ y,
                                                     const double* __restrict__ b,
                                                     const T* __restrict__ sT, const T* __restrict__ sA,
                                                     const T* __restrict__ S, const T* __restrict__ dc,
                                                     const int* __restrict__ sg, int N, int nx, int ny,
-                                                    int nz, int64_t cells) {
+                                                    int nz, int cells) {
   extern __shared__ char smem[];
-  T* xs = reinterpret_cast<T*>(smem);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int64_t c0 = int64_t(blockIdx.x) * TILE;
-  if (LDS) {
-    for (int idx = threadIdx.x; idx < N * TILE; idx += 256) {
-      int m = idx / TILE, cl = idx - m * TILE;
-      int64_t cc = c0 + cl;
-      xs[idx] = cc < cells ? T(x[int64_t(m) * cells + cc]) : T(0);
-    }
-    __syncthreads();
+  T* xs = reinterpret_cast<T*>(smem);       // [N][TILE]
+  T* Ss = xs + N * TILE;                    // [N][N]
+  const int cl = threadIdx.x & (TILE - 1);
+  const int slot = threadIdx.x / TILE;
+  const int c0 = int(blockIdx.x) * TILE;
+  if (LDS_S) {
+    for (int idx = threadIdx.x; idx < N * N; idx += 256) Ss[idx] = S[idx];
   }
-  const int64_t c = c0 + lane;
+#pragma unroll 4
+  for (int idx = threadIdx.x; idx < N * TILE; idx += 256) {
+    const int m = idx / TILE, l = idx - m * TILE;
+    const int cc = c0 + l;
+    xs[idx] = cc < cells ? T(x[int64_t(m) * cells + cc]) : T(0);
+  }
+  __syncthreads();
+  const int c = c0 + cl;
   if (c >= cells) return;
-  const int i = int(c % nx);
-  const int64_t rr = c / nx;
-  const int j = int(rr % ny);
-  const int k = int(rr / ny);
+  const int rr = c / nx;
+  const int i = c - rr * nx;
+  const int k = rr / ny;
+  const int j = rr - k * ny;
   const int pos[3] = {i, j, k};
   const int ext[3] = {nx, ny, nz};
-  const int64_t stride[3] = {1, nx, int64_t(nx) * ny};
+  const int stride[3] = {1, nx, nx * ny};
   const T st = sT[c], sa = sA[c];
-  for (int m0 = wave * MB; m0 < N; m0 += 4 * MB) {
-    T acc[MB];
+  T xc[DPT], str[DPT], acc[DPT];
 #pragma unroll
-    for (int q = 0; q < MB; ++q) acc[q] = T(0);
-    if (m0 + MB <= N) {
-      for (int n = 0; n < N; ++n) {
-        T xv = LDS ? xs[n * TILE + lane] : T(x[int64_t(n) * cells + c]);
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + DSLOTS * q;
+    xc[q] = str[q] = acc[q] = T(0);
+    if (m >= N) continue;
+    const int64_t o = int64_t(m) * cells + c;
+    xc[q] = xs[m * TILE + cl];
 #pragma unroll
-        for (int q = 0; q < MB; ++q) acc[q] += S[(m0 + q) * N + n] * xv;
-      }
-    } else {
-      for (int n = 0; n < N; ++n) {
-        T xv = LDS ? xs[n * TILE + lane] : T(x[int64_t(n) * cells + c]);
-        for (int q = 0; q < MB; ++q)
-          if (m0 + q < N) acc[q] += S[(m0 + q) * N + n] * xv;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < MB; ++q) {
-      const int m = m0 + q;
-      if (m >= N) break;
-      const int64_t o = int64_t(m) * cells + c;
-      const T xc = LDS ? xs[m * TILE + lane] : T(x[o]);
-      T str = T(0);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int s = sg[4 * m + a];
-        if (s == 0) continue;
-        const int p = pos[a] - s;
-        const T xn = (p >= 0 && p < ext[a]) ? T(x[o - s * stride[a]]) : T(0);
-        str += dc[4 * m + a] * (xc - xn);
-      }
-      const T val = str + st * (xc - acc[q]) + sa * acc[q];
-      if (RES)
-        y[o] = TO(b[o] - double(val));
-      else
-        y[o] = TO(val);
+    for (int a = 0; a < 3; ++a) {
+      const int sgn = sg[4 * m + a];
+      if (sgn == 0) continue;
+      const int p = pos[a] - sgn;
+      const T xn = (p >= 0 && p < ext[a]) ? T(x[o - sgn * stride[a]]) : T(0);
+      str[q] += dc[4 * m + a] * (xc[q] - xn);
     }
   }
+#pragma unroll 4
+  for (int n = 0; n < N; ++n) {
+    const T xv = xs[n * TILE + cl];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int m = slot + DSLOTS * q;
+      if (m < N) acc[q] += (LDS_S ? Ss[m * N + n] : S[m * N + n]) * xv;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + DSLOTS * q;
+    if (m >= N) break;
+    const int64_t o = int64_t(m) * cells + c;
+    const T val = str[q] + st * (xc[q] - acc[q]) + sa * acc[q];
+    if (RES)
+      y[o] = TO(b[o] - double(val));
+    else
+      y[o] = TO(val);
+  }
+}
+
+template <class T, class TI, class TO, bool RES, bool LDS_S>
+void go_dpt(const Operator& op, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
+            const T* dc, size_t lds, hipStream_t s) {
+  const unsigned grid = unsigned((op.cells + TILE - 1) / TILE);
+  const int dpt = (op.ndir + DSLOTS - 1) / DSLOTS;
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, static_cast<const TI*>(x), static_cast<TO*>(y), b, sT,
+                       sA, S, dc, op.dsgn, op.ndir, op.nx, op.ny, op.nz, int(op.cells));
+  };
+  if (dpt <= 1)
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 1>);
+  else if (dpt <= 2)
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 2>);
+  else if (dpt <= 4)
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 4>);
+  else if (dpt <= 8)
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 8>);
+  else
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 16>);
 }
 
 template <class T, class TI, class TO, bool RES>
@@ -99,17 +126,13 @@ void go(const Operator& op, const void* x, void* y, const double* b, hipStream_t
   } else {
     sT = op.sT32; sA = op.sA32; S = op.S32; dc = op.dc32;
   }
-  const size_t lds = size_t(op.ndir) * TILE * sizeof(T);
-  const unsigned grid = unsigned((op.cells + TILE - 1) / TILE);
-  if (lds <= 48 * 1024) {
-    hipLaunchKernelGGL((apply_kernel<T, TI, TO, RES, true>), dim3(grid), dim3(256), lds, s,
-                       static_cast<const TI*>(x), static_cast<TO*>(y), b, sT, sA, S, dc, op.dsgn,
-                       op.ndir, op.nx, op.ny, op.nz, op.cells);
-  } else {
-    hipLaunchKernelGGL((apply_kernel<T, TI, TO, RES, false>), dim3(grid), dim3(256), 0, s,
-                       static_cast<const TI*>(x), static_cast<TO*>(y), b, sT, sA, S, dc, op.dsgn,
-                       op.ndir, op.nx, op.ny, op.nz, op.cells);
-  }
+  const size_t lx = size_t(op.ndir) * TILE * sizeof(T);
+  const size_t ls = size_t(op.ndir) * op.ndir * sizeof(T);
+  constexpr size_t kLds = 48 * 1024;
+  if (lx + ls <= kLds)
+    go_dpt<T, TI, TO, RES, true>(op, x, y, b, sT, sA, S, dc, lx + ls, s);
+  else
+    go_dpt<T, TI, TO, RES, false>(op, x, y, b, sT, sA, S, dc, lx, s);
   RTE_HIP(hipGetLastError());
 }
 

@@ -129,7 +129,8 @@ void launch_apply(const Operator& op, const void* x, int tin, void* y, int tout,
                   bool fp64, hipStream_t s);
 
 // MgNet pieces
-enum ConvMode { CONV_STORE = 0, CONV_ACCUM = 1, CONV_RESID_R = 2, CONV_RESID_T = 3 };
+// STORE_T: out = conv and out2 = a^{-1} (.) conv (a level's first smoothing input)
+enum ConvMode { CONV_STORE = 0, CONV_ACCUM = 1, CONV_STORE_T = 2, CONV_RESID_R = 3, CONV_RESID_T = 4 };
 enum MfmaKind { MFMA_F32 = 0, MFMA_BF16 = 1 };
 
 struct ConvLaunch {
@@ -141,6 +142,7 @@ struct ConvLaunch {
   int out_dim[3];
   int cout;
   int g_dim[3];
+  int dim;
   int cstride, ostride;
   int nclass, ntap;
   int8_t obase[8][3];
@@ -149,12 +151,14 @@ struct ConvLaunch {
   const float* f;
   const float* a;
   const float* ainv;
+  float* out2;
 };
 void launch_conv(const ConvLaunch& c, int kind, hipStream_t s);
 void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride);
 void convT4_setup(ConvLaunch& c, int dim, const int in_dim[3]);
 
-void launch_lift(const Operator& op, const Model& m, const double* v, float* f0, hipStream_t s);
+void launch_lift(const Operator& op, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
+                 hipStream_t s);
 void launch_proj(const Operator& op, const Model& m, const double* v, const float* u0, float* z,
                  hipStream_t s);
 void launch_scale_fields(const float* ainv, const float* f, float* t, int64_t count, hipStream_t s);

@@ -35,14 +35,17 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Block b owns elements [b * chunk, min(n, (b + 1) * chunk)) with
+// chunk = ceil(n / nblk); computed in 32 bits (n < 2^31).
 __device__ inline void chunk_of(int64_t n, int nblk, int64_t& beg, int64_t& end) {
-  const int64_t chunk = (n + nblk - 1) / nblk;
+  const unsigned nn = unsigned(n);
+  const unsigned chunk = (nn + unsigned(nblk) - 1u) / unsigned(nblk);
   beg = int64_t(blockIdx.x) * chunk;
   end = beg + chunk < n ? beg + chunk : n;
 }
 
 // part[blk][i] = sum over the block's chunk of V_i . w, i < nv.
-__device__ inline void dots_body(const double* __restrict__ V, int64_t ldv, int nv,
+__device__ __attribute__((always_inline)) inline void dots_body(const double* __restrict__ V, int64_t ldv, int nv,
                                  const double* __restrict__ w, int64_t n, double* __restrict__ part,
                                  int nblk, double* red) {
   int64_t beg, end;
@@ -52,6 +55,7 @@ __device__ inline void dots_body(const double* __restrict__ V, int64_t ldv, int 
 #pragma unroll
     for (int q = 0; q < NVB; ++q) acc[q] = 0.0;
     const int cnt = nv - vb < NVB ? nv - vb : NVB;
+#pragma unroll 4
     for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
       const double we = w[e];
 #pragma unroll
@@ -86,6 +90,7 @@ __global__ __launch_bounds__(KT) void update_dots_kernel(const double* __restric
   chunk_of(n, nblk, beg, end);
   for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
     double acc = w[e];
+#pragma unroll 8
     for (int i = 0; i < nv; ++i) acc -= hs[i] * V[int64_t(i) * ldv + e];
     w[e] = acc;
   }
@@ -107,6 +112,7 @@ __global__ __launch_bounds__(KT) void update_norm_kernel(const double* __restric
   double ss = 0.0;
   for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
     double acc = w[e];
+#pragma unroll 8
     for (int i = 0; i < nv; ++i) acc -= hs[i] * V[int64_t(i) * ldv + e];
     w[e] = acc;
     ss += acc * acc;
@@ -238,10 +244,12 @@ unsigned ew_grid(int64_t n) {
 
 }  // namespace
 
+// Partial-sum blocks for a length-n reduction: about 1024 elements per block
+// (four per thread), at most 2048 blocks; depends on n only.
 int krylov_blocks(int64_t n) {
-  int64_t b = (n + int64_t(KT) * 16 - 1) / (int64_t(KT) * 16);
+  int64_t b = (n + 1023) / 1024;
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > 2048) b = 2048;
   return int(b);
 }
 

@@ -4,13 +4,16 @@
 // Every convolution is an implicit GEMM: rows are the pixels of a "virtual
 // grid" (the output grid, or one parity class of it for the transposed
 // convolution), columns are output channels, and the reduction runs over
-// taps x input channels.  A 256-thread block computes 64 rows x (16 NT)
-// columns; each wave owns 16 rows.  Operands are read straight from global
-// memory into MFMA fragments -- each lane loads 4 (or 8) consecutive
-// channels of one pixel (16/32 bytes) and the matching 4 (8) input channels
-// of one output channel's weights, which are pre-packed [tap][cout][cin] --
-// so the reuse of a pixel's channels across output-channel tiles happens in
-// registers and the reuse across taps in the caches.
+// taps x input channels.  Each wave computes a 16-row x (16 NT)-column
+// tile; a 256-thread block holds four such waves, either on four row groups
+// or, when the launch would otherwise leave the chip underfilled (coarse
+// levels), on one row group with the k-steps split four ways.  Operands are
+// read straight from global memory into MFMA fragments -- each lane loads 4
+// (or 8) consecutive channels of one pixel (16/32 bytes) and the matching
+// input channels of one output channel's weights, which are pre-packed
+// [tap][cout][cin] -- with the next k-step's loads issued before the current
+// step's MFMAs; reuse of a pixel's channels across output-channel tiles
+// happens in registers and reuse across taps in the caches.
 //
 // MFMA operand layout (16x16 output tile): lane l supplies row (l mod 16)
 // of A and column (l mod 16) of B for k-group l/16; it receives D rows
@@ -23,6 +26,7 @@
 //   ACCUM   out += conv
 //   RESID_R out = f - conv - a (.) u           (u = the conv input, same grid)
 //   RESID_T out = a^{-1} (.) (f - conv - a (.) u)
+//   STORE_T out = conv, out2 = a^{-1} (.) conv
 #include <cstring>
 
 #include "common.h"
@@ -39,6 +43,7 @@ struct ConvArgs {
   const float* in;
   const void* w;
   float* out;
+  float* out2;
   const float* f;
   const float* a;
   const float* ainv;
@@ -46,8 +51,8 @@ struct ConvArgs {
   int out_dim[3];
   int g_dim[3];
   int cin, cout, cstride, ostride, ntap, mode;
-  int8_t obase[8][3];
-  int8_t toff[64][3];
+  int transposed;  // 0: 3-tap cross-correlation, 1: kernel-4 stride-2 transposed
+  int dim;
 };
 
 __device__ inline short bf16_bits(float v) {
@@ -55,114 +60,288 @@ __device__ inline short bf16_bits(float v) {
   return __builtin_bit_cast(short, h);
 }
 
+template <int KIND> struct BType;
+template <> struct BType<0> { typedef float4 type; typedef float elem; };
+template <> struct BType<1> { typedef v4s type; typedef uint16_t elem; };
+template <> struct BType<2> { typedef v8bf type; typedef uint16_t elem; };
+
+// Operand registers of one k-step: KPL input channels of this lane's pixel
+// and, per output-channel tile, KPL weights of this lane's output channel.
 template <int KIND, int NT>
+struct Ops {
+  float4 a0, a1;
+  typename BType<KIND>::type b[NT];
+};
+
+// Loads are unconditional (the address is always inside the tensor) and
+// out-of-range taps are zeroed with a select afterwards: no branch separates
+// the loads of a batch, so none of them waits for the others.
+template <int KIND, int NT>
+__device__ inline void load_ops(Ops<KIND, NT>& o, const float* ap, bool inb, const void* w, size_t woff,
+                                int cin) {
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 l0 = *reinterpret_cast<const float4*>(ap);
+  o.a0 = inb ? l0 : z4;
+  if (KIND == 2) {
+    const float4 l1 = *reinterpret_cast<const float4*>(ap + 4);
+    o.a1 = inb ? l1 : z4;
+  } else {
+    o.a1 = z4;
+  }
+  typedef typename BType<KIND>::elem E;
+  typedef typename BType<KIND>::type T;
+  const E* W = static_cast<const E*>(w) + woff;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) o.b[nt] = *reinterpret_cast<const T*>(W + size_t(nt) * 16 * cin);
+}
+
+template <int KIND, int NT>
+__device__ inline void mma(v4f* acc, const Ops<KIND, NT>& o) {
+  if constexpr (KIND == 0) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a0.x, o.b[nt].x, acc[nt], 0, 0, 0);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a0.y, o.b[nt].y, acc[nt], 0, 0, 0);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a0.z, o.b[nt].z, acc[nt], 0, 0, 0);
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a0.w, o.b[nt].w, acc[nt], 0, 0, 0);
+    }
+  } else if constexpr (KIND == 1) {
+    const v4s av = v4s{bf16_bits(o.a0.x), bf16_bits(o.a0.y), bf16_bits(o.a0.z), bf16_bits(o.a0.w)};
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, o.b[nt], acc[nt], 0, 0, 0);
+  } else {
+    v8bf av;
+    av[0] = __bf16(o.a0.x); av[1] = __bf16(o.a0.y); av[2] = __bf16(o.a0.z); av[3] = __bf16(o.a0.w);
+    av[4] = __bf16(o.a1.x); av[5] = __bf16(o.a1.y); av[6] = __bf16(o.a1.z); av[7] = __bf16(o.a1.w);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, o.b[nt], acc[nt], 0, 0, 0);
+  }
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// KSPLIT = false: the block's 4 waves own 4 consecutive 16-row groups and
+// run the whole reduction.  KSPLIT = true: the 4 waves share one 16-row
+// group and each runs a quarter of the k-steps; waves 1-3 hand their
+// partial tiles to wave 0 through LDS, which adds them in wave order
+// (deterministic) and writes the epilogue.  The k-loop runs in batches of
+// DEPTH k-steps whose operand loads are all issued before the batch's MFMAs;
+// the last (< DEPTH) steps run singly.
+template <int KIND, int NT, bool KSPLIT, int MODE>
 __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A) {
   constexpr int KPL = KIND == 2 ? 8 : 4;  // channels per lane per k-step
   constexpr int KC = 4 * KPL;             // channels per k-step
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform by construction; readfirstlane lets the compiler keep the
+  // k-step bookkeeping (tap, channel chunk, tap offsets) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int grp = lane >> 4, li = lane & 15;
   const int cls = blockIdx.z;
+  // row indices fit in 32 bits (pixels per level < 2^31)
   const int gx = A.g_dim[0], gy = A.g_dim[1];
-  const int64_t gm = int64_t(gx) * gy * A.g_dim[2];
-  const int64_t rbase = int64_t(blockIdx.x) * 64 + wave * 16;
+  const int gm = gx * gy * A.g_dim[2];
+  const int rbase = KSPLIT ? int(blockIdx.x) * 16 : int(blockIdx.x) * 64 + wave * 16;
   const int co0 = blockIdx.y * (NT * 16);
-  const int64_t row = rbase + li;
+  const int row = rbase + li;
   const bool rv = row < gm;
-  int X = 0, Y = 0, Z = 0;
-  if (rv) {
-    X = int(row % gx);
-    const int64_t t = row / gx;
-    Y = int(t % gy);
-    Z = int(t / gy);
+  int X, Y, Z;
+  {
+    const int rc = rv ? row : gm - 1;  // address a valid row; zeroed below
+    const int t = rc / gx;
+    X = rc - t * gx;
+    Z = t / gy;
+    Y = t - Z * gy;
   }
   v4f acc[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  const int cin = A.cin;
-  for (int t = 0; t < A.ntap; ++t) {
-    const int tap = cls * A.ntap + t;
-    const int ix = A.cstride * X + A.toff[tap][0];
-    const int iy = A.cstride * Y + A.toff[tap][1];
-    const int iz = A.cstride * Z + A.toff[tap][2];
-    const bool inb = rv && ix >= 0 && ix < A.in_dim[0] && iy >= 0 && iy < A.in_dim[1] && iz >= 0 &&
-                     iz < A.in_dim[2];
-    const int64_t ipix = inb ? (int64_t(iz) * A.in_dim[1] + iy) * A.in_dim[0] + ix : 0;
-    const float* ap = A.in + ipix * cin + grp * KPL;
-    const size_t wrow = (size_t(tap) * A.cout + co0 + li) * cin + grp * KPL;
-    for (int ci0 = 0; ci0 < cin; ci0 += KC) {
-      float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
-      if (inb) {
-        a0 = *reinterpret_cast<const float4*>(ap + ci0);
-        if (KPL == 8) a1 = *reinterpret_cast<const float4*>(ap + ci0 + 4);
+  const int cin = A.cin, cout = A.cout;
+  const int nchunk = cin / KC;
+  const int nks = A.ntap * nchunk;
+  int ks0 = 0, ks1 = nks;
+  if (KSPLIT) {
+    ks0 = (nks * wave) >> 2;
+    ks1 = (nks * (wave + 1)) >> 2;
+  }
+  int tap = ks0 / nchunk;
+  int ci0 = (ks0 - tap * nchunk) * KC;
+  // Tap offsets are computed from the (wave-uniform) tap index: a table in
+  // memory would be a per-lane load that every k-step has to wait for.
+  // Per lane only the base coordinates and a 32-bit element offset vary.
+  const int xb = A.cstride * X, yb = A.cstride * Y, zb = A.cstride * Z;
+  const int W0 = A.in_dim[0], W1 = A.in_dim[1], W2 = A.in_dim[2];
+  const int lane_a = grp * KPL;                       // + pixel * cin + c0
+  const int lane_w = li * cin + grp * KPL;            // + (tap * cout + co0) * cin + c0
+  auto locate = [&](int tp, int c0, const float*& ap, bool& inb, size_t& woff) {
+    const int tt = cls * A.ntap + tp;
+    int k3[3], off[3];
+    if (A.transposed)
+      convT4_tap(A.dim, cls, tp, k3, off);
+    else
+      conv3_tap(A.dim, tp, k3, off);
+    const int ix = xb + off[0], iy = yb + off[1], iz = zb + off[2];
+    inb = rv && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1) && unsigned(iz) < unsigned(W2);
+    const int ipix = (clampi(iz, 0, W2 - 1) * W1 + clampi(iy, 0, W1 - 1)) * W0 + clampi(ix, 0, W0 - 1);
+    ap = A.in + (ipix * cin + lane_a + c0);
+    woff = size_t((tt * cout + co0) * cin + c0) + lane_w;
+  };
+
+  // This lane's output rows are r0 .. r0 + 3.  Epilogue operands do not
+  // depend on the reduction: request them now so their latency hides under
+  // the k-loop (only the wave that writes the epilogue).
+  const int r0 = rbase + grp * 4;
+  size_t oidx[4];
+  bool ovalid[4];
+  {
+    const int rc = r0 < gm ? r0 : gm - 1;
+    const int t = rc / gx;
+    int x = rc - t * gx;
+    int z = t / gy;
+    int y = t - z * gy;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j > 0 && r0 + j < gm) {
+        if (++x == gx) {
+          x = 0;
+          if (++y == gy) {
+            y = 0;
+            ++z;
+          }
+        }
       }
-      if constexpr (KIND == 0) {
-        const float* W = static_cast<const float*>(A.w) + wrow + ci0;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const float4 bv = *reinterpret_cast<const float4*>(W + size_t(nt) * 16 * cin);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bv.x, acc[nt], 0, 0, 0);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, bv.y, acc[nt], 0, 0, 0);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, bv.z, acc[nt], 0, 0, 0);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, bv.w, acc[nt], 0, 0, 0);
-        }
-      } else if constexpr (KIND == 1) {
-        const uint16_t* W = static_cast<const uint16_t*>(A.w) + wrow + ci0;
-        const v4s av = v4s{bf16_bits(a0.x), bf16_bits(a0.y), bf16_bits(a0.z), bf16_bits(a0.w)};
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const v4s bv = *reinterpret_cast<const v4s*>(W + size_t(nt) * 16 * cin);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nt], 0, 0, 0);
-        }
-      } else {
-        const uint16_t* W = static_cast<const uint16_t*>(A.w) + wrow + ci0;
-        v8bf av;
-        av[0] = __bf16(a0.x); av[1] = __bf16(a0.y); av[2] = __bf16(a0.z); av[3] = __bf16(a0.w);
-        av[4] = __bf16(a1.x); av[5] = __bf16(a1.y); av[6] = __bf16(a1.z); av[7] = __bf16(a1.w);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const v8bf bv = *reinterpret_cast<const v8bf*>(W + size_t(nt) * 16 * cin);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
-        }
-      }
+      ovalid[j] = r0 + j < gm;
+      // transposed conv: class cls writes output parity (cls & 1, cls >> 1 & 1, cls >> 2 & 1)
+      const int ox = A.ostride * x + (A.transposed ? (cls & 1) : 0);
+      const int oy = A.ostride * y + (A.transposed ? (cls >> 1) & 1 : 0);
+      const int oz = A.ostride * z + (A.transposed && A.dim == 3 ? (cls >> 2) & 1 : 0);
+      oidx[j] = size_t((oz * A.out_dim[1] + oy) * A.out_dim[0] + ox) * cout;
     }
   }
+  constexpr bool NEED_F = MODE == CONV_RESID_R || MODE == CONV_RESID_T;
+  constexpr bool NEED_I = MODE == CONV_RESID_T || MODE == CONV_STORE_T;
+  constexpr bool NEED_U = MODE == CONV_ACCUM || NEED_F;
+  float ef[4 * NT], ea[4 * NT], ei[4 * NT], eu[4 * NT];
+  if (!KSPLIT || wave == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int q = j * NT + nt;
+        const size_t o = oidx[j] + co0 + nt * 16 + li;
+        if (NEED_F) {
+          ef[q] = A.f[o];
+          ea[q] = A.a[o];
+        }
+        if (NEED_I) ei[q] = A.ainv[o];
+        if (NEED_U) eu[q] = MODE == CONV_ACCUM ? A.out[o] : A.in[o];
+      }
+  }
 
-  const int cout = A.cout;
+  // Full batches: all DEPTH steps' operand loads are issued before the
+  // batch's MFMAs.  The remaining (< DEPTH) steps run one at a time.
+  constexpr int DEPTH = NT >= 4 ? 4 : 8;
+  auto advance = [&]() {
+    ci0 += KC;
+    if (ci0 == cin) {
+      ci0 = 0;
+      ++tap;
+    }
+  };
+  int ks = ks0;
+  for (; ks + DEPTH <= ks1; ks += DEPTH) {
+    Ops<KIND, NT> buf[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      const float* ap;
+      bool inb;
+      size_t woff;
+      locate(tap, ci0, ap, inb, woff);
+      load_ops<KIND, NT>(buf[d], ap, inb, A.w, woff, cin);
+      advance();
+    }
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) mma<KIND, NT>(acc, buf[d]);
+  }
+  for (; ks < ks1; ++ks) {
+    Ops<KIND, NT> one;
+    const float* ap;
+    bool inb;
+    size_t woff;
+    locate(tap, ci0, ap, inb, woff);
+    load_ops<KIND, NT>(one, ap, inb, A.w, woff, cin);
+    advance();
+    mma<KIND, NT>(acc, one);
+  }
+
+  if constexpr (KSPLIT) {
+    __shared__ float red[3][NT][4][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[wave - 1][nt][j][lane] = acc[nt][j];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[nt][j] += red[w][nt][j][lane];
+  }
+
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int64_t r = rbase + grp * 4 + j;
-    if (r >= gm) continue;
-    const int Xo = int(r % gx);
-    const int64_t t2 = r / gx;
-    const int Yo = int(t2 % gy), Zo = int(t2 / gy);
-    const int ox = A.ostride * Xo + A.obase[cls][0];
-    const int oy = A.ostride * Yo + A.obase[cls][1];
-    const int oz = A.ostride * Zo + A.obase[cls][2];
-    const int64_t opix = (int64_t(oz) * A.out_dim[1] + oy) * A.out_dim[0] + ox;
+    if (!ovalid[j]) continue;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int col = co0 + nt * 16 + li;
-      const int64_t o = opix * cout + col;
+      const int q = j * NT + nt;
+      const size_t o = oidx[j] + co0 + nt * 16 + li;
       const float v = acc[nt][j];
-      switch (A.mode) {
-        case CONV_STORE: A.out[o] = v; break;
-        case CONV_ACCUM: A.out[o] += v; break;
-        case CONV_RESID_R: A.out[o] = A.f[o] - v - A.a[o] * A.in[o]; break;
-        default: A.out[o] = A.ainv[o] * (A.f[o] - v - A.a[o] * A.in[o]); break;
+      if constexpr (MODE == CONV_STORE) {
+        A.out[o] = v;
+      } else if constexpr (MODE == CONV_ACCUM) {
+        A.out[o] = eu[q] + v;
+      } else if constexpr (MODE == CONV_STORE_T) {
+        A.out[o] = v;
+        A.out2[o] = ei[q] * v;
+      } else if constexpr (MODE == CONV_RESID_R) {
+        A.out[o] = ef[q] - v - ea[q] * eu[q];
+      } else {
+        A.out[o] = ei[q] * (ef[q] - v - ea[q] * eu[q]);
       }
     }
   }
 }
 
-template <int KIND>
-void conv_dispatch(const ConvArgs& a, dim3 grid, int nt, hipStream_t s) {
+template <int KIND, bool KSPLIT, int MODE>
+void conv_dispatch3(const ConvArgs& a, dim3 grid, int nt, hipStream_t s) {
   switch (nt) {
-    case 4: hipLaunchKernelGGL((conv_kernel<KIND, 4>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((conv_kernel<KIND, 2>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((conv_kernel<KIND, 1>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((conv_kernel<KIND, 4, KSPLIT, MODE>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((conv_kernel<KIND, 2, KSPLIT, MODE>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((conv_kernel<KIND, 1, KSPLIT, MODE>), grid, dim3(256), 0, s, a); break;
   }
+}
+
+template <int KIND, bool KSPLIT>
+void conv_dispatch2(const ConvArgs& a, dim3 grid, int nt, hipStream_t s) {
+  switch (a.mode) {
+    case CONV_STORE: conv_dispatch3<KIND, KSPLIT, CONV_STORE>(a, grid, nt, s); break;
+    case CONV_ACCUM: conv_dispatch3<KIND, KSPLIT, CONV_ACCUM>(a, grid, nt, s); break;
+    case CONV_STORE_T: conv_dispatch3<KIND, KSPLIT, CONV_STORE_T>(a, grid, nt, s); break;
+    case CONV_RESID_R: conv_dispatch3<KIND, KSPLIT, CONV_RESID_R>(a, grid, nt, s); break;
+    default: conv_dispatch3<KIND, KSPLIT, CONV_RESID_T>(a, grid, nt, s); break;
+  }
+}
+
+template <int KIND>
+void conv_dispatch(const ConvArgs& a, dim3 grid, int nt, bool ksplit, hipStream_t s) {
+  if (ksplit)
+    conv_dispatch2<KIND, true>(a, grid, nt, s);
+  else
+    conv_dispatch2<KIND, false>(a, grid, nt, s);
 }
 
 // ---------------------------------------------------------- lift / proj ---
@@ -173,35 +352,54 @@ __device__ inline float diag_of(const float* dc, const float* Sd, float st, floa
   return dc[4 * m + 3] + st * (1.f - smm) + sa * smm;
 }
 
-// f0[p][c] = sum_m Win[c][m] v[m][p] / d[m][p] for a tile of 64 pixels.
+constexpr int PT = 16;  // pixels per block of the lift / projection kernels
+
+// f0[p][c] = sum_m Win[c][m] v[m][p] / d[m][p] for a tile of 16 pixels; when
+// t0 is given also t0 = ainv0 (.) f0 (the first smoothing step's input).
+// LDS holds v~ as [m][pixel] and W_in transposed as [m][c], so the
+// channel-fastest thread order reads consecutive banks.
 __global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ v, const float* __restrict__ sT,
                                                    const float* __restrict__ sA, const float* __restrict__ dc,
                                                    const float* __restrict__ Sd, const float* __restrict__ Win,
-                                                   float* __restrict__ f0, int N, int C0, int64_t P) {
+                                                   float* __restrict__ f0, const float* __restrict__ ainv,
+                                                   float* __restrict__ t0, int N, int C0, int64_t P) {
   extern __shared__ float sm[];
-  float* vt = sm;               // [N][64]
-  float* w = sm + N * 64;       // [C0][N]
-  const int64_t p0 = int64_t(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < C0 * N; idx += 256) w[idx] = Win[idx];
-  for (int idx = threadIdx.x; idx < N * 64; idx += 256) {
-    const int m = idx >> 6;
-    const int64_t p = p0 + (idx & 63);
-    float val = 0.f;
-    if (p < P) val = float(v[int64_t(m) * P + p]) / diag_of(dc, Sd, sT[p], sA[p], m);
-    vt[idx] = val;
+  float* vt = sm;               // [N][PT]
+  float* wt = sm + N * PT;      // [N][C0]
+  const int64_t p0 = int64_t(blockIdx.x) * PT;
+  for (int idx = threadIdx.x; idx < C0 * N; idx += 256) {
+    const int c = idx / N, m = idx - c * N;
+    wt[m * C0 + c] = Win[idx];
+  }
+  {
+    const int64_t p = p0 + (threadIdx.x & (PT - 1));
+    const float st = p < P ? sT[p] : 0.f, sa = p < P ? sA[p] : 0.f;
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < N * PT; idx += 256) {
+      const int m = idx / PT;
+      float val = 0.f;
+      if (p < P) val = float(v[int64_t(m) * P + p]) / diag_of(dc, Sd, st, sa, m);
+      vt[idx] = val;
+    }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 64 * C0; idx += 256) {
+  for (int idx = threadIdx.x; idx < PT * C0; idx += 256) {
     const int pl = idx / C0, c = idx - pl * C0;
     const int64_t p = p0 + pl;
     if (p >= P) continue;
     float acc = 0.f;
-    for (int m = 0; m < N; ++m) acc += w[c * N + m] * vt[m * 64 + pl];
-    f0[p * C0 + c] = acc;
+#pragma unroll 4
+    for (int m = 0; m < N; ++m) acc += wt[m * C0 + c] * vt[m * PT + pl];
+    const int64_t o = p * C0 + c;
+    f0[o] = acc;
+    if (t0) t0[o] = ainv[o] * acc;
   }
 }
 
-// z[m][p] = s v[m][p] / d[m][p] + sum_c Wout[m][c] u0[p][c].
+// z[m][p] = s v[m][p] / d[m][p] + sum_c Wout[m][c] u0[p][c] for 16 pixels:
+// thread t owns pixel t % 16 and directions t / 16 + 16 q; u0 rows are
+// padded in LDS (conflict-free) and v is requested before the sum.
+template <int DPT>
 __global__ __launch_bounds__(256) void proj_kernel(const double* __restrict__ v, const float* __restrict__ u0,
                                                    const float* __restrict__ sT, const float* __restrict__ sA,
                                                    const float* __restrict__ dc, const float* __restrict__ Sd,
@@ -209,24 +407,46 @@ __global__ __launch_bounds__(256) void proj_kernel(const double* __restrict__ v,
                                                    int N, int C0, int64_t P) {
   extern __shared__ float sm[];
   const int ld = C0 + 1;
-  float* us = sm;  // [64][C0 + 1]
-  const int64_t p0 = int64_t(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < 64 * C0; idx += 256) {
+  float* us = sm;              // [PT][C0 + 1]
+  float* ws = sm + PT * ld;    // [N][C0]
+  const int64_t p0 = int64_t(blockIdx.x) * PT;
+  for (int idx = threadIdx.x; idx < PT * C0; idx += 256) {
     const int pl = idx / C0, c = idx - pl * C0;
     const int64_t p = p0 + pl;
     us[pl * ld + c] = p < P ? u0[p * C0 + c] : 0.f;
   }
+#pragma unroll 4
+  for (int idx = threadIdx.x; idx < N * C0; idx += 256) ws[idx] = Wout[idx];
+  const int pl = threadIdx.x & (PT - 1);
+  const int slot = threadIdx.x / PT;
+  const int64_t p = p0 + pl;
+  double vv[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 16 * q;
+    vv[q] = (p < P && m < N) ? v[int64_t(m) * P + p] : 0.0;
+  }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int64_t p = p0 + lane;
   if (p >= P) return;
   const float st = sT[p], sa = sA[p];
-  for (int m = wave; m < N; m += 4) {
-    float acc = 0.f;
-    for (int c = 0; c < C0; ++c) acc += Wout[m * C0 + c] * us[lane * ld + c];
+  float acc[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) acc[q] = 0.f;
+#pragma unroll 4
+  for (int c = 0; c < C0; ++c) {
+    const float u = us[pl * ld + c];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int m = slot + 16 * q;
+      if (m < N) acc[q] += ws[m * C0 + c] * u;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 16 * q;
+    if (m >= N) break;
     const int64_t o = int64_t(m) * P + p;
-    z[o] = sc * (float(v[o]) / diag_of(dc, Sd, st, sa, m)) + acc;
+    z[o] = sc * (float(vv[q]) / diag_of(dc, Sd, st, sa, m)) + acc[q];
   }
 }
 
@@ -301,6 +521,7 @@ __global__ void head_kernel(const float* __restrict__ F, int c, const float* __r
 
 // ------------------------------------------------------------ launchers ---
 void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride) {
+  c.dim = dim;
   c.cstride = stride;
   c.ostride = 1;
   c.nclass = 1;
@@ -319,6 +540,7 @@ void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride) {
 }
 
 void convT4_setup(ConvLaunch& c, int dim, const int in_dim[3]) {
+  c.dim = dim;
   c.cstride = 1;
   c.ostride = 2;
   c.nclass = 1 << dim;
@@ -344,6 +566,7 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   ConvArgs a;
   a.in = c.in;
   a.out = c.out;
+  a.out2 = c.out2;
   a.f = c.f;
   a.a = c.a;
   a.ainv = c.ainv;
@@ -358,49 +581,79 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   a.ostride = c.ostride;
   a.ntap = c.ntap;
   a.mode = c.mode;
-  std::memset(a.obase, 0, sizeof(a.obase));
-  std::memset(a.toff, 0, sizeof(a.toff));
-  for (int k = 0; k < c.nclass; ++k)
-    for (int i = 0; i < 3; ++i) a.obase[k][i] = c.obase[k][i];
-  for (int k = 0; k < c.nclass * c.ntap; ++k)
-    for (int i = 0; i < 3; ++i) a.toff[k][i] = c.toff[k][i];
+  a.transposed = c.ostride == 2 ? 1 : 0;
+  a.dim = c.dim;
   RTE_REQUIRE(c.w->taps == c.nclass * c.ntap && c.w->cin == c.cin && c.w->cout == c.cout, RTE_EINVAL,
               "conv weights do not match the launch");
   // the residual epilogues read the input at the output pixel
   if (c.mode == CONV_RESID_R || c.mode == CONV_RESID_T)
     RTE_REQUIRE(c.cin == c.cout && c.cstride == 1 && c.ostride == 1, RTE_EINVAL, "bad residual conv");
+  if (c.mode == CONV_STORE_T) RTE_REQUIRE(c.out2 && c.ainv, RTE_EINVAL, "dual store needs out2 and ainv");
   const int64_t gm = int64_t(c.g_dim[0]) * c.g_dim[1] * c.g_dim[2];
-  const int nt = c.cout % 64 == 0 ? 4 : (c.cout % 32 == 0 ? 2 : 1);
-  dim3 grid(unsigned((gm + 63) / 64), unsigned(c.cout / (nt * 16)), unsigned(c.nclass));
+  const int64_t row_units = (gm + 15) / 16;
+  // Tile choice: the widest output-channel tile that still yields >= 2048
+  // waves; otherwise 16x16 tiles with the reduction split over the 4 waves
+  // of a block (when there are enough k-steps to share).
+  const int kc = (kind == MFMA_F32 || c.cin % 32 != 0) ? 16 : 32;
+  const int nks = c.ntap * (c.cin / kc);
+  const int64_t target = 2048;
+  int nt = 0;
+  for (int cand : {4, 2, 1})
+    if (c.cout % (16 * cand) == 0 && row_units * (c.cout / (16 * cand)) * c.nclass >= target) {
+      nt = cand;
+      break;
+    }
+  bool ksplit = false;
+  if (nt == 0) {
+    nt = 1;
+    ksplit = nks >= 8;
+  }
+  dim3 grid(unsigned(ksplit ? row_units : (row_units + 3) / 4), unsigned(c.cout / (nt * 16)),
+            unsigned(c.nclass));
   ProfScope ps(RTE_K_CONV, s);
   ps.work = 2.0 * double(gm) * c.cout * double(c.cin) * c.ntap * c.nclass;
   if (kind == MFMA_F32) {
     a.w = c.w->d32;
-    conv_dispatch<0>(a, grid, nt, s);
+    conv_dispatch<0>(a, grid, nt, ksplit, s);
   } else if (c.cin % 32 == 0) {
     a.w = c.w->d16;
-    conv_dispatch<2>(a, grid, nt, s);
+    conv_dispatch<2>(a, grid, nt, ksplit, s);
   } else {
     a.w = c.w->d16;
-    conv_dispatch<1>(a, grid, nt, s);
+    conv_dispatch<1>(a, grid, nt, ksplit, s);
   }
   RTE_HIP(hipGetLastError());
 }
 
-void launch_lift(const Operator& op, const Model& m, const double* v, float* f0, hipStream_t s) {
-  const size_t lds = (size_t(op.ndir) * 64 + size_t(m.c0) * op.ndir) * sizeof(float);
+void launch_lift(const Operator& op, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
+                 hipStream_t s) {
+  const size_t lds = (size_t(op.ndir) * PT + size_t(m.c0) * op.ndir) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "lift tile does not fit in LDS");
-  hipLaunchKernelGGL(lift_kernel, dim3(unsigned((op.cells + 63) / 64)), dim3(256), lds, s, v, op.sT32, op.sA32,
-                     op.dc32, op.Sdiag32, m.d_w_in, f0, op.ndir, m.c0, op.cells);
+  hipLaunchKernelGGL(lift_kernel, dim3(unsigned((op.cells + PT - 1) / PT)), dim3(256), lds, s, v, op.sT32,
+                     op.sA32, op.dc32, op.Sdiag32, m.d_w_in, f0, ainv, t0, op.ndir, m.c0, op.cells);
   RTE_HIP(hipGetLastError());
 }
 
 void launch_proj(const Operator& op, const Model& m, const double* v, const float* u0, float* z,
                  hipStream_t s) {
-  const size_t lds = size_t(64) * (m.c0 + 1) * sizeof(float);
+  const size_t lds = (size_t(PT) * (m.c0 + 1) + size_t(op.ndir) * m.c0) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "projection tile does not fit in LDS");
-  hipLaunchKernelGGL(proj_kernel, dim3(unsigned((op.cells + 63) / 64)), dim3(256), lds, s, v, u0, op.sT32,
-                     op.sA32, op.dc32, op.Sdiag32, m.d_w_out, m.s, z, op.ndir, m.c0, op.cells);
+  const dim3 grid(unsigned((op.cells + PT - 1) / PT));
+  const int dpt = (op.ndir + 15) / 16;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, v, u0, op.sT32, op.sA32, op.dc32, op.Sdiag32, m.d_w_out,
+                       m.s, z, op.ndir, m.c0, op.cells);
+  };
+  if (dpt <= 1)
+    go(proj_kernel<1>);
+  else if (dpt <= 2)
+    go(proj_kernel<2>);
+  else if (dpt <= 4)
+    go(proj_kernel<4>);
+  else if (dpt <= 8)
+    go(proj_kernel<8>);
+  else
+    go(proj_kernel<16>);
   RTE_HIP(hipGetLastError());
 }
 

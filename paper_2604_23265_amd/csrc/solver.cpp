@@ -53,10 +53,16 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
     c.f = f[l]; c.a = op.fa[l]; c.ainv = op.fainv[l];
     launch_conv(c, kind, s);
   };
-  std::vector<bool> uz(L, true);
+  // uz[l]: u_l is still zero; tready[l]: t_l already holds a^{-1} (.) f_l,
+  // written by the producer of f_l (lift or restriction epilogue)
+  std::vector<bool> uz(L, true), tready(L, false);
+  auto first_steps = [&](int l) {
+    return l < L - 1 ? int(m.Bpre[l].size()) : int(m.Bc.size());
+  };
   auto smooth = [&](int l, const ConvW& B) {
     if (uz[l]) {
-      launch_scale_fields(op.fainv[l], f[l], t[l], P[l] * C[l], s);
+      if (!tready[l]) launch_scale_fields(op.fainv[l], f[l], t[l], P[l] * C[l], s);
+      tready[l] = false;
       conv_same(l, t[l], B, u[l], CONV_STORE);
       uz[l] = false;
     } else {
@@ -65,7 +71,9 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
     }
   };
 
-  launch_lift(op, m, v, f[0], s);
+  const bool want0 = first_steps(0) > 0;
+  launch_lift(op, m, v, f[0], want0 ? op.fainv[0] : nullptr, want0 ? t[0] : nullptr, s);
+  tready[0] = want0;
   for (int l = 0; l < L - 1; ++l) {
     uz[l] = true;
     for (const ConvW& B : m.Bpre[l]) smooth(l, B);
@@ -78,9 +86,13 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
     int d[3];
     dims(l, d);
     conv3_setup(c, op.dim, d, 2);
+    const bool want = first_steps(l + 1) > 0;
     c.in = rin; c.cin = m.R[l].cin; c.w = &m.R[l]; c.out = f[l + 1]; c.cout = m.R[l].cout;
-    c.mode = CONV_STORE;
+    c.mode = want ? CONV_STORE_T : CONV_STORE;
+    c.out2 = want ? t[l + 1] : nullptr;
+    c.ainv = op.fainv[l + 1];
     launch_conv(c, kind, s);
+    tready[l + 1] = want;
   }
   uz[L - 1] = true;
   for (const ConvW& B : m.Bc) smooth(L - 1, B);
