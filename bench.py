@@ -24,6 +24,29 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+CONV_SOURCE = os.path.join(ROOT, "paper_2604_23265_amd", "csrc", "mgnet.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_kernel_c2_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per conv launch from the committed counter summary, or None.
+
+    The summary records the SHA-256 of the convolution source it was taken
+    with; a changed kernel makes the figure stale, so it is not reported.
+    """
+    import hashlib
+    try:
+        src = hashlib.sha256(open(CONV_SOURCE, "rb").read()).hexdigest()
+        fields = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("source-sha256") != src:
+            return None
+        return float(fields["hbm-bytes-per-launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -63,6 +86,62 @@ def cpu_baseline(prob, blob, gpu_iters, budget_s):
     }
 
 
+def serving_leg(args, api, torch, configs, weights):
+    """Served latency on the C3 stream: a closed batch measures saturated throughput, then
+    Poisson arrivals at 0.7x that rate give arrival-to-completion p50/p99."""
+    reqs = [configs.c3_request(r) for r in range(args.serving_requests)]
+    models = {}
+    ops = []
+    for p in reqs:
+        N = p["dirs"].shape[0]
+        if N not in models:
+            hdr, t = configs.problem_weights(p)
+            models[N] = api.Model(weights.pack_mgn1(hdr, t))
+        ops.append(api.Operator(p, model=models[N]))
+    outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
+    kw = dict(restart=30, rtol=1e-6, max_iters=args.serving_max_iters, precond="bf16")
+    srv = api.Server(arena_bytes=args.serving_arena_gb << 30, max_slots=args.serving_slots)
+
+    def run(arrivals):
+        t0 = time.perf_counter()
+        pending = {}
+        submitted = 0
+        done = {}
+        while len(done) < len(ops):
+            now = time.perf_counter() - t0
+            while submitted < len(ops) and arrivals[submitted] <= now:
+                tk = srv.submit(ops[submitted], outs[submitted], model=ops[submitted].model, **kw)
+                pending[tk] = (submitted, t0 + arrivals[submitted])
+                submitted += 1
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    i, t_arr = pending.pop(tk)
+                    done[i] = (time.perf_counter() - t_arr, r[0], r[1])
+            time.sleep(0.0005)
+        return time.perf_counter() - t0, done
+
+    log("serving: closed batch of %d requests" % len(ops))
+    wall, done = run([0.0] * len(ops))
+    sat = len(ops) / wall
+    rate = 0.7 * sat
+    arr = list(configs.c3_arrivals(len(ops), rate=rate, seed=3999))
+    arr = [a - arr[0] for a in arr]
+    log("serving: Poisson arrivals at %.2f req/s" % rate)
+    wall2, done2 = run(arr)
+    lat = [d[0] * 1e3 for d in done2.values()]
+    its = [d[2]["iterations"] for d in done2.values()]
+    ok = sum(1 for d in done2.values() if d[1] == 0)
+    q = srv.query()
+    srv.close()
+    return {"requests": len(ops), "slots": args.serving_slots, "saturated_solves_per_s": sat,
+            "arrival_rate": rate, "completed_ok": ok, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "iterations_mean": float(np.mean(its)), "iterations_max": int(np.max(its)),
+            "arena_peak_gb": q["arena_peak"] / 2 ** 30, "max_iters": args.serving_max_iters,
+            "stream": "seeded C3 draws: grid {64,128,256}^2, 16/32 directions, eps log-uniform [1e-3,1], "
+                      "g ~ U[0,0.8], lognormal GRF sigma_T; BF16 MgNet FGMRES(30) to 1e-6"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +152,12 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
     ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
+    ap.add_argument("--serving-requests", type=int, default=0, help="requests of the C3 stream (0 = skip)")
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-arena-gb", type=int, default=16)
+    ap.add_argument("--serving-max-iters", type=int, default=3000)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="bytes of a plain device copy run before the solves (reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path "
@@ -85,6 +170,12 @@ def main():
     from rte_inputs import configs, weights
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = configs.c2(0)
     hdr, t = configs.problem_weights(prob)
     blob = weights.pack_mgn1(hdr, t)
@@ -150,17 +241,19 @@ def main():
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
     }
     if prof is not None:
-        ms, launches, work = prof
+        ms, launches, work, nbytes = prof
         avg_ms = ms / max(launches, 1)
         if args.prof == "conv":
             achieved = work / (ms * 1e-3) / 1e12
             out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["bf16"],
                                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS["bf16"],
-                               "traffic": None, "kernel": "conv_kernel (implicit-GEMM 3x3/stride-2/"
+                               "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                               "kernel": "conv_kernel (implicit-GEMM 3x3/stride-2/"
                                "transposed convs of the V-cycle, BF16 MFMA)",
                                "timed_launches": launches, "sampling": "every %d-th launch" % args.prof_every,
                                "avg_launch_us": avg_ms * 1e3,
-                               "work_per_launch": work / max(launches, 1), "work_unit": "FLOP"}
+                               "work_per_launch": work / max(launches, 1), "work_unit": "FLOP",
+                               "algorithmic_bytes_per_launch": nbytes / max(launches, 1)}
         else:
             achieved = work / (ms * 1e-3) / 1e9
             out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -175,6 +268,8 @@ def main():
                             "iterations_per_solve": float(np.mean(its32)),
                             "latency_ms": {"p50": percentile(lat32, 50), "p99": percentile(lat32, 99)}}
         out["bf16_over_fp32"] = value / out["fp32_path"]["value"]
+    if args.serving_requests:
+        out["serving"] = serving_leg(args, api, torch, configs, weights)
     if not args.no_cpu_baseline:
         log("cpu_baseline: oracle sample (~%.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(prob, blob, float(np.mean(its)), args.cpu_budget)

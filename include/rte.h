@@ -230,15 +230,18 @@ rte_status rte_server_destroy(rte_server* srv);
  * the class with an event pair on the stream it is launched on (1 = all
  * launches; sampling keeps the events' own cost out of the timed work);
  * 0 disables.  rte_prof_query synchronises the recorded events and returns,
- * since the last reset, the summed duration, the number of timed launches
- * and their summed algorithmic work: FLOPs for RTE_K_CONV
- * (2 x rows x cout x cin x taps), bytes that must cross HBM for the
- * bandwidth-bound classes (operands read once, results written once), and
- * 0 for RTE_K_PRECOND (a composite: the whole V-cycle). */
+ * since the last reset, the summed duration, the number of timed launches,
+ * their summed algorithmic work -- FLOPs for RTE_K_CONV
+ * (2 x rows x cout x cin x taps), bytes for the bandwidth-bound classes,
+ * 0 for RTE_K_PRECOND (a composite: the whole V-cycle) -- and their summed
+ * algorithmic bytes (every operand read once, every result written once;
+ * for RTE_K_CONV: input tensor, weights, output and epilogue tensors).
+ * Any output pointer may be NULL. */
 enum { RTE_K_APPLY = 0, RTE_K_RESIDUAL = 1, RTE_K_CONV = 2, RTE_K_ORTH = 3,
        RTE_K_PRECOND = 4, RTE_K_COUNT = 5 };
 rte_status rte_prof_enable(int kernel_class, int every);
-rte_status rte_prof_query(int kernel_class, double* total_ms, int64_t* launches, double* work);
+rte_status rte_prof_query(int kernel_class, double* total_ms, int64_t* launches, double* work,
+                          double* bytes);
 rte_status rte_prof_reset(void);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -81,7 +81,8 @@ _SIGS = {
     "rte_server_query": [_P, C.POINTER(ServerStats)],
     "rte_server_destroy": [_P],
     "rte_prof_enable": [C.c_int, C.c_int],
-    "rte_prof_query": [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+    "rte_prof_query": [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                       C.POINTER(C.c_double)],
     "rte_prof_reset": [],
 }
 

@@ -260,12 +260,13 @@ def prof_enable(cls, every=1):
 
 
 def prof_query(cls):
-    """(total ms, launches, algorithmic work) of a kernel class since the last reset."""
+    """(total ms, timed launches, algorithmic work, algorithmic bytes) since the last reset."""
     ms = C.c_double()
     cnt = C.c_int64()
     work = C.c_double()
-    check(lib().rte_prof_query(int(cls), C.byref(ms), C.byref(cnt), C.byref(work)))
-    return ms.value, cnt.value, work.value
+    nbytes = C.c_double()
+    check(lib().rte_prof_query(int(cls), C.byref(ms), C.byref(cnt), C.byref(work), C.byref(nbytes)))
+    return ms.value, cnt.value, work.value, nbytes.value
 
 
 def prof_reset():

@@ -26,12 +26,13 @@ struct Prof {
   int64_t seen[RTE_K_COUNT] = {};
   struct Rec {
     hipEvent_t e0, e1;
-    double work;
+    double work, bytes;
   };
   std::vector<Rec> pending[RTE_K_COUNT];
   std::vector<hipEvent_t> pool;
   double ms[RTE_K_COUNT] = {};
   double work[RTE_K_COUNT] = {};
+  double bytes[RTE_K_COUNT] = {};
   int64_t count[RTE_K_COUNT] = {};
   hipEvent_t get() {
     if (!pool.empty()) {
@@ -50,6 +51,7 @@ struct Prof {
       RTE_HIP(hipEventElapsedTime(&t, pr.e0, pr.e1));
       ms[c] += t;
       work[c] += pr.work;
+      bytes[c] += pr.bytes;
       count[c] += 1;
       pool.push_back(pr.e0);
       pool.push_back(pr.e1);
@@ -63,13 +65,14 @@ Prof& prof() {
 }
 }  // namespace
 
-ProfScope::ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+ProfScope::ProfScope(int c, hipStream_t st, bool ext_launch) : cls(c), s(st), ext(ext_launch) {
   Prof& P = prof();
   if (P.every[c] <= 0) return;
   std::lock_guard<std::mutex> lk(P.mu);
   if (P.every[c] <= 0 || (P.seen[c]++ % P.every[c]) != 0) return;
   e0 = P.get();
-  RTE_HIP(hipEventRecord(e0, s));
+  e1 = P.get();
+  if (!ext) RTE_HIP(hipEventRecord(e0, s));
 }
 
 ProfScope::~ProfScope() {
@@ -77,9 +80,8 @@ ProfScope::~ProfScope() {
   Prof& P = prof();
   std::lock_guard<std::mutex> lk(P.mu);
   try {
-    e1 = P.get();
-    (void)hipEventRecord(e1, s);
-    P.pending[cls].push_back({e0, e1, work});
+    if (!ext) (void)hipEventRecord(e1, s);
+    P.pending[cls].push_back({e0, e1, work, bytes < 0 ? work : bytes});
     if (P.pending[cls].size() >= 65536) P.drain(cls);
   } catch (...) {
   }
@@ -286,7 +288,7 @@ rte_status rte_prof_enable(int c, int every) {
   });
 }
 
-rte_status rte_prof_query(int c, double* total_ms, int64_t* launches, double* work) {
+rte_status rte_prof_query(int c, double* total_ms, int64_t* launches, double* work, double* bytes) {
   return guarded([&] {
     RTE_REQUIRE(c >= 0 && c < RTE_K_COUNT, RTE_EINVAL, "unknown kernel class");
     Prof& P = prof();
@@ -295,6 +297,7 @@ rte_status rte_prof_query(int c, double* total_ms, int64_t* launches, double* wo
     if (total_ms) *total_ms = P.ms[c];
     if (launches) *launches = P.count[c];
     if (work) *work = P.work[c];
+    if (bytes) *bytes = P.bytes[c];
   });
 }
 
@@ -306,6 +309,7 @@ rte_status rte_prof_reset(void) {
       P.drain(c);
       P.ms[c] = 0;
       P.work[c] = 0;
+      P.bytes[c] = 0;
       P.count[c] = 0;
     }
   });

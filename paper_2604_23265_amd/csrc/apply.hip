@@ -31,12 +31,17 @@ __global__ __launch_bounds__(256) void apply_kernel(const TI* __restrict__ x, TO
                                                     int nz, int cells) {
   extern __shared__ char smem[];
   T* xs = reinterpret_cast<T*>(smem);       // [N][TILE]
-  T* Ss = xs + N * TILE;                    // [N][N]
+  T* Ss = xs + N * TILE;                    // [N][N + 1]: padded rows, so the direction
+                                            // rows read by one wave sit in different banks
+  const int ldS = N + 1;
   const int cl = threadIdx.x & (TILE - 1);
   const int slot = threadIdx.x / TILE;
   const int c0 = int(blockIdx.x) * TILE;
   if (LDS_S) {
-    for (int idx = threadIdx.x; idx < N * N; idx += 256) Ss[idx] = S[idx];
+    for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+      const int r = idx / N;
+      Ss[r * ldS + (idx - r * N)] = S[idx];
+    }
   }
 #pragma unroll 4
   for (int idx = threadIdx.x; idx < N * TILE; idx += 256) {
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const TI* __restrict__ x, TO
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
       const int m = slot + DSLOTS * q;
-      if (m < N) acc[q] += (LDS_S ? Ss[m * N + n] : S[m * N + n]) * xv;
+      if (m < N) acc[q] += (LDS_S ? Ss[m * ldS + n] : S[m * N + n]) * xv;
     }
   }
 #pragma unroll
@@ -96,12 +101,12 @@ __global__ __launch_bounds__(256) void apply_kernel(const TI* __restrict__ x, TO
 
 template <class T, class TI, class TO, bool RES, bool LDS_S>
 void go_dpt(const Operator& op, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
-            const T* dc, size_t lds, hipStream_t s) {
+            const T* dc, size_t lds, hipStream_t s, const ProfScope& ps) {
   const unsigned grid = unsigned((op.cells + TILE - 1) / TILE);
   const int dpt = (op.ndir + DSLOTS - 1) / DSLOTS;
   auto launch = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, static_cast<const TI*>(x), static_cast<TO*>(y), b, sT,
-                       sA, S, dc, op.dsgn, op.ndir, op.nx, op.ny, op.nz, int(op.cells));
+    launch_k(kern, dim3(grid), dim3(256), uint32_t(lds), s, ps, static_cast<const TI*>(x), static_cast<TO*>(y), b,
+             sT, sA, S, dc, static_cast<const int*>(op.dsgn), op.ndir, op.nx, op.ny, op.nz, int(op.cells));
   };
   if (dpt <= 1)
     launch(apply_kernel<T, TI, TO, RES, LDS_S, 1>);
@@ -116,7 +121,7 @@ void go_dpt(const Operator& op, const void* x, void* y, const double* b, const T
 }
 
 template <class T, class TI, class TO, bool RES>
-void go(const Operator& op, const void* x, void* y, const double* b, hipStream_t s) {
+void go(const Operator& op, const void* x, void* y, const double* b, hipStream_t s, const ProfScope& ps) {
   const T* sT;
   const T* sA;
   const T* S;
@@ -127,12 +132,12 @@ void go(const Operator& op, const void* x, void* y, const double* b, hipStream_t
     sT = op.sT32; sA = op.sA32; S = op.S32; dc = op.dc32;
   }
   const size_t lx = size_t(op.ndir) * TILE * sizeof(T);
-  const size_t ls = size_t(op.ndir) * op.ndir * sizeof(T);
+  const size_t ls = size_t(op.ndir) * (op.ndir + 1) * sizeof(T);
   constexpr size_t kLds = 48 * 1024;
   if (lx + ls <= kLds)
-    go_dpt<T, TI, TO, RES, true>(op, x, y, b, sT, sA, S, dc, lx + ls, s);
+    go_dpt<T, TI, TO, RES, true>(op, x, y, b, sT, sA, S, dc, lx + ls, s, ps);
   else
-    go_dpt<T, TI, TO, RES, false>(op, x, y, b, sT, sA, S, dc, lx, s);
+    go_dpt<T, TI, TO, RES, false>(op, x, y, b, sT, sA, S, dc, lx, s, ps);
   RTE_HIP(hipGetLastError());
 }
 
@@ -143,23 +148,23 @@ void launch_apply(const Operator& op, const void* x, int tin, void* y, int tout,
   const double unknowns = double(op.n), cells = double(op.cells);
   if (b) {
     RTE_REQUIRE(fp64 && tin == 1 && tout == 1, RTE_EINVAL, "residual is FP64 only");
-    ProfScope ps(RTE_K_RESIDUAL, s);
+    ProfScope ps(RTE_K_RESIDUAL, s, true);
     ps.work = 24.0 * unknowns + 16.0 * cells;  // x, b in; r out; sT, sA
-    go<double, double, double, true>(op, x, y, b, s);
+    go<double, double, double, true>(op, x, y, b, s, ps);
     return;
   }
-  ProfScope ps(RTE_K_APPLY, s);
+  ProfScope ps(RTE_K_APPLY, s, true);
   const double esz[2] = {4.0, 8.0};
   ps.work = (esz[tin] + esz[tout]) * unknowns + (fp64 ? 16.0 : 8.0) * cells;
   if (fp64) {
     RTE_REQUIRE(tin == 1 && tout == 1, RTE_EINVAL, "FP64 apply takes FP64 vectors");
-    go<double, double, double, false>(op, x, y, nullptr, s);
+    go<double, double, double, false>(op, x, y, nullptr, s, ps);
   } else if (tin == 0 && tout == 0) {
-    go<float, float, float, false>(op, x, y, nullptr, s);
+    go<float, float, float, false>(op, x, y, nullptr, s, ps);
   } else if (tin == 0 && tout == 1) {
-    go<float, float, double, false>(op, x, y, nullptr, s);
+    go<float, float, double, false>(op, x, y, nullptr, s, ps);
   } else {
-    go<float, double, float, false>(op, x, y, nullptr, s);
+    go<float, double, float, false>(op, x, y, nullptr, s, ps);
   }
 }
 

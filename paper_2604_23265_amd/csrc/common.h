@@ -1,6 +1,7 @@
 // Internal declarations shared by the librte sources (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -192,15 +193,30 @@ void launch_lsq(const double* H, const double* g, int jj, int k, double* y, hipS
 void launch_xupdate(double* x, const float* Z, int64_t ldz, const double* y, int jj, int64_t n,
                     hipStream_t s);
 
-// kernel-class timing
+// kernel-class timing.  A sampled scope owns an event pair.  With ext =
+// true the enclosed launch goes through launch_k, and the dispatch itself
+// stamps the events around the kernel's execution (the interval a kernel
+// trace reports); otherwise the events are recorded on the stream around
+// everything the scope encloses.
 struct ProfScope {
   int cls;
   hipStream_t s;
-  double work = 0;  // algorithmic FLOPs or bytes of the enclosed launch
+  double work = 0;   // algorithmic FLOPs (or bytes) of the enclosed launch
+  double bytes = -1; // algorithmic bytes; < 0 means equal to work
+  bool ext;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ProfScope(int cls, hipStream_t s);
+  ProfScope(int cls, hipStream_t s, bool ext = false);
   ~ProfScope();
 };
+
+template <typename F, typename... Args>
+inline void launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const ProfScope& ps,
+                     Args... args) {
+  if (ps.e0 && ps.ext)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ps.e0, ps.e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
 
 // solver internals shared with the server
 struct SolveLayout {

@@ -256,47 +256,47 @@ int krylov_blocks(int64_t n) {
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, int nblk,
                  hipStream_t s) {
   RTE_REQUIRE(nv >= 1 && nv <= HMAX, RTE_EINVAL, "too many basis vectors");
-  ProfScope ps(RTE_K_ORTH, s);
+  ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 1);
-  hipLaunchKernelGGL(dots_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nv, w, n, part, nblk);
+  launch_k(dots_kernel, dim3(nblk), dim3(KT), 0, s, ps, V, ldv, nv, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
 void launch_reduce(const double* part, int nblk, int nv, double* out, hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s);
-  hipLaunchKernelGGL(reduce_kernel, dim3(nv), dim3(KT), 0, s, part, nblk, out);
+  ProfScope ps(RTE_K_ORTH, s, true);
+  launch_k(reduce_kernel, dim3(nv), dim3(KT), 0, s, ps, part, nblk, out);
   RTE_HIP(hipGetLastError());
 }
 
 void launch_update_dots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
                         double* part, int nblk, hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s);
+  ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once
-  hipLaunchKernelGGL(update_dots_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nv, h, w, n, part, nblk);
+  launch_k(update_dots_kernel, dim3(nblk), dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
 void launch_update_norm(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
                         double* part, int nblk, hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s);
+  ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 2);
-  hipLaunchKernelGGL(update_norm_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nv, h, w, n, part, nblk);
+  launch_k(update_norm_kernel, dim3(nblk), dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
 void launch_finish_step(const double* h1, const double* h2, const double* partn, int nblk, int j, int k,
                         double* H, double* cs, double* sn, double* g, const double* bnorm, double* stat,
                         hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s);
-  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(KT), 0, s, h1, h2, partn, nblk, j, k, H, cs, sn, g, bnorm,
+  ProfScope ps(RTE_K_ORTH, s, true);
+  launch_k(finish_kernel, dim3(1), dim3(KT), 0, s, ps, h1, h2, partn, nblk, j, k, H, cs, sn, g, bnorm,
                      stat);
   RTE_HIP(hipGetLastError());
 }
 
 void launch_scale_by(double* w, const double* stat_inv, int64_t n, hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s);
+  ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 16.0 * double(n);
-  hipLaunchKernelGGL(scale_kernel, dim3(ew_grid(n)), dim3(KT), 0, s, w, stat_inv, n);
+  launch_k(scale_kernel, dim3(ew_grid(n)), dim3(KT), 0, s, ps, w, stat_inv, n);
   RTE_HIP(hipGetLastError());
 }
 

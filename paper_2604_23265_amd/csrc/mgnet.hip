@@ -317,31 +317,31 @@ __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A) {
 }
 
 template <int KIND, bool KSPLIT, int MODE>
-void conv_dispatch3(const ConvArgs& a, dim3 grid, int nt, hipStream_t s) {
+void conv_dispatch3(const ConvArgs& a, dim3 grid, int nt, hipStream_t s, const ProfScope& ps) {
   switch (nt) {
-    case 4: hipLaunchKernelGGL((conv_kernel<KIND, 4, KSPLIT, MODE>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((conv_kernel<KIND, 2, KSPLIT, MODE>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((conv_kernel<KIND, 1, KSPLIT, MODE>), grid, dim3(256), 0, s, a); break;
+    case 4: launch_k(conv_kernel<KIND, 4, KSPLIT, MODE>, grid, dim3(256), 0, s, ps, a); break;
+    case 2: launch_k(conv_kernel<KIND, 2, KSPLIT, MODE>, grid, dim3(256), 0, s, ps, a); break;
+    default: launch_k(conv_kernel<KIND, 1, KSPLIT, MODE>, grid, dim3(256), 0, s, ps, a); break;
   }
 }
 
 template <int KIND, bool KSPLIT>
-void conv_dispatch2(const ConvArgs& a, dim3 grid, int nt, hipStream_t s) {
+void conv_dispatch2(const ConvArgs& a, dim3 grid, int nt, hipStream_t s, const ProfScope& ps) {
   switch (a.mode) {
-    case CONV_STORE: conv_dispatch3<KIND, KSPLIT, CONV_STORE>(a, grid, nt, s); break;
-    case CONV_ACCUM: conv_dispatch3<KIND, KSPLIT, CONV_ACCUM>(a, grid, nt, s); break;
-    case CONV_STORE_T: conv_dispatch3<KIND, KSPLIT, CONV_STORE_T>(a, grid, nt, s); break;
-    case CONV_RESID_R: conv_dispatch3<KIND, KSPLIT, CONV_RESID_R>(a, grid, nt, s); break;
-    default: conv_dispatch3<KIND, KSPLIT, CONV_RESID_T>(a, grid, nt, s); break;
+    case CONV_STORE: conv_dispatch3<KIND, KSPLIT, CONV_STORE>(a, grid, nt, s, ps); break;
+    case CONV_ACCUM: conv_dispatch3<KIND, KSPLIT, CONV_ACCUM>(a, grid, nt, s, ps); break;
+    case CONV_STORE_T: conv_dispatch3<KIND, KSPLIT, CONV_STORE_T>(a, grid, nt, s, ps); break;
+    case CONV_RESID_R: conv_dispatch3<KIND, KSPLIT, CONV_RESID_R>(a, grid, nt, s, ps); break;
+    default: conv_dispatch3<KIND, KSPLIT, CONV_RESID_T>(a, grid, nt, s, ps); break;
   }
 }
 
 template <int KIND>
-void conv_dispatch(const ConvArgs& a, dim3 grid, int nt, bool ksplit, hipStream_t s) {
+void conv_dispatch(const ConvArgs& a, dim3 grid, int nt, bool ksplit, hipStream_t s, const ProfScope& ps) {
   if (ksplit)
-    conv_dispatch2<KIND, true>(a, grid, nt, s);
+    conv_dispatch2<KIND, true>(a, grid, nt, s, ps);
   else
-    conv_dispatch2<KIND, false>(a, grid, nt, s);
+    conv_dispatch2<KIND, false>(a, grid, nt, s, ps);
 }
 
 // ---------------------------------------------------------- lift / proj ---
@@ -610,17 +610,25 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   }
   dim3 grid(unsigned(ksplit ? row_units : (row_units + 3) / 4), unsigned(c.cout / (nt * 16)),
             unsigned(c.nclass));
-  ProfScope ps(RTE_K_CONV, s);
+  ProfScope ps(RTE_K_CONV, s, true);
   ps.work = 2.0 * double(gm) * c.cout * double(c.cin) * c.ntap * c.nclass;
+  {
+    // algorithmic bytes: input tensor, weights, output and epilogue tensors once
+    const double in_el = double(c.in_dim[0]) * c.in_dim[1] * c.in_dim[2] * c.cin;
+    const double out_el = double(gm) * c.nclass * c.cout;
+    const double wbytes = double(c.w->taps) * c.cout * c.cin * (kind == MFMA_F32 ? 4.0 : 2.0);
+    const double extra[] = {0.0, 1.0, 2.0, 2.0, 3.0};  // STORE, ACCUM, STORE_T, RESID_R, RESID_T
+    ps.bytes = 4.0 * in_el + wbytes + 4.0 * out_el * (1.0 + extra[c.mode]);
+  }
   if (kind == MFMA_F32) {
     a.w = c.w->d32;
-    conv_dispatch<0>(a, grid, nt, ksplit, s);
+    conv_dispatch<0>(a, grid, nt, ksplit, s, ps);
   } else if (c.cin % 32 == 0) {
     a.w = c.w->d16;
-    conv_dispatch<2>(a, grid, nt, ksplit, s);
+    conv_dispatch<2>(a, grid, nt, ksplit, s, ps);
   } else {
     a.w = c.w->d16;
-    conv_dispatch<1>(a, grid, nt, ksplit, s);
+    conv_dispatch<1>(a, grid, nt, ksplit, s, ps);
   }
   RTE_HIP(hipGetLastError());
 }

@@ -1,0 +1,122 @@
+"""Continuous-batching server: results alone vs in the mix, admission, failure isolation."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import host, model_for, say, torch_cuda
+from oracle import solve as osolve
+from rte_inputs import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(count, grids=(16, 32), ndirs=(16,)):
+    return [configs.c3_request(r, ndir_choices=ndirs, grid_choices=grids) for r in range(count)]
+
+
+def _build(reqs):
+    from paper_2604_23265_amd import api
+    models = {}
+    ops = []
+    for p in reqs:
+        N = p["dirs"].shape[0]
+        if N not in models:
+            models[N] = model_for(p)[0]
+        ops.append(api.Operator(p, model=models[N]))
+    return models, ops
+
+
+def _wait(srv, tickets, timeout=120.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t in done:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                done[t] = r
+        assert time.time() - t0 < timeout, "server did not finish in time"
+        time.sleep(0.001)
+    return done
+
+
+def test_results_alone_equal_results_in_the_mix():
+    torch = torch_cuda()
+    from paper_2604_23265_amd import api
+    say("case serving mix of 8 requests")
+    reqs = _requests(8)
+    models, ops = _build(reqs)
+    kw = dict(restart=30, rtol=1e-8, precond="bf16")
+    alone = []
+    for p, op in zip(reqs, ops):
+        x, st = op.solve(**kw)
+        assert st["converged"] == 1
+        alone.append(x.clone())
+    srv = api.Server(arena_bytes=512 << 20, max_slots=4)
+    outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+    tickets = [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops, outs)]
+    done = _wait(srv, tickets)
+    q = srv.query()
+    say("  server", q)
+    srv.close()
+    for t, a, out, p in zip(tickets, alone, outs, reqs):
+        code, st = done[t]
+        assert code == 0 and st["converged"] == 1
+        assert bool((out == a).all()), "result differs between alone and in the mix"
+    assert q["completed"] == len(reqs) and q["arena_peak"] <= q["arena_bytes"]
+    # and the served results satisfy the FP64 residual check of the oracle
+    P = osolve.Problem(reqs[0])
+    assert osolve.relative_residual(P, host(outs[0])) <= 1e-8 * 1.01
+
+
+def test_admission_by_footprint():
+    torch = torch_cuda()
+    from paper_2604_23265_amd import api
+    say("case serving admission")
+    reqs = _requests(6, grids=(32,))
+    models, ops = _build(reqs)
+    kw = dict(restart=20, rtol=1e-6, precond="bf16")
+    need = ops[0].workspace_bytes(ops[0].model, **kw)
+    srv = api.Server(arena_bytes=int(2.5 * need) + 4096, max_slots=8)   # room for two at a time
+    outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
+    tickets = [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops, outs)]
+    done = _wait(srv, tickets)
+    q = srv.query()
+    srv.close()
+    assert all(done[t][0] == 0 for t in tickets)
+    assert q["arena_peak"] <= q["arena_bytes"] and q["arena_peak"] >= need
+    assert q["arena_peak"] < 3 * need
+
+
+def test_errors_and_poisoned_request_isolation():
+    torch = torch_cuda()
+    from paper_2604_23265_amd import _lib as L
+    from paper_2604_23265_amd import api
+    say("case serving errors")
+    reqs = _requests(3)
+    models, ops = _build(reqs)
+    kw = dict(restart=30, rtol=1e-8, precond="fp32")
+    small = api.Server(arena_bytes=1 << 20, max_slots=2)
+    with pytest.raises(L.RteError) as e:
+        small.submit(ops[0], torch.empty(ops[0].n, dtype=torch.float64, device="cuda"), model=ops[0].model, **kw)
+    assert e.value.code == L.RTE_ENOMEM
+    with pytest.raises(L.RteError) as e:
+        small.poll(12345)
+    assert e.value.code == L.RTE_ENOTFOUND
+    small.close()
+
+    srv = api.Server(arena_bytes=256 << 20, max_slots=3)
+    bad_b = torch.full((ops[1].n,), float("nan"), dtype=torch.float64, device="cuda")
+    outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
+    t0 = srv.submit(ops[0], outs[0], model=ops[0].model, **kw)
+    t1 = srv.submit(ops[1], outs[1], model=ops[1].model, b=bad_b, **kw)
+    t2 = srv.submit(ops[2], outs[2], model=ops[2].model, **kw)
+    done = _wait(srv, [t0, t1, t2])
+    srv.close()
+    assert done[t1][0] in (L.RTE_EINVAL, L.RTE_EBREAKDOWN)
+    for t, op, out in ((t0, ops[0], outs[0]), (t2, ops[2], outs[2])):
+        assert done[t][0] == 0
+        x, st = op.solve(**kw)
+        assert bool((x == out).all())
