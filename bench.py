@@ -4,9 +4,12 @@ Workload: 128x128 cells, 32 circle directions, flatland HG g = 0.5,
 eps = 0.01, lognormal sigma_T (Gaussian random field, std 0.5, correlation
 length 0.1), sigma_a = 0.05, q = 1, unit inflow on the left edge; 4-level
 MgNet with 32 channels and seeded weights; FGMRES(30) to a relative FP64
-residual of 1e-6.  One step = one complete solve from x = 0 with inputs
-already resident in HBM.  `value` is BF16-MgNet solves per second; the FP32
-MgNet path is timed the same way beside it.
+residual of 1e-6.  One step = a batch of independent instances of this
+family (media seeds 2000 + s) solved from x = 0 through the
+continuous-batching server, inputs already resident in HBM.  `value` is
+BF16-MgNet solves per second over the whole job; the FP32 MgNet path is
+timed the same way beside it, and one instance solved alone is reported as
+`single_solve`.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -145,8 +148,11 @@ def serving_leg(args, api, torch, configs, weights):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3, help="timed batches")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed batches")
+    ap.add_argument("--batch", type=int, default=10, help="independent instances per step")
+    ap.add_argument("--arena-gb", type=float, default=8.0)
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -176,46 +182,60 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prob = configs.c2(0)
-    hdr, t = configs.problem_weights(prob)
+    # the C2 family: media seeds 2000 + s, s = 0 .. batch-1, one seeded network
+    probs = [configs.c2(s) for s in range(args.batch)]
+    hdr, t = configs.problem_weights(probs[0])
     blob = weights.pack_mgn1(hdr, t)
     model = api.Model(blob)
-    op = api.Operator(prob, model=model)
+    ops = [api.Operator(p, model=model) for p in probs]
     kw = dict(restart=30, rtol=1e-6, max_iters=20000)
-    ws = torch.empty(op.workspace_bytes(model, precond="bf16", **kw), dtype=torch.uint8, device="cuda")
-    psi = torch.empty(op.n, dtype=torch.float64, device="cuda")
+    outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
+    srv = api.Server(arena_bytes=int(args.arena_gb * 2 ** 30), max_slots=args.batch)
+    classes = {"conv": L.K_CONV, "orth": L.K_ORTH, "apply": L.K_APPLY, "none": None}
+    pc = classes[args.prof]
+
+    def batch(mode):
+        """One step: every instance of the batch submitted at once and solved to rtol."""
+        tk = [srv.submit(op, o, model=model, precond=mode, **kw) for op, o in zip(ops, outs)]
+        res = {}
+        while len(res) < len(tk):
+            for x in tk:
+                if x not in res:
+                    r = srv.poll(x)
+                    if r is not None:
+                        res[x] = r
+            time.sleep(0.0002)
+        sts = [res[x][1] for x in tk]
+        if not all(s["converged"] for s in sts):
+            raise RuntimeError("a solve did not converge: %r" % (sts,))
+        return sts
 
     def run(mode, steps, prof_cls=None):
-        lat, its, res = [], [], []
         if prof_cls is not None:
             api.prof_reset()
             api.prof_enable(prof_cls, args.prof_every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        sts = []
         for _ in range(steps):
-            s0 = time.perf_counter()
-            _, st = op.solve(model=model, psi=psi, workspace=ws, precond=mode, **kw)
-            lat.append((time.perf_counter() - s0) * 1e3)
-            its.append(st["iterations"])
-            res.append(st["rel_residual"])
-            if not st["converged"]:
-                raise RuntimeError("solve did not converge: %r" % (st,))
+            sts += batch(mode)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = None
         if prof_cls is not None:
             api.prof_enable(prof_cls, 0)
             prof = api.prof_query(prof_cls)
-        return dt, lat, its, res, prof
+        return dt, sts, prof
 
-    log("warmup: %d BF16-path solves" % args.warmup)
+    log("warmup: %d batches of %d BF16-path solves" % (args.warmup, args.batch))
     for _ in range(args.warmup):
-        op.solve(model=model, psi=psi, workspace=ws, precond="bf16", **kw)
-    classes = {"conv": L.K_CONV, "orth": L.K_ORTH, "apply": L.K_APPLY, "none": None}
-    pc = classes[args.prof]
-    log("timed: %d BF16-path solves (events on kernel class %s)" % (args.steps, args.prof))
-    dt, lat, its, res, prof = run("bf16", args.steps, pc)
-    value = args.steps / dt
+        batch("bf16")
+    log("timed: %d batches of %d BF16-path solves (events on kernel class %s)" % (args.steps, args.batch, args.prof))
+    dt, sts, prof = run("bf16", args.steps, pc)
+    nsolves = args.steps * args.batch
+    value = nsolves / dt
+    lat = [s["ms_total"] for s in sts]
+    its = [s["iterations"] for s in sts]
     out = {
         "metric": "GMRES solves/s at 1e-6 rel residual, BF16 MgNet vs FP32; p50/p99 latency",
         "value": value,
@@ -233,16 +253,20 @@ def main():
             "workload": "2D 128x128 grid, 32 directions, HG g=0.5, eps=0.01, lognormal GRF sigma_T "
                         "(std 0.5, corr 0.1), sigma_a=0.05, q=1, unit left inflow; 4-level MgNet, "
                         "32 channels, seeded weights; FGMRES(30), FP64 Arnoldi, rtol 1e-6",
-            "grid": [128, 128], "directions": 32, "unknowns": int(op.n), "restart": 30, "rtol": 1e-6,
+            "step": "%d independent instances (GRF seeds 2000..%d) solved concurrently through the "
+                    "continuous-batching server" % (args.batch, 2000 + args.batch - 1),
+            "grid": [128, 128], "directions": 32, "unknowns": int(ops[0].n), "restart": 30, "rtol": 1e-6,
             "precond": "MgNet BF16 MFMA, FP32 accumulation",
         },
         "iterations_per_solve": float(np.mean(its)),
-        "rel_residual_max": float(np.max(res)),
-        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "rel_residual_max": float(max(s["rel_residual"] for s in sts)),
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "note": "submission to completion inside a batch"},
     }
     if prof is not None:
         ms, launches, work, nbytes = prof
         avg_ms = ms / max(launches, 1)
+        samp = "one Arnoldi step in %d run without its graph, every launch of the class in it timed" % args.prof_every
         if args.prof == "conv":
             achieved = work / (ms * 1e-3) / 1e12
             out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["bf16"],
@@ -250,7 +274,7 @@ def main():
                                "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
                                "kernel": "conv_kernel (implicit-GEMM 3x3/stride-2/"
                                "transposed convs of the V-cycle, BF16 MFMA)",
-                               "timed_launches": launches, "sampling": "every %d-th launch" % args.prof_every,
+                               "timed_launches": launches, "sampling": samp,
                                "avg_launch_us": avg_ms * 1e3,
                                "work_per_launch": work / max(launches, 1), "work_unit": "FLOP",
                                "algorithmic_bytes_per_launch": nbytes / max(launches, 1)}
@@ -258,16 +282,30 @@ def main():
             achieved = work / (ms * 1e-3) / 1e9
             out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": args.prof,
-                               "timed_launches": launches, "sampling": "every %d-th launch" % args.prof_every,
+                               "timed_launches": launches, "sampling": samp,
                                "avg_launch_us": avg_ms * 1e3,
                                "work_per_launch": work / max(launches, 1), "work_unit": "byte"}
     if not args.no_fp32:
-        log("timed: %d FP32-path solves" % args.steps)
-        dt32, lat32, its32, res32, _ = run("fp32", args.steps)
-        out["fp32_path"] = {"value": args.steps / dt32, "unit": "solves/s", "ms_per_step": dt32 / args.steps * 1e3,
-                            "iterations_per_solve": float(np.mean(its32)),
-                            "latency_ms": {"p50": percentile(lat32, 50), "p99": percentile(lat32, 99)}}
+        log("timed: %d batches of FP32-path solves" % args.steps)
+        dt32, sts32, _ = run("fp32", args.steps)
+        out["fp32_path"] = {"value": nsolves / dt32, "unit": "solves/s", "ms_per_step": dt32 / args.steps * 1e3,
+                            "iterations_per_solve": float(np.mean([s["iterations"] for s in sts32])),
+                            "latency_ms": {"p50": percentile([s["ms_total"] for s in sts32], 50),
+                                           "p99": percentile([s["ms_total"] for s in sts32], 99)}}
         out["bf16_over_fp32"] = value / out["fp32_path"]["value"]
+    if not args.no_single:
+        log("single solves: instance 0 alone, %d times" % args.steps)
+        ws = torch.empty(ops[0].workspace_bytes(model, precond="bf16", **kw), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = ops[0].solve(model=model, psi=outs[0], workspace=ws, precond="bf16", **kw)
+        torch.cuda.synchronize()
+        d1 = (time.perf_counter() - t0) / args.steps
+        out["single_solve"] = {"value": 1.0 / d1, "unit": "solves/s", "ms": d1 * 1e3,
+                               "iterations": st["iterations"], "instance": "GRF seed 2000"}
+    srv.close()
+    prob, blob = probs[0], blob
     if args.serving_requests:
         out["serving"] = serving_leg(args, api, torch, configs, weights)
     if not args.no_cpu_baseline:

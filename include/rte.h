@@ -227,9 +227,11 @@ rte_status rte_server_destroy(rte_server* srv);
 
 /* ---- kernel timing: HIP events around launches of one kernel class ----
  * rte_prof_enable(cls, every): every > 0 brackets every `every`-th launch of
- * the class with an event pair on the stream it is launched on (1 = all
- * launches; sampling keeps the events' own cost out of the timed work);
- * 0 disables.  rte_prof_query synchronises the recorded events and returns,
+ * the class with an event pair stamped by its dispatch (1 = all launches;
+ * sampling keeps the events' own cost out of the timed work); 0 disables.
+ * Solves replay their Arnoldi steps as HIP graphs, whose launches cannot be
+ * bracketed; while any class is enabled a solve runs one step in `every`
+ * without its graph and times every launch of the enabled classes in it.  rte_prof_query synchronises the recorded events and returns,
  * since the last reset, the summed duration, the number of timed launches,
  * their summed algorithmic work -- FLOPs for RTE_K_CONV
  * (2 x rows x cout x cin x taps), bytes for the bandwidth-bound classes,

@@ -65,11 +65,30 @@ Prof& prof() {
 }
 }  // namespace
 
+bool& prof_capturing() {
+  thread_local bool v = false;
+  return v;
+}
+
+bool& prof_force() {
+  thread_local bool v = false;
+  return v;
+}
+
+int prof_stride() {
+  Prof& P = prof();
+  int s = 0;
+  for (int c = 0; c < RTE_K_COUNT; ++c)
+    if (P.every[c] > 0 && (s == 0 || P.every[c] < s)) s = P.every[c];
+  return s;
+}
+
 ProfScope::ProfScope(int c, hipStream_t st, bool ext_launch) : cls(c), s(st), ext(ext_launch) {
   Prof& P = prof();
-  if (P.every[c] <= 0) return;
+  if (P.every[c] <= 0 || prof_capturing()) return;
   std::lock_guard<std::mutex> lk(P.mu);
-  if (P.every[c] <= 0 || (P.seen[c]++ % P.every[c]) != 0) return;
+  if (P.every[c] <= 0) return;
+  if (!prof_force() && (P.seen[c]++ % P.every[c]) != 0) return;
   e0 = P.get();
   e1 = P.get();
   if (!ext) RTE_HIP(hipEventRecord(e0, s));
@@ -155,7 +174,10 @@ rte_status rte_build_operator(const rte_geometry* geom, const rte_medium* med, c
 }
 
 rte_status rte_operator_free(rte_operator* op) {
-  return guarded([&] { delete op; });
+  return guarded([&] {
+    if (op) drop_step_graphs(op->op.get());
+    delete op;
+  });
 }
 
 rte_status rte_operator_get_info(const rte_operator* h, rte_operator_info* info) {

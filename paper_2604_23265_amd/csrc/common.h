@@ -209,6 +209,13 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Thread-local state of the kernel-class timer: while a graph is being
+// captured nothing is timed; inside a sampled (eager) Arnoldi step every
+// launch of an enabled class is timed.
+bool& prof_capturing();
+bool& prof_force();
+int prof_stride();  // 0 when no class is being timed, else the smallest `every`
+
 template <typename F, typename... Args>
 inline void launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const ProfScope& ps,
                      Args... args) {
@@ -250,6 +257,7 @@ class SolveRun {
   bool ready();
   void wait();
   void advance();
+  void step_body(int j, hipStream_t s);  // the kernels of Arnoldi step j
   bool done() const { return phase_ == DONE; }
   void fill_stats(rte_solve_stats* st) const;
   rte_status status() const { return status_; }
@@ -284,7 +292,15 @@ class SolveRun {
   double bnorm_ = 0, prev_ = 0, rel_ = 0;
   rte_status status_ = RTE_ENOCONV;
   double t0_ = 0, ms_ = 0;
+  bool graphs_ = true;
+  std::vector<hipGraphExec_t>* gcache_ = nullptr;  // per-step graphs for this workspace
 };
+
+// Graphs of Arnoldi steps, keyed by everything their kernel arguments hold;
+// dropped when the operator they reference is freed.
+std::vector<hipGraphExec_t>* step_graphs(const Operator* op, const Model* m, int precond, const char* ws,
+                                         const double* x, const double* b, int k);
+void drop_step_graphs(const Operator* op);
 
 }  // namespace rte
 

@@ -27,6 +27,7 @@
 //   RESID_R out = f - conv - a (.) u           (u = the conv input, same grid)
 //   RESID_T out = a^{-1} (.) (f - conv - a (.) u)
 //   STORE_T out = conv, out2 = a^{-1} (.) conv
+#include <algorithm>
 #include <cstring>
 
 #include "common.h"
@@ -313,6 +314,193 @@ __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A) {
         A.out[o] = ei[q] * (ef[q] - v - ea[q] * eu[q]);
       }
     }
+  }
+}
+
+// 3x3, stride-1, 2D convolution with the block's input footprint staged in
+// LDS (BF16 weights, cin a multiple of 32, grid width a multiple of 16).
+// The block owns ROWS consecutive pixels of the row-major grid: a 64- (or
+// 16-) pixel segment of one image row, or 64/gx whole rows of a narrow grid.
+// Per 32-channel chunk the footprint (rows + halo) is read from global once,
+// rounded to BF16 and written to LDS with an 80-byte pixel stride (the 16-
+// byte A-fragment reads of eight consecutive lanes then hit distinct banks);
+// all 9 taps read their A fragments from LDS.  Chunks are double-buffered.
+// KSPLIT: the 4 waves share 16 pixels and split the 9 taps (3, 2, 2, 2);
+// their partial tiles are combined in LDS in wave order.
+constexpr int LDS_PIX_WORDS = 20;  // 32 BF16 channels (16 words) + 4 words of padding
+
+template <int NT, bool KSPLIT, int MODE>
+__global__ __launch_bounds__(256) void conv3_lds_kernel(const ConvArgs A) {
+  constexpr int ROWS = KSPLIT ? 16 : 64;
+  constexpr int KC = 32;
+  extern __shared__ uint32_t tile[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int grp = lane >> 4, li = lane & 15;
+  const int gx = A.g_dim[0], gy = A.g_dim[1];
+  const int gm = gx * gy;
+  const int cin = A.cin, cout = A.cout;
+  const int nchunk = cin / KC;
+  const int rb = int(blockIdx.x) * ROWS;
+  const int co0 = blockIdx.y * (NT * 16);
+  // footprint of the block: rows y0 .. y0 + nrow - 1, columns x0 .. x0 + width - 1
+  const int y0 = rb / gx;
+  const int x0 = rb - y0 * gx;
+  const int width = gx >= ROWS ? ROWS : gx;
+  const int nrow = gx >= ROWS ? 1 : ROWS / gx;
+  const int TW = width + 2, TH = nrow + 2;
+  const int tpix = TW * TH;
+  uint32_t* buf[2] = {tile, tile + tpix * LDS_PIX_WORDS};
+
+  // stage chunk c of the footprint into LDS buffer b (all 256 threads)
+  auto stage = [&](int c, int b) {
+    uint32_t* dst = buf[b];
+    const int n4 = tpix * 8;  // float4 pieces: 8 per pixel (32 channels)
+    for (int idx = threadIdx.x; idx < n4; idx += 256) {
+      const int pix = idx >> 3, c4 = idx & 7;
+      const int ty = pix / TW, tx = pix - ty * TW;
+      const int iy = y0 - 1 + ty, ix = x0 - 1 + tx;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (unsigned(iy) < unsigned(gy) && unsigned(ix) < unsigned(gx))
+        v = *reinterpret_cast<const float4*>(A.in + size_t(iy * gx + ix) * cin + c * KC + c4 * 4);
+      const uint32_t lo = uint32_t(uint16_t(bf16_bits(v.x))) | (uint32_t(uint16_t(bf16_bits(v.y))) << 16);
+      const uint32_t hi = uint32_t(uint16_t(bf16_bits(v.z))) | (uint32_t(uint16_t(bf16_bits(v.w))) << 16);
+      *reinterpret_cast<uint2*>(dst + pix * LDS_PIX_WORDS + c4 * 2) = make_uint2(lo, hi);
+    }
+  };
+
+  // this lane's A row: pixel rb + (wave's 16-row group) + li
+  const int wrow = KSPLIT ? 0 : wave * 16;
+  const int r = rb + wrow + li;
+  const int ly = (wrow + li) / width, lx = (wrow + li) - ((wrow + li) / width) * width;  // within footprint
+  // taps of this wave
+  const int t_first = KSPLIT ? wave : 0;
+  const int t_step = KSPLIT ? 4 : 1;
+
+  // epilogue rows of this lane: rb + wrow + grp * 4 + j (consecutive pixels of one image row)
+  const int r0 = rb + wrow + grp * 4;
+  size_t oidx[4];
+  bool ovalid[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ovalid[j] = r0 + j < gm;
+    oidx[j] = size_t(ovalid[j] ? r0 + j : 0) * cout;
+  }
+  constexpr bool NEED_F = MODE == CONV_RESID_R || MODE == CONV_RESID_T;
+  constexpr bool NEED_I = MODE == CONV_RESID_T || MODE == CONV_STORE_T;
+  constexpr bool NEED_U = MODE == CONV_ACCUM || NEED_F;
+  float ef[4 * NT], ea[4 * NT], ei[4 * NT], eu[4 * NT];
+  if (!KSPLIT || wave == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int q = j * NT + nt;
+        const size_t o = oidx[j] + co0 + nt * 16 + li;
+        if (NEED_F) {
+          ef[q] = A.f[o];
+          ea[q] = A.a[o];
+        }
+        if (NEED_I) ei[q] = A.ainv[o];
+        if (NEED_U) eu[q] = MODE == CONV_ACCUM ? A.out[o] : A.in[o];
+      }
+  }
+
+  v4f acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* W = static_cast<const uint16_t*>(A.w);
+  const size_t wlane = size_t(co0 + li) * cin + grp * 8;
+
+  stage(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int b = c & 1;
+    if (c + 1 < nchunk) stage(c + 1, b ^ 1);  // next chunk loads while this one computes
+    // B fragments of this wave's taps (t = t_first + i t_step) for chunk c
+    constexpr int TPW = KSPLIT ? 3 : 9;
+    v8bf bw[TPW][NT];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = t_first + i * t_step;
+      if (t >= 9) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        bw[i][nt] = *reinterpret_cast<const v8bf*>(W + (size_t(t) * cout + nt * 16) * cin + wlane + c * KC);
+    }
+    const uint32_t* src = buf[b];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = t_first + i * t_step;
+      if (t >= 9) continue;
+      const int ky = t / 3, kx = t - (t / 3) * 3;
+      const int pix = (ly + ky) * TW + (lx + kx);
+      const v8bf av = *reinterpret_cast<const v8bf*>(src + pix * LDS_PIX_WORDS + grp * 4);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[i][nt], acc[nt], 0, 0, 0);
+    }
+    __syncthreads();  // buffer b is rewritten two chunks later; chunk c + 1 is now complete
+  }
+  (void)r;
+
+  if constexpr (KSPLIT) {
+    float* red = reinterpret_cast<float*>(tile);  // reuse the staging area
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (wave > 0) red[((wave - 1) * NT * 4 + nt * 4 + j) * 64 + lane] = acc[nt][j];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[nt][j] += red[(w * NT * 4 + nt * 4 + j) * 64 + lane];
+  }
+
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (!ovalid[j]) continue;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int q = j * NT + nt;
+      const size_t o = oidx[j] + co0 + nt * 16 + li;
+      const float v = acc[nt][j];
+      if constexpr (MODE == CONV_STORE) {
+        A.out[o] = v;
+      } else if constexpr (MODE == CONV_ACCUM) {
+        A.out[o] = eu[q] + v;
+      } else if constexpr (MODE == CONV_STORE_T) {
+        A.out[o] = v;
+        A.out2[o] = ei[q] * v;
+      } else if constexpr (MODE == CONV_RESID_R) {
+        A.out[o] = ef[q] - v - ea[q] * eu[q];
+      } else {
+        A.out[o] = ei[q] * (ef[q] - v - ea[q] * eu[q]);
+      }
+    }
+  }
+}
+
+template <bool KSPLIT, int MODE>
+void lds_dispatch3(const ConvArgs& a, dim3 grid, int nt, size_t lds, hipStream_t s, const ProfScope& ps) {
+  switch (nt) {
+    case 4: launch_k(conv3_lds_kernel<4, KSPLIT, MODE>, grid, dim3(256), uint32_t(lds), s, ps, a); break;
+    case 2: launch_k(conv3_lds_kernel<2, KSPLIT, MODE>, grid, dim3(256), uint32_t(lds), s, ps, a); break;
+    default: launch_k(conv3_lds_kernel<1, KSPLIT, MODE>, grid, dim3(256), uint32_t(lds), s, ps, a); break;
+  }
+}
+
+template <bool KSPLIT>
+void lds_dispatch2(const ConvArgs& a, dim3 grid, int nt, size_t lds, hipStream_t s, const ProfScope& ps) {
+  switch (a.mode) {
+    case CONV_STORE: lds_dispatch3<KSPLIT, CONV_STORE>(a, grid, nt, lds, s, ps); break;
+    case CONV_ACCUM: lds_dispatch3<KSPLIT, CONV_ACCUM>(a, grid, nt, lds, s, ps); break;
+    case CONV_STORE_T: lds_dispatch3<KSPLIT, CONV_STORE_T>(a, grid, nt, lds, s, ps); break;
+    case CONV_RESID_R: lds_dispatch3<KSPLIT, CONV_RESID_R>(a, grid, nt, lds, s, ps); break;
+    default: lds_dispatch3<KSPLIT, CONV_RESID_T>(a, grid, nt, lds, s, ps); break;
   }
 }
 
@@ -610,6 +798,13 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   }
   dim3 grid(unsigned(ksplit ? row_units : (row_units + 3) / 4), unsigned(c.cout / (nt * 16)),
             unsigned(c.nclass));
+  // The LDS-staged kernel covers 3x3 stride-1 2D convolutions with BF16
+  // weights on grids whose width is a multiple of 16 (64-pixel blocks must
+  // tile the grid: segments of one row, or whole rows of a narrow grid).
+  const int gxv = c.g_dim[0], gyv = c.g_dim[1];
+  const bool lds_ok = kind == MFMA_BF16 && c.dim == 2 && c.ostride == 1 && c.cstride == 1 && c.ntap == 9 &&
+                      c.cin % 32 == 0 && gxv % 16 == 0 &&
+                      (ksplit ? true : (gxv >= 64 ? gxv % 64 == 0 : (64 % gxv == 0 && gyv % (64 / gxv) == 0)));
   ProfScope ps(RTE_K_CONV, s, true);
   ps.work = 2.0 * double(gm) * c.cout * double(c.cin) * c.ntap * c.nclass;
   {
@@ -620,7 +815,19 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
     const double extra[] = {0.0, 1.0, 2.0, 2.0, 3.0};  // STORE, ACCUM, STORE_T, RESID_R, RESID_T
     ps.bytes = 4.0 * in_el + wbytes + 4.0 * out_el * (1.0 + extra[c.mode]);
   }
-  if (kind == MFMA_F32) {
+  if (lds_ok) {
+    const int rows = ksplit ? 16 : 64;
+    const int width = gxv >= rows ? rows : gxv;
+    const int nrow = gxv >= rows ? 1 : rows / gxv;
+    size_t lds = size_t(2) * (width + 2) * (nrow + 2) * LDS_PIX_WORDS * 4;
+    if (ksplit) lds = std::max(lds, size_t(3) * nt * 4 * 64 * 4);
+    a.w = c.w->d16;
+    const dim3 g2(unsigned((gm + rows - 1) / rows), grid.y, 1);
+    if (ksplit)
+      lds_dispatch2<true>(a, g2, nt, lds, s, ps);
+    else
+      lds_dispatch2<false>(a, g2, nt, lds, s, ps);
+  } else if (kind == MFMA_F32) {
     a.w = c.w->d32;
     conv_dispatch<0>(a, grid, nt, ksplit, s, ps);
   } else if (c.cin % 32 == 0) {

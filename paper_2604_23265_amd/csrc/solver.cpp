@@ -1,7 +1,11 @@
 // MgNet V-cycle orchestration and the flexible GMRES driver.
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <tuple>
 
 #include "common.h"
 
@@ -134,11 +138,54 @@ SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet) 
 
 namespace {
 
+struct GraphKey {
+  const Operator* op;
+  const Model* m;
+  int precond;
+  const char* ws;
+  const double* x;
+  const double* b;
+  int k;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(op, m, precond, ws, x, b, k) < std::tie(o.op, o.m, o.precond, o.ws, o.x, o.b, o.k);
+  }
+};
+
+std::mutex g_graph_mu;
+std::map<GraphKey, std::unique_ptr<std::vector<hipGraphExec_t>>>& graph_map() {
+  static auto* m = new std::map<GraphKey, std::unique_ptr<std::vector<hipGraphExec_t>>>();
+  return *m;
+}
+
+std::atomic<int64_t> g_steps{0};  // Arnoldi steps enqueued by every solve (timer sampling)
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 }  // namespace
+
+std::vector<hipGraphExec_t>* step_graphs(const Operator* op, const Model* m, int precond, const char* ws,
+                                         const double* x, const double* b, int k) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto& slot = graph_map()[GraphKey{op, m, precond, ws, x, b, k}];
+  if (!slot) slot.reset(new std::vector<hipGraphExec_t>(size_t(k), nullptr));
+  return slot.get();
+}
+
+void drop_step_graphs(const Operator* op) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto& mp = graph_map();
+  for (auto it = mp.begin(); it != mp.end();) {
+    if (it->first.op == op) {
+      for (hipGraphExec_t e : *it->second)
+        if (e) (void)hipGraphExecDestroy(e);
+      it = mp.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
 
 void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o) {
   RTE_REQUIRE(o != nullptr, RTE_EINVAL, "null solve options");
@@ -186,6 +233,9 @@ SolveRun::SolveRun(const Operator& op, const Model* m, const rte_solve_opts& o, 
   bn_ = p;
   mgws_ = ws + lay_.off_mg;
   b_ = o.b ? o.b : op.b64;
+  const char* env = std::getenv("RTE_GRAPHS");
+  graphs_ = !(env && env[0] == '0');
+  if (graphs_) gcache_ = step_graphs(&op, m, o.precond, ws, x, b_, k);
   RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_), 3 * 8 * sizeof(double), hipHostMallocDefault));
   for (auto& e : ev_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -239,24 +289,75 @@ void SolveRun::enqueue_restart() {
 }
 
 // Arnoldi step j: z_j = M(v_j); w = L z_j; CGS2 against v_0..v_j; Givens.
-void SolveRun::enqueue_step(int j) {
+void SolveRun::step_body(int j, hipStream_t s) {
   const int64_t n = op_.n;
   const int nb = lay_.nblk, k = lay_.k;
   const double* Vj = V_ + size_t(j) * n;
   double* Vn = V_ + size_t(j + 1) * n;
   float* Zj = Z_ + size_t(j) * n;
   if (mg_)
-    precond_apply(op_, *m_, kind_, Vj, Zj, mgws_, s_);
+    precond_apply(op_, *m_, kind_, Vj, Zj, mgws_, s);
   else
-    launch_cast_f64_f32(Vj, Zj, n, s_);
-  launch_apply(op_, Zj, 0, Vn, 1, nullptr, false, s_);
-  launch_dots(V_, n, j + 1, Vn, n, part1_, nb, s_);
-  launch_reduce(part1_, nb, j + 1, h1_, s_);
-  launch_update_dots(V_, n, j + 1, h1_, Vn, n, part2_, nb, s_);
-  launch_reduce(part2_, nb, j + 1, h2_, s_);
-  launch_update_norm(V_, n, j + 1, h2_, Vn, n, partn_, nb, s_);
-  launch_finish_step(h1_, h2_, partn_, nb, j, k, H_, cs_, sn_, g_, bn_, stat_, s_);
-  launch_scale_by(Vn, stat_ + 3, n, s_);
+    launch_cast_f64_f32(Vj, Zj, n, s);
+  launch_apply(op_, Zj, 0, Vn, 1, nullptr, false, s);
+  launch_dots(V_, n, j + 1, Vn, n, part1_, nb, s);
+  launch_reduce(part1_, nb, j + 1, h1_, s);
+  launch_update_dots(V_, n, j + 1, h1_, Vn, n, part2_, nb, s);
+  launch_reduce(part2_, nb, j + 1, h2_, s);
+  launch_update_norm(V_, n, j + 1, h2_, Vn, n, partn_, nb, s);
+  launch_finish_step(h1_, h2_, partn_, nb, j, k, H_, cs_, sn_, g_, bn_, stat_, s);
+  launch_scale_by(Vn, stat_ + 3, n, s);
+}
+
+namespace {
+
+// Capture the kernels of one Arnoldi step on a private stream (nothing runs
+// during capture) and instantiate them as a graph.
+hipGraphExec_t capture_step(SolveRun& run, int j) {
+  thread_local hipStream_t cap = nullptr;
+  if (!cap) RTE_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  prof_capturing() = true;
+  hipGraph_t g = nullptr;
+  RTE_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  try {
+    run.step_body(j, cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    prof_capturing() = false;
+    throw;
+  }
+  prof_capturing() = false;
+  RTE_HIP(hipStreamEndCapture(cap, &g));
+  hipGraphExec_t e = nullptr;
+  hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  RTE_HIP(err);
+  return e;
+}
+
+}  // namespace
+
+// Replays the step's graph (captured on first use for this workspace);
+// while the kernel-class timer is on, one step in `every` runs eagerly with
+// all of its launches of the enabled classes timed.
+void SolveRun::enqueue_step(int j) {
+  const int stride = prof_stride();
+  const bool sample = stride > 0 && (g_steps.fetch_add(1) % stride) == 0;
+  if (!graphs_ || sample) {
+    prof_force() = sample;
+    try {
+      step_body(j, s_);
+    } catch (...) {
+      prof_force() = false;
+      throw;
+    }
+    prof_force() = false;
+  } else {
+    hipGraphExec_t& ge = (*gcache_)[j];
+    if (!ge) ge = capture_step(*this, j);
+    RTE_HIP(hipGraphLaunch(ge, s_));
+  }
   read_into(j % 2, stat_, 2);
   j_enq_ = j + 1;
 }

@@ -239,3 +239,22 @@ def test_c2_full_solve_meets_rtol_in_fp64(c2_full, mode):
     say("  oracle residual", res)
     assert res <= 1e-6 * (1 + 1e-6)
     assert abs(res - st["rel_residual"]) <= 1e-9
+
+
+def test_graph_replays_equal_eager_solves(monkeypatch):
+    """Arnoldi steps run as replayed HIP graphs; every replay must equal the eager run."""
+    torch = torch_cuda()
+    say("case graphs vs eager c2_small")
+    prob, model, op, P = setup_case("c2_small")
+    monkeypatch.setenv("RTE_GRAPHS", "0")
+    ref, st0 = op.solve(model=model, precond="bf16", rtol=1e-8)
+    monkeypatch.setenv("RTE_GRAPHS", "1")
+    ws = torch.empty(op.workspace_bytes(model, precond="bf16", rtol=1e-8), dtype=torch.uint8, device="cuda")
+    psi = torch.empty(op.n, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        x, st = op.solve(model=model, psi=psi, workspace=ws, precond="bf16", rtol=1e-8)
+        assert st["iterations"] == st0["iterations"]
+        assert bool((x == ref).all()), "graph replay %d differs from the eager solve" % rep
+        # unrelated eager work and a synchronisation between replays
+        op.apply(torch.randn(op.n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
