@@ -179,13 +179,14 @@ int krylov_blocks(int64_t n);
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part,
                  int nblk, hipStream_t s);
 void launch_reduce(const double* part, int nblk, int nv, double* out, hipStream_t s);
-void launch_update_dots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                        double* part, int nblk, hipStream_t s);
-void launch_update_norm(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                        double* part, int nblk, hipStream_t s);
-void launch_finish_step(const double* h1, const double* h2, const double* partn, int nblk, int j,
-                        int k, double* H, double* cs, double* sn, double* g, const double* bnorm,
-                        double* stat, hipStream_t s);
+// w <- w - V h; part: V^T w (first nv) and w.w (index nv)
+void launch_updots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
+                   double* part, int nblk, hipStream_t s);
+// w <- (w - V h) * f[0]
+void launch_update_scale(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
+                         const double* f, hipStream_t s);
+void launch_finish_step(const double* h1, const double* h2, int j, int k, double* H, double* cs, double* sn,
+                        double* g, const double* bnorm, double* stat, hipStream_t s);
 void launch_scale_by(double* w, const double* stat_inv, int64_t n, hipStream_t s);
 void launch_start_cycle(const double* partn, int nblk, double* g, int k, double* stat,
                         hipStream_t s);

@@ -44,81 +44,110 @@ __device__ inline void chunk_of(int64_t n, int nblk, int64_t& beg, int64_t& end)
   end = beg + chunk < n ? beg + chunk : n;
 }
 
-// part[blk][i] = sum over the block's chunk of V_i . w, i < nv.
-__device__ __attribute__((always_inline)) inline void dots_body(const double* __restrict__ V, int64_t ldv, int nv,
-                                 const double* __restrict__ w, int64_t n, double* __restrict__ part,
-                                 int nblk, double* red) {
-  int64_t beg, end;
-  chunk_of(n, nblk, beg, end);
-  for (int vb = 0; vb < nv; vb += NVB) {
-    double acc[NVB];
+// The streaming kernels below keep one element of every basis vector in
+// registers: NV is a compile-time register budget (8, 16, 32 or 64 >= nv).
+// Loads of indices past nv re-read vector nv - 1 (a cached line) and are
+// masked arithmetically, so no branch separates the loads of an element.
+template <int NV>
+__device__ inline void load_column(const double* __restrict__ V, int64_t ldv, int nv, int64_t e, double* v) {
 #pragma unroll
-    for (int q = 0; q < NVB; ++q) acc[q] = 0.0;
-    const int cnt = nv - vb < NVB ? nv - vb : NVB;
-#pragma unroll 4
-    for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
-      const double we = w[e];
+  for (int i = 0; i < NV; ++i) v[i] = V[int64_t(i < nv ? i : nv - 1) * ldv + e];
+}
+
+// Block sums of acc[0 .. cnt-1] (cnt uniform) written to part[blk][base + i].
+template <int NV>
+__device__ inline void block_store(double* acc, int cnt, double* __restrict__ part, int base, double* red) {
 #pragma unroll
-      for (int q = 0; q < NVB; ++q)
-        if (q < cnt) acc[q] += V[int64_t(vb + q) * ldv + e] * we;
-    }
-#pragma unroll
-    for (int q = 0; q < NVB; ++q) {
-      if (q >= cnt) break;
-      const double s = block_sum(acc[q], red);
-      if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + vb + q] = s;
+  for (int i = 0; i < NV; ++i) {
+    if (i < cnt) {  // uniform: every thread reaches the same barriers
+      const double s = block_sum(acc[i], red);
+      if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + base + i] = s;
     }
   }
 }
 
+// part[blk][i] = sum over the block's chunk of V_i . w, i < nv.
+template <int NV>
 __global__ __launch_bounds__(KT) void dots_kernel(const double* __restrict__ V, int64_t ldv, int nv,
                                                   const double* __restrict__ w, int64_t n,
                                                   double* __restrict__ part, int nblk) {
   __shared__ double red[KT / 64];
-  dots_body(V, ldv, nv, w, n, part, nblk, red);
+  int64_t beg, end;
+  chunk_of(n, nblk, beg, end);
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
+    double v[NV];
+    load_column<NV>(V, ldv, nv, e, v);
+    const double we = w[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += v[i] * we;
+  }
+  block_store<NV>(acc, nv, part, 0, red);
 }
 
-// w -= sum_i h_i V_i, then the partial dots of the updated w with every V_i.
-__global__ __launch_bounds__(KT) void update_dots_kernel(const double* __restrict__ V, int64_t ldv, int nv,
-                                                         const double* __restrict__ h, double* __restrict__ w,
-                                                         int64_t n, double* __restrict__ part, int nblk) {
+// First Gram-Schmidt correction and the second pass's dots in one read of
+// V: w1 = w - sum_i h_i V_i (written back), then part[blk][i] = V_i . w1
+// (i < nv) and part[blk][nv] = w1 . w1.  With HOLD the element's column of V
+// stays in registers between the two uses; without it (the widest budget,
+// which would not fit) the column is loaded again, from cache.
+template <int NV, bool HOLD>
+__global__ __launch_bounds__(KT) void updots_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                                                    const double* __restrict__ h, double* __restrict__ w,
+                                                    int64_t n, double* __restrict__ part, int nblk) {
   __shared__ double red[KT / 64];
-  __shared__ double hs[HMAX];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __shared__ double hs[NV];
+  if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
   __syncthreads();
   int64_t beg, end;
   chunk_of(n, nblk, beg, end);
+  double acc[NV];
+  double ww = 0.0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
-    double acc = w[e];
-#pragma unroll 8
-    for (int i = 0; i < nv; ++i) acc -= hs[i] * V[int64_t(i) * ldv + e];
-    w[e] = acc;
+    double x = w[e];
+    if constexpr (HOLD) {
+      double v[NV];
+      load_column<NV>(V, ldv, nv, e, v);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) x -= hs[i] * v[i];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[i] * x;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) x -= hs[i] * V[int64_t(i < nv ? i : nv - 1) * ldv + e];
+      __asm__ volatile("" ::: "memory");  // compiler fence: reload the column, do not keep it live
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += V[int64_t(i < nv ? i : nv - 1) * ldv + e] * x;
+    }
+    w[e] = x;
+    ww += x * x;
   }
-  // the dots re-read this block's own chunk of w, written by its own threads
-  __syncthreads();
-  dots_body(V, ldv, nv, w, n, part, nblk, red);
+  block_store<NV>(acc, nv, part, 0, red);
+  const double s = block_sum(ww, red);
+  if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + nv] = s;
 }
 
-// w -= sum_i h_i V_i, then the partial sums of w^2.
-__global__ __launch_bounds__(KT) void update_norm_kernel(const double* __restrict__ V, int64_t ldv, int nv,
-                                                         const double* __restrict__ h, double* __restrict__ w,
-                                                         int64_t n, double* __restrict__ part, int nblk) {
-  __shared__ double red[KT / 64];
-  __shared__ double hs[HMAX];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+// Second correction and normalisation: w = (w - sum_i h_i V_i) * f[0].
+template <int NV>
+__global__ __launch_bounds__(KT) void update_scale_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+                                                          const double* __restrict__ h, double* __restrict__ w,
+                                                          int64_t n, const double* __restrict__ f) {
+  __shared__ double hs[NV];
+  if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
   __syncthreads();
-  int64_t beg, end;
-  chunk_of(n, nblk, beg, end);
-  double ss = 0.0;
-  for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
-    double acc = w[e];
-#pragma unroll 8
-    for (int i = 0; i < nv; ++i) acc -= hs[i] * V[int64_t(i) * ldv + e];
-    w[e] = acc;
-    ss += acc * acc;
+  const double a = f[0];
+  int64_t e = int64_t(blockIdx.x) * KT + threadIdx.x;
+  for (; e < n; e += int64_t(gridDim.x) * KT) {
+    double v[NV];
+    load_column<NV>(V, ldv, nv, e, v);
+    double x = w[e];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) x -= hs[i] * v[i];
+    w[e] = x * a;
   }
-  const double s = block_sum(ss, red);
-  if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX] = s;
 }
 
 // out[i] = sum_blk part[blk][i], one block per i, fixed order.
@@ -133,31 +162,30 @@ __global__ __launch_bounds__(KT) void reduce_kernel(const double* __restrict__ p
 }
 
 // Close Arnoldi step j: assemble column j of the Hessenberg matrix
-// (h1 + h2 from the two Gram-Schmidt passes, ||w|| below the diagonal),
-// rotate it by the previous Givens rotations, form the new rotation, update
-// g, and publish stat = {|g_{j+1}|/||b||, flags, ||w||, 1/||w||}.
-// flags: 1 = non-finite value, 2 = ||w|| negligible (the Krylov space is
-// invariant: the least-squares solution is exact).
-__global__ __launch_bounds__(KT) void finish_kernel(const double* __restrict__ h1, const double* __restrict__ h2,
-                                                    const double* __restrict__ partn, int nblk, int j, int k,
-                                                    double* __restrict__ H, double* __restrict__ cs,
-                                                    double* __restrict__ sn, double* __restrict__ g,
-                                                    const double* __restrict__ bnorm, double* __restrict__ stat) {
-  __shared__ double red[KT / 64];
-  double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += KT) s += partn[int64_t(b) * HMAX];
-  s = block_sum(s, red);
-  if (threadIdx.x != 0) return;
-  const double hn = sqrt(s);
+// (h1 + h2 from the two Gram-Schmidt passes; below the diagonal the norm of
+// w2 = w1 - V h2, which for orthonormal V is sqrt(||w1||^2 - ||h2||^2) since
+// h2 = V^T w1), rotate it by the previous Givens rotations, form the new
+// rotation, update g, and publish stat = {|g_{j+1}|/||b||, flags, ||w2||,
+// 1/||w2||}.  h2[j + 1] holds ||w1||^2.  flags: 1 = non-finite value,
+// 2 = ||w2|| negligible (the Krylov space is invariant: the least-squares
+// solution is exact).
+__global__ void finish_kernel(const double* __restrict__ h1, const double* __restrict__ h2, int j, int k,
+                              double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                              double* __restrict__ g, const double* __restrict__ bnorm,
+                              double* __restrict__ stat) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double* col = H + int64_t(j) * (k + 1);
-  double cmax = 0;
+  double cmax = 0, h2sq = 0;
   for (int i = 0; i <= j; ++i) {
     col[i] = h1[i] + h2[i];
     cmax = fmax(cmax, fabs(col[i]));
+    h2sq += h2[i] * h2[i];
   }
+  const double hn2 = h2[j + 1] - h2sq;
+  const double hn = hn2 > 0 ? sqrt(hn2) : 0.0;
   col[j + 1] = hn;
   int flags = 0;
-  if (!isfinite(hn) || !isfinite(cmax)) flags |= 1;
+  if (!isfinite(hn2) || !isfinite(cmax)) flags |= 1;
   if (hn <= 1e-14 * cmax) flags |= 2;
   for (int i = 0; i < j; ++i) {
     const double t = cs[i] * col[i] + sn[i] * col[i + 1];
@@ -253,12 +281,34 @@ int krylov_blocks(int64_t n) {
   return int(b);
 }
 
+namespace {
+template <int NV>
+void dots_go(dim3 g, hipStream_t s, const ProfScope& ps, const double* V, int64_t ldv, int nv, const double* w,
+             int64_t n, double* part, int nblk) {
+  launch_k(dots_kernel<NV>, g, dim3(KT), 0, s, ps, V, ldv, nv, w, n, part, nblk);
+}
+template <int NV>
+void updots_go(dim3 g, hipStream_t s, const ProfScope& ps, const double* V, int64_t ldv, int nv, const double* h,
+               double* w, int64_t n, double* part, int nblk) {
+  launch_k(updots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, part, nblk);
+}
+template <int NV>
+void upscale_go(dim3 g, hipStream_t s, const ProfScope& ps, const double* V, int64_t ldv, int nv, const double* h,
+                double* w, int64_t n, const double* f) {
+  launch_k(update_scale_kernel<NV>, g, dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, f);
+}
+}  // namespace
+
 void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, int nblk,
                  hipStream_t s) {
-  RTE_REQUIRE(nv >= 1 && nv <= HMAX, RTE_EINVAL, "too many basis vectors");
+  RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 1);
-  launch_k(dots_kernel, dim3(nblk), dim3(KT), 0, s, ps, V, ldv, nv, w, n, part, nblk);
+  const dim3 g(nblk);
+  if (nv <= 8) dots_go<8>(g, s, ps, V, ldv, nv, w, n, part, nblk);
+  else if (nv <= 16) dots_go<16>(g, s, ps, V, ldv, nv, w, n, part, nblk);
+  else if (nv <= 32) dots_go<32>(g, s, ps, V, ldv, nv, w, n, part, nblk);
+  else dots_go<64>(g, s, ps, V, ldv, nv, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
@@ -268,28 +318,36 @@ void launch_reduce(const double* part, int nblk, int nv, double* out, hipStream_
   RTE_HIP(hipGetLastError());
 }
 
-void launch_update_dots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                        double* part, int nblk, hipStream_t s) {
+void launch_updots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double* part,
+                   int nblk, hipStream_t s) {
+  RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once
-  launch_k(update_dots_kernel, dim3(nblk), dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, part, nblk);
+  const dim3 g(nblk);
+  if (nv <= 8) updots_go<8>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
+  else if (nv <= 16) updots_go<16>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
+  else if (nv <= 32) updots_go<32>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
+  else updots_go<64>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_update_norm(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                        double* part, int nblk, hipStream_t s) {
+void launch_update_scale(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
+                         const double* f, hipStream_t s) {
+  RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 2);
-  launch_k(update_norm_kernel, dim3(nblk), dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, part, nblk);
+  const dim3 g(ew_grid(n));
+  if (nv <= 8) upscale_go<8>(g, s, ps, V, ldv, nv, h, w, n, f);
+  else if (nv <= 16) upscale_go<16>(g, s, ps, V, ldv, nv, h, w, n, f);
+  else if (nv <= 32) upscale_go<32>(g, s, ps, V, ldv, nv, h, w, n, f);
+  else upscale_go<64>(g, s, ps, V, ldv, nv, h, w, n, f);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_finish_step(const double* h1, const double* h2, const double* partn, int nblk, int j, int k,
-                        double* H, double* cs, double* sn, double* g, const double* bnorm, double* stat,
-                        hipStream_t s) {
+void launch_finish_step(const double* h1, const double* h2, int j, int k, double* H, double* cs, double* sn,
+                        double* g, const double* bnorm, double* stat, hipStream_t s) {
   ProfScope ps(RTE_K_ORTH, s, true);
-  launch_k(finish_kernel, dim3(1), dim3(KT), 0, s, ps, h1, h2, partn, nblk, j, k, H, cs, sn, g, bnorm,
-                     stat);
+  launch_k(finish_kernel, dim3(1), dim3(64), 0, s, ps, h1, h2, j, k, H, cs, sn, g, bnorm, stat);
   RTE_HIP(hipGetLastError());
 }
 

@@ -300,13 +300,14 @@ void SolveRun::step_body(int j, hipStream_t s) {
   else
     launch_cast_f64_f32(Vj, Zj, n, s);
   launch_apply(op_, Zj, 0, Vn, 1, nullptr, false, s);
+  // CGS2 in three passes over V: h1 = V^T w; w1 = w - V h1 with h2 = V^T w1
+  // and ||w1||^2; then v_{j+1} = (w1 - V h2) / ||w1 - V h2||
   launch_dots(V_, n, j + 1, Vn, n, part1_, nb, s);
   launch_reduce(part1_, nb, j + 1, h1_, s);
-  launch_update_dots(V_, n, j + 1, h1_, Vn, n, part2_, nb, s);
-  launch_reduce(part2_, nb, j + 1, h2_, s);
-  launch_update_norm(V_, n, j + 1, h2_, Vn, n, partn_, nb, s);
-  launch_finish_step(h1_, h2_, partn_, nb, j, k, H_, cs_, sn_, g_, bn_, stat_, s);
-  launch_scale_by(Vn, stat_ + 3, n, s);
+  launch_updots(V_, n, j + 1, h1_, Vn, n, part2_, nb, s);
+  launch_reduce(part2_, nb, j + 2, h2_, s);
+  launch_finish_step(h1_, h2_, j, k, H_, cs_, sn_, g_, bn_, stat_, s);
+  launch_update_scale(V_, n, j + 1, h2_, Vn, n, stat_ + 3, s);
 }
 
 namespace {
