@@ -1,5 +1,6 @@
 // extern "C" entry points of librte: argument checks, error mapping and the
 // kernel-class event timer.
+#include <chrono>
 #include <cstring>
 #include <memory>
 
@@ -75,6 +76,16 @@ bool& prof_force() {
   return v;
 }
 
+bool& prof_quiet() {
+  thread_local bool v = false;
+  return v;
+}
+
+double& prof_scale() {
+  thread_local double v = 1.0;
+  return v;
+}
+
 int prof_stride() {
   Prof& P = prof();
   int s = 0;
@@ -85,7 +96,7 @@ int prof_stride() {
 
 ProfScope::ProfScope(int c, hipStream_t st, bool ext_launch) : cls(c), s(st), ext(ext_launch) {
   Prof& P = prof();
-  if (P.every[c] <= 0 || prof_capturing()) return;
+  if (P.every[c] <= 0 || prof_capturing() || (prof_quiet() && !prof_force())) return;
   std::lock_guard<std::mutex> lk(P.mu);
   if (P.every[c] <= 0) return;
   if (!prof_force() && (P.seen[c]++ % P.every[c]) != 0) return;
@@ -100,7 +111,8 @@ ProfScope::~ProfScope() {
   std::lock_guard<std::mutex> lk(P.mu);
   try {
     if (!ext) (void)hipEventRecord(e1, s);
-    P.pending[cls].push_back({e0, e1, work, bytes < 0 ? work : bytes});
+    const double sc = prof_scale();
+    P.pending[cls].push_back({e0, e1, work * sc, (bytes < 0 ? work : bytes) * sc});
     if (P.pending[cls].size() >= 65536) P.drain(cls);
   } catch (...) {
   }
@@ -150,7 +162,10 @@ rte_status mgnet_load(const void* blob, size_t bytes, mgnet_model** out) {
 }
 
 rte_status mgnet_free(mgnet_model* model) {
-  return guarded([&] { delete model; });
+  return guarded([&] {
+    if (model) drop_step_graphs(model->m.get());
+    delete model;
+  });
 }
 
 rte_status mgnet_describe(const mgnet_model* h, int* d) {
@@ -175,7 +190,6 @@ rte_status rte_build_operator(const rte_geometry* geom, const rte_medium* med, c
 
 rte_status rte_operator_free(rte_operator* op) {
   return guarded([&] {
-    if (op) drop_step_graphs(op->op.get());
     delete op;
   });
 }
@@ -199,13 +213,13 @@ rte_status rte_operator_copy_array(const rte_operator* h, int which, int level, 
     size_t need = 0;
     DevArena tmp;
     switch (which) {
-      case RTE_ARR_RHS: src = o.b64; need = size_t(o.n) * 8; break;
-      case RTE_ARR_SCATTER: src = o.S64; need = size_t(o.ndir) * o.ndir * 8; break;
+      case RTE_ARR_RHS: src = o.a.b64; need = size_t(o.n) * 8; break;
+      case RTE_ARR_SCATTER: src = o.a.S64; need = size_t(o.ndir) * o.ndir * 8; break;
       case RTE_ARR_SIGMA: {
         need = size_t(o.cells) * 16;
         RTE_REQUIRE(bytes == need, RTE_EINVAL, "rte_operator_copy_array: wrong size");
-        RTE_HIP(hipMemcpyAsync(dst, o.sT64, size_t(o.cells) * 8, hipMemcpyDeviceToDevice, S(stream)));
-        RTE_HIP(hipMemcpyAsync(static_cast<char*>(dst) + size_t(o.cells) * 8, o.sA64, size_t(o.cells) * 8,
+        RTE_HIP(hipMemcpyAsync(dst, o.a.sT64, size_t(o.cells) * 8, hipMemcpyDeviceToDevice, S(stream)));
+        RTE_HIP(hipMemcpyAsync(static_cast<char*>(dst) + size_t(o.cells) * 8, o.a.sA64, size_t(o.cells) * 8,
                                hipMemcpyDeviceToDevice, S(stream)));
         return;
       }
@@ -213,7 +227,7 @@ rte_status rte_operator_copy_array(const rte_operator* h, int which, int level, 
       case RTE_ARR_FIELD_AINV: {
         RTE_REQUIRE(o.model != nullptr, RTE_EINVAL, "operator has no CoeffNet fields");
         RTE_REQUIRE(level >= 0 && level < o.model->levels, RTE_EINVAL, "level out of range");
-        src = which == RTE_ARR_FIELD_A ? o.fa[level] : o.fainv[level];
+        src = which == RTE_ARR_FIELD_A ? o.a.fa[level] : o.a.fainv[level];
         need = size_t(o.level_cells(level)) * (o.model->c0 << level) * 4;
         break;
       }
@@ -230,7 +244,7 @@ rte_status rte_apply(const rte_operator* h, const void* x, void* y, int precisio
     RTE_REQUIRE(x != y, RTE_EINVAL, "rte_apply: x and y must not alias");
     RTE_REQUIRE(precision == RTE_FP32 || precision == RTE_FP64, RTE_EINVAL, "rte_apply: bad precision");
     const int t = precision == RTE_FP64 ? 1 : 0;
-    launch_apply(*h->op, x, t, y, t, nullptr, precision == RTE_FP64, S(stream));
+    launch_apply(Target::single(*h->op), x, t, y, t, nullptr, precision == RTE_FP64, S(stream));
   });
 }
 
@@ -239,7 +253,7 @@ rte_status rte_residual(const rte_operator* h, const double* x, double* r, void*
     RTE_REQUIRE(h && x && r, RTE_EINVAL, "rte_residual: null argument");
     RTE_REQUIRE(static_cast<const void*>(x) != static_cast<const void*>(r), RTE_EINVAL,
                 "rte_residual: x and r must not alias");
-    launch_apply(*h->op, x, 1, r, 1, h->op->b64, true, S(stream));
+    launch_apply(Target::single(*h->op), x, 1, r, 1, h->op->a.b64, true, S(stream));
   });
 }
 
@@ -262,7 +276,7 @@ rte_status rte_precond_apply(const rte_operator* h, const mgnet_model* model, in
     RTE_REQUIRE(ws_bytes >= precond_bytes(o, m), RTE_ENOMEM, "rte_precond_apply: workspace too small");
     RTE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL, "workspace must be 256-byte aligned");
     m.ensure_on_device();
-    precond_apply(o, m, precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16, v, z, static_cast<char*>(ws),
+    precond_apply(Target::single(o), m, precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16, v, z, static_cast<char*>(ws),
                   S(stream));
   });
 }
@@ -273,7 +287,7 @@ rte_status rte_workspace_bytes(const rte_operator* h, const mgnet_model* model, 
     RTE_REQUIRE(h && opts && bytes, RTE_EINVAL, "rte_workspace_bytes: null argument");
     const Model* m = model ? model->m.get() : nullptr;
     validate_opts(*h->op, m, opts);
-    *bytes = solve_layout(*h->op, m, opts->restart, opts->precond != RTE_PC_NONE).total;
+    *bytes = batch_table_bytes(1) + solve_layout(*h->op, m, opts->restart, opts->precond != RTE_PC_NONE).total;
   });
 }
 
@@ -282,20 +296,35 @@ rte_status rte_solve(const rte_operator* h, const mgnet_model* model, const rte_
   rte_status solve_status = RTE_OK;
   rte_status st = guarded([&] {
     RTE_REQUIRE(h != nullptr && opts != nullptr, RTE_EINVAL, "rte_solve: null argument");
-    SolveRun run(*h->op, model ? model->m.get() : nullptr, *opts, static_cast<char*>(ws), ws_bytes, psi,
-                 S(stream));
-    run.start();
-    while (!run.done()) {
-      run.wait();
-      run.advance();
+    const Operator& op = *h->op;
+    const Model* m = model ? model->m.get() : nullptr;
+    validate_opts(op, m, opts);
+    RTE_REQUIRE(ws != nullptr && psi != nullptr, RTE_EINVAL, "null workspace or output");
+    const size_t tb = batch_table_bytes(1);
+    const size_t need = tb + solve_layout(op, m, opts->restart, opts->precond != RTE_PC_NONE).total;
+    RTE_REQUIRE(ws_bytes >= need, RTE_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    RTE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL, "workspace must be 256-byte aligned");
+    char* w = static_cast<char*>(ws);
+    Batch b(op, m, opts->restart, opts->precond, 1, w, S(stream));
+    b.add(nullptr, op, *opts, w + tb, psi, std::chrono::duration<double, std::milli>(
+                                               std::chrono::steady_clock::now().time_since_epoch()).count());
+    std::vector<Batch::Finished> done;
+    while (!b.idle()) {
+      b.wait();
+      b.advance();
+      b.collect(done);
     }
-    run.fill_stats(stats);
-    solve_status = run.status();
+    RTE_REQUIRE(done.size() == 1, RTE_EDEVICE, "solve did not report a result");
+    if (stats) *stats = done[0].stats;
+    solve_status = done[0].status;
   });
   if (st != RTE_OK) return st;
-  if (solve_status != RTE_OK)
-    set_last_error(solve_status == RTE_ENOCONV ? "solve stopped before reaching rtol"
-                                               : "non-finite values in the Krylov process");
+  if (solve_status == RTE_ENOCONV)
+    set_last_error("solve stopped before reaching rtol");
+  else if (solve_status == RTE_EBREAKDOWN)
+    set_last_error("non-finite values in the Krylov process");
+  else if (solve_status == RTE_EINVAL)
+    set_last_error("right-hand side is not finite");
   return solve_status;
 }
 

@@ -23,12 +23,22 @@ constexpr int DSLOTS = 16; // direction slots per block: thread t -> cell t % 16
 // LDS; the scatter sum_n S_mn x_n then reuses each x_n read for all of the
 // thread's directions.  Upwind neighbours are requested before the scatter.
 template <class T, class TI, class TO, bool RES, bool LDS_S, int DPT>
-__global__ __launch_bounds__(256) void apply_kernel(const TI* __restrict__ x, TO* __restrict__ y,
+__global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restrict__ x, TO* __restrict__ y,
                                                     const double* __restrict__ b,
                                                     const T* __restrict__ sT, const T* __restrict__ sA,
                                                     const T* __restrict__ S, const T* __restrict__ dc,
                                                     const int* __restrict__ sg, int N, int nx, int ny,
                                                     int nz, int cells) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  x = at(x, bs.ws);
+  y = at(y, bs.ws);
+  if (RES) b = at(b, bs.ws);
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  S = at(S, bs.op);
+  dc = at(dc, bs.op);
+  sg = at(sg, bs.op);
   extern __shared__ char smem[];
   T* xs = reinterpret_cast<T*>(smem);       // [N][TILE]
   T* Ss = xs + N * TILE;                    // [N][N + 1]: padded rows, so the direction
@@ -100,13 +110,15 @@ __global__ __launch_bounds__(256) void apply_kernel(const TI* __restrict__ x, TO
 }
 
 template <class T, class TI, class TO, bool RES, bool LDS_S>
-void go_dpt(const Operator& op, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
+void go_dpt(const Target& Tg, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
             const T* dc, size_t lds, hipStream_t s, const ProfScope& ps) {
-  const unsigned grid = unsigned((op.cells + TILE - 1) / TILE);
+  const Operator& op = *Tg.op;
+  const dim3 grid(unsigned((op.cells + TILE - 1) / TILE), 1, unsigned(Tg.sl.count));
   const int dpt = (op.ndir + DSLOTS - 1) / DSLOTS;
   auto launch = [&](auto kern) {
-    launch_k(kern, dim3(grid), dim3(256), uint32_t(lds), s, ps, static_cast<const TI*>(x), static_cast<TO*>(y), b,
-             sT, sA, S, dc, static_cast<const int*>(op.dsgn), op.ndir, op.nx, op.ny, op.nz, int(op.cells));
+    launch_k(kern, grid, dim3(256), uint32_t(lds), s, ps, Tg.sl, static_cast<const TI*>(x), static_cast<TO*>(y),
+             b, sT, sA, S, dc, static_cast<const int*>(Tg.arr.dsgn), op.ndir, op.nx, op.ny, op.nz,
+             int(op.cells));
   };
   if (dpt <= 1)
     launch(apply_kernel<T, TI, TO, RES, LDS_S, 1>);
@@ -121,36 +133,39 @@ void go_dpt(const Operator& op, const void* x, void* y, const double* b, const T
 }
 
 template <class T, class TI, class TO, bool RES>
-void go(const Operator& op, const void* x, void* y, const double* b, hipStream_t s, const ProfScope& ps) {
+void go(const Target& Tg, const void* x, void* y, const double* b, hipStream_t s, const ProfScope& ps) {
+  const OpArrays& A = Tg.arr;
   const T* sT;
   const T* sA;
   const T* S;
   const T* dc;
   if constexpr (sizeof(T) == 8) {
-    sT = op.sT64; sA = op.sA64; S = op.S64; dc = op.dc64;
+    sT = A.sT64; sA = A.sA64; S = A.S64; dc = A.dc64;
   } else {
-    sT = op.sT32; sA = op.sA32; S = op.S32; dc = op.dc32;
+    sT = A.sT32; sA = A.sA32; S = A.S32; dc = A.dc32;
   }
-  const size_t lx = size_t(op.ndir) * TILE * sizeof(T);
-  const size_t ls = size_t(op.ndir) * (op.ndir + 1) * sizeof(T);
+  const int N = Tg.op->ndir;
+  const size_t lx = size_t(N) * TILE * sizeof(T);
+  const size_t ls = size_t(N) * (N + 1) * sizeof(T);
   constexpr size_t kLds = 48 * 1024;
   if (lx + ls <= kLds)
-    go_dpt<T, TI, TO, RES, true>(op, x, y, b, sT, sA, S, dc, lx + ls, s, ps);
+    go_dpt<T, TI, TO, RES, true>(Tg, x, y, b, sT, sA, S, dc, lx + ls, s, ps);
   else
-    go_dpt<T, TI, TO, RES, false>(op, x, y, b, sT, sA, S, dc, lx, s, ps);
+    go_dpt<T, TI, TO, RES, false>(Tg, x, y, b, sT, sA, S, dc, lx, s, ps);
   RTE_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-void launch_apply(const Operator& op, const void* x, int tin, void* y, int tout, const double* b,
-                  bool fp64, hipStream_t s) {
+void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, const double* b, bool fp64,
+                  hipStream_t s) {
+  const Operator& op = *Tg.op;
   const double unknowns = double(op.n), cells = double(op.cells);
   if (b) {
     RTE_REQUIRE(fp64 && tin == 1 && tout == 1, RTE_EINVAL, "residual is FP64 only");
     ProfScope ps(RTE_K_RESIDUAL, s, true);
     ps.work = 24.0 * unknowns + 16.0 * cells;  // x, b in; r out; sT, sA
-    go<double, double, double, true>(op, x, y, b, s, ps);
+    go<double, double, double, true>(Tg, x, y, b, s, ps);
     return;
   }
   ProfScope ps(RTE_K_APPLY, s, true);
@@ -158,13 +173,13 @@ void launch_apply(const Operator& op, const void* x, int tin, void* y, int tout,
   ps.work = (esz[tin] + esz[tout]) * unknowns + (fp64 ? 16.0 : 8.0) * cells;
   if (fp64) {
     RTE_REQUIRE(tin == 1 && tout == 1, RTE_EINVAL, "FP64 apply takes FP64 vectors");
-    go<double, double, double, false>(op, x, y, nullptr, s, ps);
+    go<double, double, double, false>(Tg, x, y, nullptr, s, ps);
   } else if (tin == 0 && tout == 0) {
-    go<float, float, float, false>(op, x, y, nullptr, s, ps);
+    go<float, float, float, false>(Tg, x, y, nullptr, s, ps);
   } else if (tin == 0 && tout == 1) {
-    go<float, float, double, false>(op, x, y, nullptr, s, ps);
+    go<float, float, double, false>(Tg, x, y, nullptr, s, ps);
   } else {
-    go<float, double, float, false>(op, x, y, nullptr, s, ps);
+    go<float, double, float, false>(Tg, x, y, nullptr, s, ps);
   }
 }
 

@@ -60,6 +60,50 @@ struct DevArena {
 
 uint16_t bf16_rne(float f);
 
+// ----------------------------------------------------- batched launches ---
+// A group of solves of one shape advances together: grid z of every launch
+// runs over the group's slots, and each per-solve array argument is an
+// offset from the slot's workspace base or operator-block base, both read
+// from the slot table.  With no table a launch covers one solve and its
+// array arguments are absolute addresses.
+struct SlotDesc {
+  uint64_t ws;       // workspace base of the solve held by the slot
+  uint64_t op;       // operator-block base of that solve
+  int32_t live;      // 1 while the solve takes Arnoldi steps in this cycle
+  int32_t occupied;  // 1 while the slot holds a solve
+  int32_t jj;        // Arnoldi steps completed in this cycle
+  int32_t limit;     // Arnoldi steps allowed in this cycle
+  double rtol;       // stop the cycle once |g_{j+1}| / ||b|| <= rtol
+  int32_t bad;       // a non-finite value appeared in this cycle
+  int32_t pad;
+};
+static_assert(sizeof(SlotDesc) == 48, "slot descriptor layout");
+
+struct Slots {
+  SlotDesc* tab = nullptr;
+  int count = 1;  // slots covered by the launch (grid z extent)
+  int gate = 0;   // 0: live slots run, 1: occupied slots run
+};
+
+struct SlotBase {
+  uint64_t ws = 0, op = 0;
+};
+
+// Reads slot z's bases; false when the slot sits this launch out.
+__device__ inline bool slot_open(const Slots& sl, int z, SlotBase& b) {
+  if (!sl.tab) return true;
+  const SlotDesc* d = sl.tab + z;
+  b.ws = d->ws;
+  b.op = d->op;
+  return (sl.gate ? d->occupied : d->live) != 0;
+}
+
+template <class T>
+__host__ __device__ inline T* at(T* p, uint64_t base) {
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + base);
+}
+
+
 // ------------------------------------------------------------ the model ---
 // A convolution in GEMM layout: w[tap][cout][cin] (input channels fastest).
 struct ConvW {
@@ -94,6 +138,27 @@ struct Model {
 };
 
 // --------------------------------------------------------- the operator ---
+constexpr int MAX_LEVELS = 8;
+
+// The operator's device arrays.  They live in one block whose layout
+// depends only on the shape (dim, grid, directions, model levels and
+// channels), so operators of one shape have them at equal offsets.
+struct OpArrays {
+  double* b64 = nullptr;      // [n]
+  float* sT32 = nullptr;      // sigma_T / eps            [cells]
+  float* sA32 = nullptr;      // eps sigma_a              [cells]
+  double* sT64 = nullptr;
+  double* sA64 = nullptr;
+  float* S32 = nullptr;       // [N][N]
+  double* S64 = nullptr;
+  float* dc32 = nullptr;      // per direction: |u_x|/h, |u_y|/h, |u_z|/h, sum  [N][4]
+  double* dc64 = nullptr;
+  int* dsgn = nullptr;        // per direction: sign(u_x), sign(u_y), sign(u_z)   [N][4]
+  float* Sdiag32 = nullptr;   // S_mm                    [N]
+  float* fa[MAX_LEVELS] = {};     // CoeffNet fields per level [cells_l][C_l]
+  float* fainv[MAX_LEVELS] = {};
+};
+
 struct Operator {
   int dim = 2, nx = 0, ny = 0, nz = 1, ndir = 0, kernel = 0;
   int64_t cells = 0, n = 0;
@@ -101,21 +166,25 @@ struct Operator {
   int device = 0;
   std::vector<double> S;            // [N][N] host copy
   DevArena mem;
-  double* b64 = nullptr;            // [n]
-  float* sT32 = nullptr;            // sigma_T / eps            [cells]
-  float* sA32 = nullptr;            // eps sigma_a              [cells]
-  double* sT64 = nullptr;
-  double* sA64 = nullptr;
-  float* S32 = nullptr;             // [N][N]
-  double* S64 = nullptr;
-  float* dc32 = nullptr;            // per direction: |u_x|/h, |u_y|/h, |u_z|/h, sum  [N][4]
-  double* dc64 = nullptr;
-  int* dsgn = nullptr;              // per direction: sign(u_x), sign(u_y), sign(u_z)   [N][4]
-  float* Sdiag32 = nullptr;         // S_mm                    [N]
+  char* block = nullptr;            // device block holding every array below
+  size_t block_bytes = 0;
+  OpArrays a;                       // absolute addresses
   const Model* model = nullptr;     // CoeffNet fields were built for this model
-  std::vector<float*> fa, fainv;    // per level [cells_l][C_l]
+  int levels = 0, c0 = 0;           // of that model (0 without one)
   int64_t level_cells(int l) const;
   int level_dim(int l, int axis) const;
+  OpArrays relative() const;        // offsets from `block`
+  // operators with equal shape keys share the block layout
+  std::vector<int64_t> shape_key() const;
+};
+
+// What a launch addresses: the operator's shape, its arrays (absolute, or
+// offsets from each slot's operator block) and the slots it covers.
+struct Target {
+  const Operator* op;
+  OpArrays arr;
+  Slots sl;
+  static Target single(const Operator& o) { return Target{&o, o.a, Slots{}}; }
 };
 
 // ------------------------------------------------------------ launchers ---
@@ -126,8 +195,8 @@ struct ApplyGeom {
 
 // y = L x (res = 0) or y = b - L x (res = 1).  tin/tout: 0 float, 1 double;
 // compute precision follows `fp64`.
-void launch_apply(const Operator& op, const void* x, int tin, void* y, int tout, const double* b,
-                  bool fp64, hipStream_t s);
+void launch_apply(const Target& T, const void* x, int tin, void* y, int tout, const double* b, bool fp64,
+                  hipStream_t s);
 
 // MgNet pieces
 // STORE_T: out = conv and out2 = a^{-1} (.) conv (a level's first smoothing input)
@@ -135,6 +204,7 @@ enum ConvMode { CONV_STORE = 0, CONV_ACCUM = 1, CONV_STORE_T = 2, CONV_RESID_R =
 enum MfmaKind { MFMA_F32 = 0, MFMA_BF16 = 1 };
 
 struct ConvLaunch {
+  Slots sl;
   const float* in;
   int in_dim[3];
   int cin;
@@ -158,15 +228,15 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s);
 void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride);
 void convT4_setup(ConvLaunch& c, int dim, const int in_dim[3]);
 
-void launch_lift(const Operator& op, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
+void launch_lift(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
                  hipStream_t s);
-void launch_proj(const Operator& op, const Model& m, const double* v, const float* u0, float* z,
-                 hipStream_t s);
-void launch_scale_fields(const float* ainv, const float* f, float* t, int64_t count, hipStream_t s);
-void launch_fill_f32(float* p, float v, int64_t count, hipStream_t s);
-void launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
-void launch_cast_f64_f32(const double* src, float* dst, int64_t count, hipStream_t s);
-void launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s);
+void launch_proj(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s);
+void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count,
+                         hipStream_t s);
+void launch_fill_f32(const Slots& sl, float* p, float v, int64_t count, hipStream_t s);
+void launch_fill_f64(const Slots& sl, double* p, double v, int64_t count, hipStream_t s);
+void launch_cast_f64_f32(const Slots& sl, const double* src, float* dst, int64_t count, hipStream_t s);
+void launch_copy_f64(const Slots& sl, const double* src, double* dst, int64_t count, hipStream_t s);
 
 // CoeffNet (setup)
 void launch_coef_conv(const float* in, int cin, const int in_dim[3], const float* w, const float* b,
@@ -174,25 +244,32 @@ void launch_coef_conv(const float* in, int cin, const int in_dim[3], const float
 void launch_head(const float* F, int c, const float* w, const float* b, float* out, int C,
                  int64_t P, hipStream_t s);
 
-// Krylov (FP64)
+// Krylov (FP64).  Every array is per solve (workspace-relative under a slot
+// table).
 int krylov_blocks(int64_t n);
-void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part,
-                 int nblk, hipStream_t s);
-void launch_reduce(const double* part, int nblk, int nv, double* out, hipStream_t s);
+void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                 double* part, int nblk, hipStream_t s);
+void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double* out, hipStream_t s);
 // w <- w - V h; part: V^T w (first nv) and w.w (index nv)
-void launch_updots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                   double* part, int nblk, hipStream_t s);
+void launch_updots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
+                   int64_t n, double* part, int nblk, hipStream_t s);
 // w <- (w - V h) * f[0]
-void launch_update_scale(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                         const double* f, hipStream_t s);
-void launch_finish_step(const double* h1, const double* h2, int j, int k, double* H, double* cs, double* sn,
-                        double* g, const double* bnorm, double* stat, hipStream_t s);
-void launch_scale_by(double* w, const double* stat_inv, int64_t n, hipStream_t s);
-void launch_start_cycle(const double* partn, int nblk, double* g, int k, double* stat,
+void launch_update_scale(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
+                         int64_t n, const double* f, hipStream_t s);
+// Hessenberg column j, Givens, |g_{j+1}|/||b||; under a slot table it also
+// records the step in the slot's descriptor and ends the slot's cycle when
+// the estimate meets rtol, the step limit is reached or breakdown occurs.
+void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int j, int k, double* H,
+                        double* cs, double* sn, double* g, const double* bnorm, double* stat, hipStream_t s);
+void launch_scale_by(const Slots& sl, double* w, const double* stat_inv, int64_t n, hipStream_t s);
+void launch_start_cycle(const Slots& sl, const double* partn, int nblk, double* g, int k, double* stat,
                         hipStream_t s);
-void launch_lsq(const double* H, const double* g, int jj, int k, double* y, hipStream_t s);
-void launch_xupdate(double* x, const float* Z, int64_t ldz, const double* y, int jj, int64_t n,
-                    hipStream_t s);
+// jj: steps to combine; under a slot table each slot's own count is used
+void launch_lsq(const Slots& sl, const double* H, const double* g, int jj, int k, double* y, hipStream_t s);
+void launch_xupdate(const Slots& sl, double* x, const float* Z, int64_t ldz, const double* y, int jj,
+                    int64_t n, hipStream_t s);
+// rep[z][0..5] = beta, ||b||, jj, bad, live, occupied of every occupied slot
+void launch_report(const Slots& sl, const double* stat, const double* bn, double* rep, hipStream_t s);
 
 // kernel-class timing.  A sampled scope owns an event pair.  With ext =
 // true the enclosed launch goes through launch_k, and the dispatch itself
@@ -215,6 +292,8 @@ struct ProfScope {
 // launch of an enabled class is timed.
 bool& prof_capturing();
 bool& prof_force();
+double& prof_scale();  // work multiplier of timed launches (slots they cover)
+bool& prof_quiet();    // batch bookkeeping launches outside sampled steps are not timed
 int prof_stride();  // 0 when no class is being timed, else the smallest `every`
 
 template <typename F, typename... Args>
@@ -231,77 +310,110 @@ struct SolveLayout {
   int k;
   int64_t n;
   int nblk;
-  size_t off_V, off_Z, off_part1, off_part2, off_partn, off_small, off_mg, total;
+  size_t off_x, off_b, off_V, off_Z, off_part1, off_part2, off_partn, off_small, off_mg, total;
   size_t mg_bytes;
 };
+// Per-solve workspace: iterate x and right-hand side b (FP64), the Krylov
+// basis V (k + 1 FP64 vectors), the preconditioned vectors Z (k FP32
+// vectors), partial sums, the small dense state and the V-cycle levels.
 SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet);
 size_t precond_bytes(const Operator& op, const Model& m);
 void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o);
-void precond_apply(const Operator& op, const Model& m, int kind, const double* v, float* z,
-                   char* ws, hipStream_t s);
+void precond_apply(const Target& T, const Model& m, int kind, const double* v, float* z, char* ws,
+                   hipStream_t s);
 
+// Device tables of a batch: the slot descriptors and the per-slot report.
+size_t batch_table_bytes(int capacity);
 
-// One flexible GMRES solve as a resumable state machine.  Work is enqueued
-// on one stream; every host decision reads a small FP64 status block that
-// the device copies into pinned host memory, and at most two Arnoldi steps
-// are in flight ahead of the decision that may make the second one unused.
-// rte_solve drives a run with blocking waits; the server interleaves many
-// runs with non-blocking readiness checks.
-class SolveRun {
+// A group of flexible GMRES(k) solves of one shape (Saad's right-
+// preconditioned FGMRES with FP64 Arnoldi and an FP64 true residual at every
+// restart) advanced together on one stream.  Every launch covers all of the
+// group's slots; a solve that meets its tolerance inside a cycle stops
+// taking steps on the device (its slot turns not-live) without a host round
+// trip.  Solves join and leave at cycle boundaries, where the host reads one
+// report per slot.  At most two Arnoldi steps are in flight ahead of the
+// host's check for a cycle whose slots have all stopped.
+class Batch {
  public:
-  SolveRun(const Operator& op, const Model* m, const rte_solve_opts& o, char* ws, size_t ws_bytes,
-           double* x, hipStream_t s);
-  ~SolveRun();
-  SolveRun(const SolveRun&) = delete;
-  SolveRun& operator=(const SolveRun&) = delete;
-  void start();
-  bool ready();
+  struct Finished {
+    void* tag;
+    rte_status status;
+    rte_solve_stats stats;
+  };
+  Batch(const Operator& shape, const Model* m, int k, int precond, int capacity, char* tables, hipStream_t s);
+  ~Batch();
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
+  bool compatible(const Operator& op, const Model* m, int k, int precond) const;
+  bool full() const;      // every slot is taken or promised to a waiting solve
+  bool idle() const;      // nothing in flight, occupied or waiting
+  int members() const;    // occupied + waiting
+  // A solve to join at the next cycle boundary; ws holds solve_layout bytes.
+  void add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws, double* out, double t_start);
+  bool ready();           // the awaited device result has arrived (non-blocking)
   void wait();
-  void advance();
-  void step_body(int j, hipStream_t s);  // the kernels of Arnoldi step j
-  bool done() const { return phase_ == DONE; }
-  void fill_stats(rte_solve_stats* st) const;
-  rte_status status() const { return status_; }
+  void advance();         // take the next host decision
+  // Solves whose result has reached the caller's output buffer.
+  void collect(std::vector<Finished>& out);
+  // After a device error: waits for the stream and hands back every solve.
+  void abandon(rte_status st, std::vector<Finished>& out);
+  void step_body(int j, int zc, hipStream_t s);  // the launches of Arnoldi step j
 
  private:
-  enum Phase { BNORM, BETA, STEPS, FINAL, DONE };
-  enum { SLOT_A = 0, SLOT_B = 1, SLOT_R = 2 };
-  void enqueue_restart();
+  struct Member {
+    void* tag = nullptr;
+    const Operator* op = nullptr;
+    rte_solve_opts o{};
+    char* ws = nullptr;
+    double* out = nullptr;
+    double t0 = 0, ms = 0;
+    int slot = -1;
+    int iters = 0, restarts = 0, stall = 0;
+    double bnorm = -1, prev = 0, rel = 0;
+    rte_status status = RTE_EAGAIN;
+    hipEvent_t copied = nullptr;
+  };
+  enum Phase { IDLE, RESTART, STEPS };
+  void boundary();
+  void decide();
   void enqueue_step(int j);
-  void read_into(int slot, const double* dev, int count);
-  void finish(rte_status st);
+  void finish_member(Member* mb, rte_status st);
+  void upload(int slot);
+  void upload_all();
+  Slots slots(int gate) const { return Slots{tab_, zc_, gate}; }
 
-  const Operator& op_;
+  const Operator& shape_;
+  std::vector<int64_t> key_;
   const Model* m_;
-  rte_solve_opts o_;
-  double* x_;
-  hipStream_t s_;
-  SolveLayout lay_;
+  int k_, precond_, kind_, cap_;
   bool mg_;
-  int kind_;
-  const double* b_;
-  double *V_, *part1_, *part2_, *partn_;
-  float* Z_;
-  char* mgws_;
-  double *H_, *g_, *cs_, *sn_, *y_, *h1_, *h2_, *stat_, *bn_;
-  double* host_ = nullptr;   // pinned [3][8]
-  hipEvent_t ev_[3] = {nullptr, nullptr, nullptr};
-  Phase phase_ = BNORM;
-  int wait_slot_ = SLOT_R;
+  SolveLayout lay_;
+  OpArrays rel_;
+  SlotDesc* tab_;           // device [cap]
+  double* rep_;             // device [cap][8]
+  hipStream_t s_;
+  SlotDesc* hdesc_ = nullptr;   // pinned mirror of the host-set fields
+  SlotDesc* hsnap_ = nullptr;   // pinned [2][cap]: descriptors after steps
+  double* hrep_ = nullptr;      // pinned [cap][8]
+  hipEvent_t ev_step_[2] = {nullptr, nullptr};
+  hipEvent_t ev_rep_ = nullptr;
+  std::vector<std::unique_ptr<Member>> slot_;  // occupant per slot
+  std::vector<std::unique_ptr<Member>> waiting_, draining_;
+  Phase phase_ = IDLE;
+  int zc_ = 0;                  // slots covered by the launches of this cycle
+  int nlive_ = 0;               // live slots at the last host check (timer accounting)
   int j_wait_ = 0, j_enq_ = 0;
-  int iters_ = 0, restarts_ = 0, stall_ = 0;
-  double bnorm_ = 0, prev_ = 0, rel_ = 0;
-  rte_status status_ = RTE_ENOCONV;
-  double t0_ = 0, ms_ = 0;
   bool graphs_ = true;
-  std::vector<hipGraphExec_t>* gcache_ = nullptr;  // per-step graphs for this workspace
+  std::vector<hipGraphExec_t>* gcache_ = nullptr;
 };
 
-// Graphs of Arnoldi steps, keyed by everything their kernel arguments hold;
-// dropped when the operator they reference is freed.
-std::vector<hipGraphExec_t>* step_graphs(const Operator* op, const Model* m, int precond, const char* ws,
-                                         const double* x, const double* b, int k);
-void drop_step_graphs(const Operator* op);
+// Arnoldi-step graphs are keyed by everything their kernel arguments hold:
+// the slot table, the model, the preconditioner, the restart length, the
+// operator shape and the number of slots covered.  Freeing a model drops
+// the graphs that reference its weights.
+std::vector<hipGraphExec_t>* step_graphs(const void* tab, const Model* m, int precond, int k,
+                                         const std::vector<int64_t>& shape, int zc);
+void drop_step_graphs(const Model* m);
 
 }  // namespace rte
 

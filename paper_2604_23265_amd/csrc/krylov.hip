@@ -68,9 +68,14 @@ __device__ inline void block_store(double* acc, int cnt, double* __restrict__ pa
 
 // part[blk][i] = sum over the block's chunk of V_i . w, i < nv.
 template <int NV>
-__global__ __launch_bounds__(KT) void dots_kernel(const double* __restrict__ V, int64_t ldv, int nv,
+__global__ __launch_bounds__(KT) void dots_kernel(Slots sl, const double* __restrict__ V, int64_t ldv, int nv,
                                                   const double* __restrict__ w, int64_t n,
                                                   double* __restrict__ part, int nblk) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  V = at(V, bs.ws);
+  w = at(w, bs.ws);
+  part = at(part, bs.ws);
   __shared__ double red[KT / 64];
   int64_t beg, end;
   chunk_of(n, nblk, beg, end);
@@ -93,9 +98,15 @@ __global__ __launch_bounds__(KT) void dots_kernel(const double* __restrict__ V, 
 // stays in registers between the two uses; without it (the widest budget,
 // which would not fit) the column is loaded again, from cache.
 template <int NV, bool HOLD>
-__global__ __launch_bounds__(KT) void updots_kernel(const double* __restrict__ V, int64_t ldv, int nv,
-                                                    const double* __restrict__ h, double* __restrict__ w,
+__global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __restrict__ V, int64_t ldv,
+                                                    int nv, const double* __restrict__ h, double* __restrict__ w,
                                                     int64_t n, double* __restrict__ part, int nblk) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  V = at(V, bs.ws);
+  h = at(h, bs.ws);
+  w = at(w, bs.ws);
+  part = at(part, bs.ws);
   __shared__ double red[KT / 64];
   __shared__ double hs[NV];
   if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
@@ -132,9 +143,16 @@ __global__ __launch_bounds__(KT) void updots_kernel(const double* __restrict__ V
 
 // Second correction and normalisation: w = (w - sum_i h_i V_i) * f[0].
 template <int NV>
-__global__ __launch_bounds__(KT) void update_scale_kernel(const double* __restrict__ V, int64_t ldv, int nv,
-                                                          const double* __restrict__ h, double* __restrict__ w,
-                                                          int64_t n, const double* __restrict__ f) {
+__global__ __launch_bounds__(KT) void update_scale_kernel(Slots sl, const double* __restrict__ V, int64_t ldv,
+                                                          int nv, const double* __restrict__ h,
+                                                          double* __restrict__ w, int64_t n,
+                                                          const double* __restrict__ f) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  V = at(V, bs.ws);
+  h = at(h, bs.ws);
+  w = at(w, bs.ws);
+  f = at(f, bs.ws);
   __shared__ double hs[NV];
   if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
   __syncthreads();
@@ -151,8 +169,12 @@ __global__ __launch_bounds__(KT) void update_scale_kernel(const double* __restri
 }
 
 // out[i] = sum_blk part[blk][i], one block per i, fixed order.
-__global__ __launch_bounds__(KT) void reduce_kernel(const double* __restrict__ part, int nblk,
+__global__ __launch_bounds__(KT) void reduce_kernel(Slots sl, const double* __restrict__ part, int nblk,
                                                     double* __restrict__ out) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  part = at(part, bs.ws);
+  out = at(out, bs.ws);
   __shared__ double red[KT / 64];
   const int i = blockIdx.x;
   double s = 0;
@@ -169,11 +191,21 @@ __global__ __launch_bounds__(KT) void reduce_kernel(const double* __restrict__ p
 // 1/||w2||}.  h2[j + 1] holds ||w1||^2.  flags: 1 = non-finite value,
 // 2 = ||w2|| negligible (the Krylov space is invariant: the least-squares
 // solution is exact).
-__global__ void finish_kernel(const double* __restrict__ h1, const double* __restrict__ h2, int j, int k,
-                              double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+__global__ void finish_kernel(Slots sl, const double* __restrict__ h1, const double* __restrict__ h2, int j,
+                              int k, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
                               double* __restrict__ g, const double* __restrict__ bnorm,
                               double* __restrict__ stat) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  h1 = at(h1, bs.ws);
+  h2 = at(h2, bs.ws);
+  H = at(H, bs.ws);
+  cs = at(cs, bs.ws);
+  sn = at(sn, bs.ws);
+  g = at(g, bs.ws);
+  bnorm = at(bnorm, bs.ws);
+  stat = at(stat, bs.ws);
   double* col = H + int64_t(j) * (k + 1);
   double cmax = 0, h2sq = 0;
   for (int i = 0; i <= j; ++i) {
@@ -210,12 +242,32 @@ __global__ void finish_kernel(const double* __restrict__ h1, const double* __res
   stat[1] = double(flags);
   stat[2] = hn;
   stat[3] = hn > 0 ? 1.0 / hn : 0.0;
-  if (!isfinite(stat[0])) stat[1] = double(flags | 1);
+  if (!isfinite(stat[0])) {
+    flags |= 1;
+    stat[1] = double(flags);
+  }
+  if (sl.tab) {
+    // the slot's own stopping test: a non-finite value discards the cycle
+    SlotDesc* d = sl.tab + blockIdx.z;
+    if (flags & 1) {
+      d->bad = 1;
+      d->jj = 0;
+      d->live = 0;
+    } else {
+      d->jj = j + 1;
+      if ((flags & 2) || stat[0] <= d->rtol || j + 1 >= d->limit) d->live = 0;
+    }
+  }
 }
 
 // beta = ||r|| from partial sums; g = beta e_1; stat[3] = 1/beta, stat[4] = beta.
-__global__ __launch_bounds__(KT) void start_cycle_kernel(const double* __restrict__ partn, int nblk,
+__global__ __launch_bounds__(KT) void start_cycle_kernel(Slots sl, const double* __restrict__ partn, int nblk,
                                                          double* __restrict__ g, int k, double* __restrict__ stat) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  partn = at(partn, bs.ws);
+  if (g) g = at(g, bs.ws);
+  stat = at(stat, bs.ws);
   __shared__ double red[KT / 64];
   double s = 0;
   for (int b = threadIdx.x; b < nblk; b += KT) s += partn[int64_t(b) * HMAX];
@@ -231,16 +283,26 @@ __global__ __launch_bounds__(KT) void start_cycle_kernel(const double* __restric
   stat[4] = beta;
 }
 
-__global__ void scale_kernel(double* __restrict__ w, const double* __restrict__ f, int64_t n) {
+__global__ void scale_kernel(Slots sl, double* __restrict__ w, const double* __restrict__ f, int64_t n) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  w = at(w, bs.ws);
+  f = at(f, bs.ws);
   const double a = f[0];
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) w[i] *= a;
 }
 
 // Back substitution on the rotated (upper-triangular) Hessenberg matrix.
-__global__ void lsq_kernel(const double* __restrict__ H, const double* __restrict__ g, int jj, int k,
+__global__ void lsq_kernel(Slots sl, const double* __restrict__ H, const double* __restrict__ g, int jj, int k,
                            double* __restrict__ y) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  if (sl.tab) jj = sl.tab[blockIdx.z].jj;
+  H = at(H, bs.ws);
+  g = at(g, bs.ws);
+  y = at(y, bs.ws);
   for (int i = jj - 1; i >= 0; --i) {
     double s = g[i];
     for (int l = i + 1; l < jj; ++l) s -= H[int64_t(l) * (k + 1) + i] * y[l];
@@ -249,9 +311,16 @@ __global__ void lsq_kernel(const double* __restrict__ H, const double* __restric
 }
 
 // x += sum_i y_i Z_i (Z stored in FP32).
-__global__ __launch_bounds__(KT) void xupdate_kernel(double* __restrict__ x, const float* __restrict__ Z,
-                                                     int64_t ldz, const double* __restrict__ y, int jj,
-                                                     int64_t n) {
+__global__ __launch_bounds__(KT) void xupdate_kernel(Slots sl, double* __restrict__ x,
+                                                     const float* __restrict__ Z, int64_t ldz,
+                                                     const double* __restrict__ y, int jj, int64_t n) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  if (sl.tab) jj = sl.tab[blockIdx.z].jj;
+  if (jj == 0) return;
+  x = at(x, bs.ws);
+  Z = at(Z, bs.ws);
+  y = at(y, bs.ws);
   __shared__ double ys[HMAX];
   if (threadIdx.x < jj) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
@@ -260,6 +329,26 @@ __global__ __launch_bounds__(KT) void xupdate_kernel(double* __restrict__ x, con
     double acc = x[e];
     for (int i = 0; i < jj; ++i) acc += ys[i] * double(Z[int64_t(i) * ldz + e]);
     x[e] = acc;
+  }
+}
+
+// One report row per occupied slot, gathered for a single copy to the host.
+__global__ void report_kernel(Slots sl, const double* __restrict__ stat, const double* __restrict__ bn,
+                              double* __restrict__ rep) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  stat = at(stat, bs.ws);
+  bn = at(bn, bs.ws);
+  double* r = rep + 8 * int64_t(blockIdx.z);
+  r[0] = stat[4];
+  r[1] = bn[0];
+  if (sl.tab) {
+    const SlotDesc* d = sl.tab + blockIdx.z;
+    r[2] = double(d->jj);
+    r[3] = double(d->bad);
+    r[4] = double(d->live);
+    r[5] = double(d->occupied);
   }
 }
 
@@ -283,94 +372,101 @@ int krylov_blocks(int64_t n) {
 
 namespace {
 template <int NV>
-void dots_go(dim3 g, hipStream_t s, const ProfScope& ps, const double* V, int64_t ldv, int nv, const double* w,
-             int64_t n, double* part, int nblk) {
-  launch_k(dots_kernel<NV>, g, dim3(KT), 0, s, ps, V, ldv, nv, w, n, part, nblk);
+void dots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const double* V, int64_t ldv, int nv,
+             const double* w, int64_t n, double* part, int nblk) {
+  launch_k(dots_kernel<NV>, g, dim3(KT), 0, s, ps, sl, V, ldv, nv, w, n, part, nblk);
 }
 template <int NV>
-void updots_go(dim3 g, hipStream_t s, const ProfScope& ps, const double* V, int64_t ldv, int nv, const double* h,
-               double* w, int64_t n, double* part, int nblk) {
-  launch_k(updots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, part, nblk);
+void updots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const double* V, int64_t ldv, int nv,
+               const double* h, double* w, int64_t n, double* part, int nblk) {
+  launch_k(updots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
 }
 template <int NV>
-void upscale_go(dim3 g, hipStream_t s, const ProfScope& ps, const double* V, int64_t ldv, int nv, const double* h,
-                double* w, int64_t n, const double* f) {
-  launch_k(update_scale_kernel<NV>, g, dim3(KT), 0, s, ps, V, ldv, nv, h, w, n, f);
+void upscale_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const double* V, int64_t ldv,
+                int nv, const double* h, double* w, int64_t n, const double* f) {
+  launch_k(update_scale_kernel<NV>, g, dim3(KT), 0, s, ps, sl, V, ldv, nv, h, w, n, f);
 }
+dim3 z3(unsigned x, const Slots& sl) { return dim3(x, 1, unsigned(sl.count)); }
 }  // namespace
 
-void launch_dots(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part, int nblk,
-                 hipStream_t s) {
+void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part,
+                 int nblk, hipStream_t s) {
   RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 1);
-  const dim3 g(nblk);
-  if (nv <= 8) dots_go<8>(g, s, ps, V, ldv, nv, w, n, part, nblk);
-  else if (nv <= 16) dots_go<16>(g, s, ps, V, ldv, nv, w, n, part, nblk);
-  else if (nv <= 32) dots_go<32>(g, s, ps, V, ldv, nv, w, n, part, nblk);
-  else dots_go<64>(g, s, ps, V, ldv, nv, w, n, part, nblk);
+  const dim3 g = z3(unsigned(nblk), sl);
+  if (nv <= 8) dots_go<8>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
+  else if (nv <= 16) dots_go<16>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
+  else if (nv <= 32) dots_go<32>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
+  else dots_go<64>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_reduce(const double* part, int nblk, int nv, double* out, hipStream_t s) {
+void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double* out, hipStream_t s) {
   ProfScope ps(RTE_K_ORTH, s, true);
-  launch_k(reduce_kernel, dim3(nv), dim3(KT), 0, s, ps, part, nblk, out);
+  launch_k(reduce_kernel, z3(unsigned(nv), sl), dim3(KT), 0, s, ps, sl, part, nblk, out);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_updots(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double* part,
-                   int nblk, hipStream_t s) {
+void launch_updots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
+                   double* part, int nblk, hipStream_t s) {
   RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once
-  const dim3 g(nblk);
-  if (nv <= 8) updots_go<8>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
-  else if (nv <= 16) updots_go<16>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
-  else if (nv <= 32) updots_go<32>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
-  else updots_go<64>(g, s, ps, V, ldv, nv, h, w, n, part, nblk);
+  const dim3 g = z3(unsigned(nblk), sl);
+  if (nv <= 8) updots_go<8>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
+  else if (nv <= 16) updots_go<16>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
+  else if (nv <= 32) updots_go<32>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
+  else updots_go<64>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_update_scale(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
-                         const double* f, hipStream_t s) {
+void launch_update_scale(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
+                         int64_t n, const double* f, hipStream_t s) {
   RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 8.0 * double(n) * (nv + 2);
-  const dim3 g(ew_grid(n));
-  if (nv <= 8) upscale_go<8>(g, s, ps, V, ldv, nv, h, w, n, f);
-  else if (nv <= 16) upscale_go<16>(g, s, ps, V, ldv, nv, h, w, n, f);
-  else if (nv <= 32) upscale_go<32>(g, s, ps, V, ldv, nv, h, w, n, f);
-  else upscale_go<64>(g, s, ps, V, ldv, nv, h, w, n, f);
+  const dim3 g = z3(ew_grid(n), sl);
+  if (nv <= 8) upscale_go<8>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
+  else if (nv <= 16) upscale_go<16>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
+  else if (nv <= 32) upscale_go<32>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
+  else upscale_go<64>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_finish_step(const double* h1, const double* h2, int j, int k, double* H, double* cs, double* sn,
-                        double* g, const double* bnorm, double* stat, hipStream_t s) {
+void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int j, int k, double* H, double* cs,
+                        double* sn, double* g, const double* bnorm, double* stat, hipStream_t s) {
   ProfScope ps(RTE_K_ORTH, s, true);
-  launch_k(finish_kernel, dim3(1), dim3(64), 0, s, ps, h1, h2, j, k, H, cs, sn, g, bnorm, stat);
+  launch_k(finish_kernel, z3(1, sl), dim3(64), 0, s, ps, sl, h1, h2, j, k, H, cs, sn, g, bnorm, stat);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_scale_by(double* w, const double* stat_inv, int64_t n, hipStream_t s) {
+void launch_scale_by(const Slots& sl, double* w, const double* stat_inv, int64_t n, hipStream_t s) {
   ProfScope ps(RTE_K_ORTH, s, true);
   ps.work = 16.0 * double(n);
-  launch_k(scale_kernel, dim3(ew_grid(n)), dim3(KT), 0, s, ps, w, stat_inv, n);
+  launch_k(scale_kernel, z3(ew_grid(n), sl), dim3(KT), 0, s, ps, sl, w, stat_inv, n);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_start_cycle(const double* partn, int nblk, double* g, int k, double* stat, hipStream_t s) {
-  hipLaunchKernelGGL(start_cycle_kernel, dim3(1), dim3(KT), 0, s, partn, nblk, g, k, stat);
+void launch_start_cycle(const Slots& sl, const double* partn, int nblk, double* g, int k, double* stat,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(start_cycle_kernel, z3(1, sl), dim3(KT), 0, s, sl, partn, nblk, g, k, stat);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_lsq(const double* H, const double* g, int jj, int k, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(64), 0, s, H, g, jj, k, y);
+void launch_lsq(const Slots& sl, const double* H, const double* g, int jj, int k, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(lsq_kernel, z3(1, sl), dim3(64), 0, s, sl, H, g, jj, k, y);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_xupdate(double* x, const float* Z, int64_t ldz, const double* y, int jj, int64_t n,
+void launch_xupdate(const Slots& sl, double* x, const float* Z, int64_t ldz, const double* y, int jj, int64_t n,
                     hipStream_t s) {
-  hipLaunchKernelGGL(xupdate_kernel, dim3(ew_grid(n)), dim3(KT), 0, s, x, Z, ldz, y, jj, n);
+  hipLaunchKernelGGL(xupdate_kernel, z3(ew_grid(n), sl), dim3(KT), 0, s, sl, x, Z, ldz, y, jj, n);
+  RTE_HIP(hipGetLastError());
+}
+
+void launch_report(const Slots& sl, const double* stat, const double* bn, double* rep, hipStream_t s) {
+  hipLaunchKernelGGL(report_kernel, z3(1, sl), dim3(64), 0, s, sl, stat, bn, rep);
   RTE_HIP(hipGetLastError());
 }
 

@@ -41,6 +41,7 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 struct ConvArgs {
+  Slots sl;
   const float* in;
   const void* w;
   float* out;
@@ -129,7 +130,20 @@ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > 
 // DEPTH k-steps whose operand loads are all issued before the batch's MFMAs;
 // the last (< DEPTH) steps run singly.
 template <int KIND, int NT, bool KSPLIT, int MODE>
-__global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A) {
+__global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A0) {
+  // grid z = slot * classes + parity class of the transposed convolution
+  const int nclass = A0.transposed ? (1 << A0.dim) : 1;
+  const int slot_z = int(blockIdx.z) / nclass;
+  const int cls = int(blockIdx.z) - slot_z * nclass;
+  SlotBase bs;
+  if (!slot_open(A0.sl, slot_z, bs)) return;
+  ConvArgs A = A0;
+  A.in = at(A0.in, bs.ws);
+  A.out = at(A0.out, bs.ws);
+  A.out2 = at(A0.out2, bs.ws);
+  A.f = at(A0.f, bs.ws);
+  A.a = at(A0.a, bs.op);
+  A.ainv = at(A0.ainv, bs.op);
   constexpr int KPL = KIND == 2 ? 8 : 4;  // channels per lane per k-step
   constexpr int KC = 4 * KPL;             // channels per k-step
   const int lane = threadIdx.x & 63;
@@ -137,7 +151,6 @@ __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A) {
   // k-step bookkeeping (tap, channel chunk, tap offsets) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int grp = lane >> 4, li = lane & 15;
-  const int cls = blockIdx.z;
   // row indices fit in 32 bits (pixels per level < 2^31)
   const int gx = A.g_dim[0], gy = A.g_dim[1];
   const int gm = gx * gy * A.g_dim[2];
@@ -330,7 +343,16 @@ __global__ __launch_bounds__(256) void conv_kernel(const ConvArgs A) {
 constexpr int LDS_PIX_WORDS = 20;  // 32 BF16 channels (16 words) + 4 words of padding
 
 template <int NT, bool KSPLIT, int MODE>
-__global__ __launch_bounds__(256) void conv3_lds_kernel(const ConvArgs A) {
+__global__ __launch_bounds__(256) void conv3_lds_kernel(const ConvArgs A0) {
+  SlotBase bs;
+  if (!slot_open(A0.sl, int(blockIdx.z), bs)) return;
+  ConvArgs A = A0;
+  A.in = at(A0.in, bs.ws);
+  A.out = at(A0.out, bs.ws);
+  A.out2 = at(A0.out2, bs.ws);
+  A.f = at(A0.f, bs.ws);
+  A.a = at(A0.a, bs.op);
+  A.ainv = at(A0.ainv, bs.op);
   constexpr int ROWS = KSPLIT ? 16 : 64;
   constexpr int KC = 32;
   extern __shared__ uint32_t tile[];
@@ -484,6 +506,202 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const ConvArgs A) {
   }
 }
 
+// Tiled 2D BF16 convolution: one block computes an 8x8 patch of the
+// virtual grid for 32 output channels.  Per 32-channel input chunk the
+// block stages the patch's input footprint (rounded to BF16) and the
+// chunk's weights for its 32 output channels in LDS, both with an 80-byte
+// row stride; while the chunk's MFMAs run, the next chunk's global loads
+// are already in flight in registers.  Wave w owns patch rows 2w and 2w + 1
+// (16 pixels) and both 16-channel column tiles.
+//
+// CK = 0: 3x3 stride 1; CK = 1: 3x3 stride 2 (restriction); CK = 2: the
+// 4x4 stride-2 transposed convolution, one parity class per grid-z index.
+// Every output element accumulates its chunks in order and, within a chunk,
+// its taps in order -- the same chain whatever the launch shape, so results
+// do not depend on how many solves share the launch.
+constexpr int TILE_ROW_WORDS = 20;  // 32 BF16 (16 words) + 4 words of padding
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+template <int CK>
+struct TileGeom {
+  static constexpr int NTAP = CK == 2 ? 4 : 9;
+  static constexpr int S = CK == 1 ? 2 : 1;                       // input step per virtual pixel
+  static constexpr int FP = CK == 0 ? 10 : (CK == 1 ? 17 : 9);    // footprint extent per axis
+  static constexpr int FPIX = FP * FP;
+  static constexpr int NCLS = CK == 2 ? 4 : 1;
+  static constexpr int IN_PIECES = (FPIX * 8 + 255) / 256;        // float4 loads per thread
+  static constexpr int W_PIECES = (NTAP * 128 + 255) / 256;       // 16-byte weight loads per thread
+};
+
+template <int CK, int MODE>
+__global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
+  using G = TileGeom<CK>;
+  const int slot_z = int(blockIdx.z) / G::NCLS;
+  const int cls = int(blockIdx.z) - slot_z * G::NCLS;
+  SlotBase bs;
+  if (!slot_open(A0.sl, slot_z, bs)) return;
+  const float* __restrict__ in = at(A0.in, bs.ws);
+  float* __restrict__ out = at(A0.out, bs.ws);
+  float* __restrict__ out2 = at(A0.out2, bs.ws);
+  const float* __restrict__ fF = at(A0.f, bs.ws);
+  const float* __restrict__ fA = at(A0.a, bs.op);
+  const float* __restrict__ fI = at(A0.ainv, bs.op);
+  const uint16_t* __restrict__ W = static_cast<const uint16_t*>(A0.w);
+
+  __shared__ uint32_t xin[G::FPIX * TILE_ROW_WORDS];
+  __shared__ uint32_t wsm[G::NTAP * 32 * TILE_ROW_WORDS];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int grp = lane >> 4, li = lane & 15;
+  const int gx = A0.g_dim[0];
+  const int npx = gx >> 3;
+  const int patch = blockIdx.x;
+  const int py0 = (patch / npx) * 8, px0 = (patch - (patch / npx) * npx) * 8;
+  const int co0 = blockIdx.y * 32;
+  const int W0 = A0.in_dim[0], W1 = A0.in_dim[1];
+  const int cin = A0.cin, cout = A0.cout;
+  const int nchunk = cin >> 5;
+  const int px_par = cls & 1, py_par = (cls >> 1) & 1;
+  // input coordinates of footprint entry (0, 0)
+  const int ox0 = CK == 1 ? 2 * px0 - 1 : (CK == 2 ? px0 - 1 + px_par : px0 - 1);
+  const int oy0 = CK == 1 ? 2 * py0 - 1 : (CK == 2 ? py0 - 1 + py_par : py0 - 1);
+
+  // ---- epilogue operands (independent of the reduction): request them now
+  const int ox_dim = A0.out_dim[0];
+  size_t oidx[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pr = 4 * grp + j;  // D row -> patch pixel (pr % 8, 2 wave + pr / 8)
+    const int vx = px0 + (pr & 7), vy = py0 + 2 * wave + (pr >> 3);
+    const int ox = CK == 2 ? 2 * vx + px_par : vx;
+    const int oy = CK == 2 ? 2 * vy + py_par : vy;
+    oidx[j] = size_t(oy * ox_dim + ox) * cout + co0 + li;
+  }
+  constexpr bool NEED_F = MODE == CONV_RESID_R || MODE == CONV_RESID_T;
+  constexpr bool NEED_I = MODE == CONV_RESID_T || MODE == CONV_STORE_T;
+  constexpr bool NEED_U = MODE == CONV_ACCUM || NEED_F;
+  float ef[8], ea[8], ei[8], eu[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int q = j * 2 + ni;
+      const size_t o = oidx[j] + ni * 16;
+      if (NEED_F) {
+        ef[q] = fF[o];
+        ea[q] = fA[o];
+      }
+      if (NEED_I) ei[q] = fI[o];
+      if (NEED_U) eu[q] = MODE == CONV_ACCUM ? out[o] : in[o];
+    }
+
+  // ---- staging: chunk c's footprint and weights, loaded into registers
+  v4f rin[G::IN_PIECES];
+  v4u rw[G::W_PIECES];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < G::IN_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      const int pix = idx >> 3, q4 = idx & 7;
+      const int fy = pix / G::FP, fx = pix - (pix / G::FP) * G::FP;
+      const int ix = ox0 + fx, iy = oy0 + fy;
+      const bool ok = idx < G::FPIX * 8 && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1);
+      const int ixc = clampi(ix, 0, W0 - 1), iyc = clampi(iy, 0, W1 - 1);
+      const v4f v = *reinterpret_cast<const v4f*>(in + size_t(iyc * W0 + ixc) * cin + c * 32 + q4 * 4);
+      rin[i] = ok ? v : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < G::W_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      const int idc = idx < G::NTAP * 128 ? idx : G::NTAP * 128 - 1;
+      const int t = idc >> 7, rem = idc & 127, co = rem >> 2, q8 = rem & 3;
+      rw[i] = *reinterpret_cast<const v4u*>(
+          W + (size_t((cls * G::NTAP + t) * cout + co0 + co)) * cin + c * 32 + q8 * 8);
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < G::IN_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      if (idx < G::FPIX * 8) {
+        const int pix = idx >> 3, q4 = idx & 7;
+        const v4f v = rin[i];
+        const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
+        const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
+        *reinterpret_cast<uint2*>(xin + pix * TILE_ROW_WORDS + q4 * 2) = make_uint2(lo, hi);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < G::W_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      if (idx < G::NTAP * 128) {
+        const int t = idx >> 7, rem = idx & 127, co = rem >> 2, q8 = rem & 3;
+        *reinterpret_cast<v4u*>(wsm + (t * 32 + co) * TILE_ROW_WORDS + q8 * 4) = rw[i];
+      }
+    }
+  };
+
+  // this lane's A pixel: patch (li % 8, 2 wave + li / 8)
+  const int lx = li & 7, ly = 2 * wave + (li >> 3);
+  v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+  load_chunk(0);
+  for (int c = 0; c < nchunk; ++c) {
+    if (c > 0) __syncthreads();  // the previous chunk's reads are done
+    store_chunk();
+    __syncthreads();
+    if (c + 1 < nchunk) load_chunk(c + 1);  // in flight during this chunk's MFMAs
+#pragma unroll
+    for (int t = 0; t < G::NTAP; ++t) {
+      // tap offsets (the tables of taps.h, written out for two axes): a 3x3
+      // tap t reads (t % 3 - 1, t / 3 - 1); transposed-conv tap t of parity
+      // class (px, py) reads (px - t % 2, py - t / 2)
+      const int dx = CK == 2 ? px_par - (t & 1) : t % 3 - 1;
+      const int dy = CK == 2 ? py_par - (t >> 1) : t / 3 - 1;
+      const int fx = G::S * (px0 + lx) + dx - ox0;
+      const int fy = G::S * (py0 + ly) + dy - oy0;
+      const v8bf av = *reinterpret_cast<const v8bf*>(xin + (fy * G::FP + fx) * TILE_ROW_WORDS + grp * 4);
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + (t * 32 + ni * 16 + li) * TILE_ROW_WORDS + grp * 4);
+        acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int q = j * 2 + ni;
+      const size_t o = oidx[j] + ni * 16;
+      const float v = acc[ni][j];
+      if constexpr (MODE == CONV_STORE) {
+        out[o] = v;
+      } else if constexpr (MODE == CONV_ACCUM) {
+        out[o] = eu[q] + v;
+      } else if constexpr (MODE == CONV_STORE_T) {
+        out[o] = v;
+        out2[o] = ei[q] * v;
+      } else if constexpr (MODE == CONV_RESID_R) {
+        out[o] = ef[q] - v - ea[q] * eu[q];
+      } else {
+        out[o] = ei[q] * (ef[q] - v - ea[q] * eu[q]);
+      }
+    }
+}
+
+template <int CK>
+void tile_dispatch(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, const ProfScope& ps) {
+  switch (mode) {
+    case CONV_STORE: launch_k(conv_tile_kernel<CK, CONV_STORE>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_ACCUM: launch_k(conv_tile_kernel<CK, CONV_ACCUM>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_STORE_T: launch_k(conv_tile_kernel<CK, CONV_STORE_T>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_RESID_R: launch_k(conv_tile_kernel<CK, CONV_RESID_R>, grid, dim3(256), 0, s, ps, a); break;
+    default: launch_k(conv_tile_kernel<CK, CONV_RESID_T>, grid, dim3(256), 0, s, ps, a); break;
+  }
+}
+
 template <bool KSPLIT, int MODE>
 void lds_dispatch3(const ConvArgs& a, dim3 grid, int nt, size_t lds, hipStream_t s, const ProfScope& ps) {
   switch (nt) {
@@ -546,11 +764,24 @@ constexpr int PT = 16;  // pixels per block of the lift / projection kernels
 // t0 is given also t0 = ainv0 (.) f0 (the first smoothing step's input).
 // LDS holds v~ as [m][pixel] and W_in transposed as [m][c], so the
 // channel-fastest thread order reads consecutive banks.
-__global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ v, const float* __restrict__ sT,
-                                                   const float* __restrict__ sA, const float* __restrict__ dc,
-                                                   const float* __restrict__ Sd, const float* __restrict__ Win,
-                                                   float* __restrict__ f0, const float* __restrict__ ainv,
-                                                   float* __restrict__ t0, int N, int C0, int64_t P) {
+__global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __restrict__ v,
+                                                   const float* __restrict__ sT, const float* __restrict__ sA,
+                                                   const float* __restrict__ dc, const float* __restrict__ Sd,
+                                                   const float* __restrict__ Win, float* __restrict__ f0,
+                                                   const float* __restrict__ ainv, float* __restrict__ t0, int N,
+                                                   int C0, int64_t P) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  v = at(v, bs.ws);
+  f0 = at(f0, bs.ws);
+  if (t0) {
+    t0 = at(t0, bs.ws);
+    ainv = at(ainv, bs.op);
+  }
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  dc = at(dc, bs.op);
+  Sd = at(Sd, bs.op);
   extern __shared__ float sm[];
   float* vt = sm;               // [N][PT]
   float* wt = sm + N * PT;      // [N][C0]
@@ -588,11 +819,20 @@ __global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ v,
 // thread t owns pixel t % 16 and directions t / 16 + 16 q; u0 rows are
 // padded in LDS (conflict-free) and v is requested before the sum.
 template <int DPT>
-__global__ __launch_bounds__(256) void proj_kernel(const double* __restrict__ v, const float* __restrict__ u0,
-                                                   const float* __restrict__ sT, const float* __restrict__ sA,
-                                                   const float* __restrict__ dc, const float* __restrict__ Sd,
-                                                   const float* __restrict__ Wout, float sc, float* __restrict__ z,
-                                                   int N, int C0, int64_t P) {
+__global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __restrict__ v,
+                                                   const float* __restrict__ u0, const float* __restrict__ sT,
+                                                   const float* __restrict__ sA, const float* __restrict__ dc,
+                                                   const float* __restrict__ Sd, const float* __restrict__ Wout,
+                                                   float sc, float* __restrict__ z, int N, int C0, int64_t P) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  v = at(v, bs.ws);
+  u0 = at(u0, bs.ws);
+  z = at(z, bs.ws);
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  dc = at(dc, bs.op);
+  Sd = at(Sd, bs.op);
   extern __shared__ float sm[];
   const int ld = C0 + 1;
   float* us = sm;              // [PT][C0 + 1]
@@ -638,24 +878,40 @@ __global__ __launch_bounds__(256) void proj_kernel(const double* __restrict__ v,
   }
 }
 
-__global__ void scale_fields_kernel(const float* __restrict__ ainv, const float* __restrict__ f,
+__global__ void scale_fields_kernel(Slots sl, const float* __restrict__ ainv, const float* __restrict__ f,
                                     float* __restrict__ t, int64_t n) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  ainv = at(ainv, bs.op);
+  f = at(f, bs.ws);
+  t = at(t, bs.ws);
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) t[i] = ainv[i] * f[i];
 }
 
 template <class T>
-__global__ void fill_kernel(T* p, T v, int64_t n) {
+__global__ void fill_kernel(Slots sl, T* p, T v, int64_t n) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  p = at(p, bs.ws);
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
 }
 
-__global__ void cast_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+__global__ void cast_kernel(Slots sl, const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  a = at(a, bs.ws);
+  b = at(b, bs.ws);
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) b[i] = float(a[i]);
 }
 
-__global__ void copy64_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+__global__ void copy64_kernel(Slots sl, const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  a = at(a, bs.ws);
+  b = at(b, bs.ws);
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) b[i] = a[i];
 }
@@ -752,6 +1008,7 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   RTE_REQUIRE(c.cin % 16 == 0 && c.cout % 16 == 0, RTE_EINVAL, "conv channels must be multiples of 16");
   RTE_REQUIRE(c.nclass * c.ntap <= 64 && c.nclass <= 8, RTE_EINVAL, "conv tap table overflow");
   ConvArgs a;
+  a.sl = c.sl;
   a.in = c.in;
   a.out = c.out;
   a.out2 = c.out2;
@@ -797,7 +1054,7 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
     ksplit = nks >= 8;
   }
   dim3 grid(unsigned(ksplit ? row_units : (row_units + 3) / 4), unsigned(c.cout / (nt * 16)),
-            unsigned(c.nclass));
+            unsigned(c.nclass * c.sl.count));
   // The LDS-staged kernel covers 3x3 stride-1 2D convolutions with BF16
   // weights on grids whose width is a multiple of 16 (64-pixel blocks must
   // tile the grid: segments of one row, or whole rows of a narrow grid).
@@ -815,14 +1072,28 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
     const double extra[] = {0.0, 1.0, 2.0, 2.0, 3.0};  // STORE, ACCUM, STORE_T, RESID_R, RESID_T
     ps.bytes = 4.0 * in_el + wbytes + 4.0 * out_el * (1.0 + extra[c.mode]);
   }
-  if (lds_ok) {
+  // The tiled kernel covers every 2D BF16 convolution whose channel counts
+  // are multiples of 32 and whose virtual grid is a multiple of 8 per axis.
+  int ck = -1;
+  if (kind == MFMA_BF16 && c.dim == 2 && c.cin % 32 == 0 && c.cout % 32 == 0 && gxv % 8 == 0 && gyv % 8 == 0) {
+    if (c.ostride == 1 && c.cstride == 1 && c.ntap == 9) ck = 0;
+    else if (c.ostride == 1 && c.cstride == 2 && c.ntap == 9) ck = 1;
+    else if (c.ostride == 2 && c.nclass == 4 && c.ntap == 4) ck = 2;
+  }
+  if (ck >= 0) {
+    a.w = c.w->d16;
+    const dim3 gt(unsigned((gxv / 8) * (gyv / 8)), unsigned(c.cout / 32), unsigned(c.nclass * c.sl.count));
+    if (ck == 0) tile_dispatch<0>(a, gt, c.mode, s, ps);
+    else if (ck == 1) tile_dispatch<1>(a, gt, c.mode, s, ps);
+    else tile_dispatch<2>(a, gt, c.mode, s, ps);
+  } else if (lds_ok) {
     const int rows = ksplit ? 16 : 64;
     const int width = gxv >= rows ? rows : gxv;
     const int nrow = gxv >= rows ? 1 : rows / gxv;
     size_t lds = size_t(2) * (width + 2) * (nrow + 2) * LDS_PIX_WORDS * 4;
     if (ksplit) lds = std::max(lds, size_t(3) * nt * 4 * 64 * 4);
     a.w = c.w->d16;
-    const dim3 g2(unsigned((gm + rows - 1) / rows), grid.y, 1);
+    const dim3 g2(unsigned((gm + rows - 1) / rows), grid.y, unsigned(c.sl.count));
     if (ksplit)
       lds_dispatch2<true>(a, g2, nt, lds, s, ps);
     else
@@ -840,24 +1111,26 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   RTE_HIP(hipGetLastError());
 }
 
-void launch_lift(const Operator& op, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
+void launch_lift(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
                  hipStream_t s) {
+  const Operator& op = *T.op;
   const size_t lds = (size_t(op.ndir) * PT + size_t(m.c0) * op.ndir) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "lift tile does not fit in LDS");
-  hipLaunchKernelGGL(lift_kernel, dim3(unsigned((op.cells + PT - 1) / PT)), dim3(256), lds, s, v, op.sT32,
-                     op.sA32, op.dc32, op.Sdiag32, m.d_w_in, f0, ainv, t0, op.ndir, m.c0, op.cells);
+  const dim3 grid(unsigned((op.cells + PT - 1) / PT), 1, unsigned(T.sl.count));
+  hipLaunchKernelGGL(lift_kernel, grid, dim3(256), lds, s, T.sl, v, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+                     T.arr.Sdiag32, m.d_w_in, f0, ainv, t0, op.ndir, m.c0, op.cells);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_proj(const Operator& op, const Model& m, const double* v, const float* u0, float* z,
-                 hipStream_t s) {
+void launch_proj(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s) {
+  const Operator& op = *T.op;
   const size_t lds = (size_t(PT) * (m.c0 + 1) + size_t(op.ndir) * m.c0) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "projection tile does not fit in LDS");
-  const dim3 grid(unsigned((op.cells + PT - 1) / PT));
+  const dim3 grid(unsigned((op.cells + PT - 1) / PT), 1, unsigned(T.sl.count));
   const int dpt = (op.ndir + 15) / 16;
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, v, u0, op.sT32, op.sA32, op.dc32, op.Sdiag32, m.d_w_out,
-                       m.s, z, op.ndir, m.c0, op.cells);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+                       T.arr.Sdiag32, m.d_w_out, m.s, z, op.ndir, m.c0, op.cells);
   };
   if (dpt <= 1)
     go(proj_kernel<1>);
@@ -872,28 +1145,33 @@ void launch_proj(const Operator& op, const Model& m, const double* v, const floa
   RTE_HIP(hipGetLastError());
 }
 
-void launch_scale_fields(const float* ainv, const float* f, float* t, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(scale_fields_kernel, dim3(ew_grid(count)), dim3(256), 0, s, ainv, f, t, count);
+namespace {
+dim3 ew_grid3(int64_t n, const Slots& sl) { return dim3(ew_grid(n), 1, unsigned(sl.count)); }
+}  // namespace
+
+void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(scale_fields_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, ainv, f, t, count);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_fill_f32(float* p, float v, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(fill_kernel<float>, dim3(ew_grid(count)), dim3(256), 0, s, p, v, count);
+void launch_fill_f32(const Slots& sl, float* p, float v, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel<float>, ew_grid3(count, sl), dim3(256), 0, s, sl, p, v, count);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_fill_f64(double* p, double v, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(fill_kernel<double>, dim3(ew_grid(count)), dim3(256), 0, s, p, v, count);
+void launch_fill_f64(const Slots& sl, double* p, double v, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel<double>, ew_grid3(count, sl), dim3(256), 0, s, sl, p, v, count);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_cast_f64_f32(const double* src, float* dst, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(cast_kernel, dim3(ew_grid(count)), dim3(256), 0, s, src, dst, count);
+void launch_cast_f64_f32(const Slots& sl, const double* src, float* dst, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, src, dst, count);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_copy_f64(const double* src, double* dst, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(copy64_kernel, dim3(ew_grid(count)), dim3(256), 0, s, src, dst, count);
+void launch_copy_f64(const Slots& sl, const double* src, double* dst, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(copy64_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, src, dst, count);
   RTE_HIP(hipGetLastError());
 }
 

@@ -1,12 +1,14 @@
-// Continuous batching of independent solves.  A worker thread admits queued
-// requests in arrival order while a slot (HIP stream) is free and the
-// request's workspace fits in the caller's device arena, then advances every
-// admitted solve whose last device result has arrived; finished solves free
-// their slot and arena range at once, so later arrivals join while others
-// are still running.  Each request runs the same SolveRun as rte_solve.
+// Continuous batching of solves.  A worker thread admits queued requests in
+// arrival order while fewer than max_slots solves are active and the
+// request's workspace fits in the caller's device arena.  Admitted requests
+// of one shape (grid, directions, model, restart length, preconditioner)
+// join one Batch: each launch of a batch covers all of its solves, and a
+// request that arrives while others run joins at the batch's next cycle
+// boundary.  Batches of different shapes run on streams of their own and
+// overlap on the device.  A finished solve frees its arena range as soon as
+// its result has been copied to the caller's buffer.
 #include <atomic>
 #include <chrono>
-#include <condition_variable>
 #include <deque>
 #include <map>
 #include <memory>
@@ -24,8 +26,6 @@ struct Request {
   rte_solve_opts o{};
   double* x = nullptr;
   size_t need = 0, off = 0;
-  int slot = -1;
-  std::unique_ptr<SolveRun> run;
   bool finished = false;
   rte_status status = RTE_EAGAIN;
   rte_solve_stats stats{};
@@ -36,28 +36,33 @@ double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+struct Group {
+  std::unique_ptr<Batch> b;
+  hipStream_t s = nullptr;
+  size_t tab_off = 0;
+};
+
 }  // namespace
 
 struct Server {
   char* arena = nullptr;
   size_t bytes = 0;
   int device = 0;
-  std::vector<hipStream_t> streams;
-  std::vector<bool> busy;
+  int max_slots = 1;
   std::mutex mu;
   std::deque<Request*> queue;
-  std::vector<Request*> active;
   std::map<uint64_t, std::unique_ptr<Request>> tickets;
   std::map<size_t, size_t> used;  // offset -> length
+  std::vector<std::unique_ptr<Group>> groups;  // worker thread only
   uint64_t next_ticket = 1;
-  int64_t submitted = 0, completed = 0;
+  int64_t submitted = 0, completed = 0, active = 0;
   size_t in_use = 0, peak = 0;
   std::atomic<bool> stopping{false};
   std::thread worker;
 
   static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
 
-  // first fit over the gaps between used ranges
+  // first fit over the gaps between used ranges (caller holds mu)
   bool alloc(size_t need, size_t* off) {
     size_t cur = 0;
     for (auto& kv : used) {
@@ -78,92 +83,132 @@ struct Server {
     used.erase(it);
   }
 
-  void retire(Request* r, rte_status st) {
-    // nothing of this request may still be writing into its arena range
-    if (r->slot >= 0) (void)hipStreamSynchronize(streams[r->slot]);
-    r->run.reset();
+  Group* group_for(const Request* r) {
+    for (auto& g : groups)
+      if (g->b->compatible(*r->op, r->m, r->o.restart, r->o.precond) && !g->b->full()) return g.get();
+    return nullptr;
+  }
+
+  // caller holds mu
+  Group* make_group(const Request* r) {
+    size_t off = 0;
+    if (!alloc(align(batch_table_bytes(max_slots)), &off)) return nullptr;
+    std::unique_ptr<Group> g(new Group());
+    g->tab_off = off;
+    try {
+      RTE_HIP(hipStreamCreateWithFlags(&g->s, hipStreamNonBlocking));
+      g->b.reset(new Batch(*r->op, r->m, r->o.restart, r->o.precond, max_slots, arena + off, g->s));
+    } catch (...) {
+      if (g->s) (void)hipStreamDestroy(g->s);
+      release(off);
+      throw;
+    }
+    groups.push_back(std::move(g));
+    return groups.back().get();
+  }
+
+  // caller holds mu; frees the tables of batches with nothing to do
+  bool reclaim() {
+    bool any = false;
+    for (size_t i = 0; i < groups.size();) {
+      if (groups[i]->b->idle()) {
+        groups[i]->b.reset();
+        (void)hipStreamDestroy(groups[i]->s);
+        release(groups[i]->tab_off);
+        groups.erase(groups.begin() + long(i));
+        any = true;
+      } else {
+        ++i;
+      }
+    }
+    return any;
+  }
+
+  void retire(const Batch::Finished& f) {
+    Request* r = static_cast<Request*>(f.tag);
     std::lock_guard<std::mutex> lk(mu);
-    r->status = st;
+    r->status = f.status;
+    r->stats = f.stats;
+    r->stats.status = f.status;
+    r->stats.ms_total = now_ms() - r->t_submit;  // arrival to completion
     r->finished = true;
-    r->stats.status = st;
-    if (r->slot >= 0) busy[r->slot] = false;
-    if (r->slot >= 0) release(r->off);
+    release(r->off);
+    --active;
     ++completed;
+  }
+
+  void fail_request(Request* r, rte_status st) {
+    Batch::Finished f{};
+    f.tag = r;
+    f.status = st;
+    retire(f);
+  }
+
+  void admit() {
+    std::lock_guard<std::mutex> lk(mu);
+    while (!queue.empty() && active < max_slots) {
+      Request* r = queue.front();
+      size_t off = 0;
+      bool ws = alloc(r->need, &off);
+      if (!ws && reclaim()) ws = alloc(r->need, &off);
+      if (!ws) break;  // head of line waits for space
+      Group* g = nullptr;
+      try {
+        g = group_for(r);
+        if (!g) g = make_group(r);
+        if (!g && reclaim()) g = make_group(r);
+      } catch (...) {
+        g = nullptr;
+      }
+      if (!g) {
+        release(off);
+        break;
+      }
+      queue.pop_front();
+      r->off = off;
+      ++active;
+      try {
+        g->b->add(r, *r->op, r->o, arena + off, r->x, r->t_submit);
+      } catch (const Error& e) {
+        r->status = e.code;
+        r->stats.status = e.code;
+        r->finished = true;
+        release(off);
+        --active;
+        ++completed;
+      }
+    }
   }
 
   void loop() {
     (void)hipSetDevice(device);
+    std::vector<Batch::Finished> done;
     while (true) {
-      std::vector<Request*> admitted;
+      admit();
       {
         std::lock_guard<std::mutex> lk(mu);
-        while (!queue.empty()) {
-          int slot = -1;
-          for (size_t i = 0; i < busy.size(); ++i)
-            if (!busy[i]) { slot = int(i); break; }
-          if (slot < 0) break;
-          Request* r = queue.front();
-          size_t off = 0;
-          if (!alloc(r->need, &off)) break;  // head of line waits for space
-          queue.pop_front();
-          r->off = off;
-          r->slot = slot;
-          busy[slot] = true;
-          active.push_back(r);
-          admitted.push_back(r);
-        }
-        if (stopping && queue.empty() && active.empty()) return;
-      }
-      for (Request* r : admitted) {
-        try {
-          r->run.reset(new SolveRun(*r->op, r->m, r->o, arena + r->off, r->need, r->x, streams[r->slot]));
-          r->run->start();
-        } catch (const Error& e) {
-          drop(r, e.code);
-        } catch (...) {
-          drop(r, RTE_EDEVICE);
-        }
+        if (stopping && queue.empty() && active == 0) break;
       }
       bool progress = false;
-      for (size_t i = 0; i < active.size();) {
-        Request* r = active[i];
-        rte_status st = RTE_EAGAIN;
+      for (auto& g : groups) {
+        done.clear();
         try {
-          if (r->run->ready()) {
-            r->run->advance();
+          if (!g->b->idle() && g->b->ready()) {
+            g->b->advance();
             progress = true;
-            if (r->run->done()) {
-              r->run->fill_stats(&r->stats);
-              r->stats.ms_total = now_ms() - r->t_submit;  // arrival to completion
-              st = r->run->status();
-            }
           }
+          g->b->collect(done);
         } catch (const Error& e) {
-          st = e.code;
+          g->b->abandon(e.code, done);
         } catch (...) {
-          st = RTE_EDEVICE;
+          g->b->abandon(RTE_EDEVICE, done);
         }
-        if (st != RTE_EAGAIN) {
-          {
-            std::lock_guard<std::mutex> lk(mu);
-            active.erase(active.begin() + i);
-          }
-          retire(r, st);
-        } else {
-          ++i;
-        }
+        for (const auto& f : done) retire(f);
       }
       if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-  }
-
-  void drop(Request* r, rte_status st) {
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      for (size_t i = 0; i < active.size(); ++i)
-        if (active[i] == r) { active.erase(active.begin() + i); break; }
-    }
-    retire(r, st);
+    std::lock_guard<std::mutex> lk(mu);
+    reclaim();
   }
 };
 
@@ -203,12 +248,7 @@ rte_status rte_server_create(void* arena, size_t arena_bytes, int max_slots, rte
     s->arena = static_cast<char*>(arena);
     s->bytes = arena_bytes;
     RTE_HIP(hipGetDevice(&s->device));
-    for (int i = 0; i < max_slots; ++i) {
-      hipStream_t st;
-      RTE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-      s->streams.push_back(st);
-      s->busy.push_back(false);
-    }
+    s->max_slots = max_slots;
     Server* raw = s.get();
     s->worker = std::thread([raw] { raw->loop(); });
     auto* h = new rte_server();
@@ -231,7 +271,8 @@ rte_status rte_submit(rte_server* h, const rte_operator* op, const mgnet_model* 
     r->o = *opts;
     r->x = psi_out;
     r->need = Server::align(solve_layout(*r->op, m, opts->restart, opts->precond != RTE_PC_NONE).total);
-    RTE_REQUIRE(r->need <= s.bytes, RTE_ENOMEM, "request workspace exceeds the arena");
+    RTE_REQUIRE(r->need + Server::align(batch_table_bytes(s.max_slots)) <= s.bytes, RTE_ENOMEM,
+                "request workspace exceeds the arena");
     r->t_submit = now_ms();
     std::lock_guard<std::mutex> lk(s.mu);
     RTE_REQUIRE(!s.stopping, RTE_EINVAL, "server is shutting down");
@@ -272,7 +313,7 @@ rte_status rte_server_query(rte_server* h, rte_server_stats* out) {
     std::lock_guard<std::mutex> lk(s.mu);
     out->submitted = s.submitted;
     out->completed = s.completed;
-    out->active = int64_t(s.active.size());
+    out->active = s.active;
     out->queued = int64_t(s.queue.size());
     out->arena_bytes = s.bytes;
     out->arena_in_use = s.in_use;
@@ -285,7 +326,6 @@ rte_status rte_server_destroy(rte_server* h) {
     if (!h) return;
     h->s->stopping = true;
     if (h->s->worker.joinable()) h->s->worker.join();
-    for (hipStream_t st : h->s->streams) (void)hipStreamDestroy(st);
     delete h;
   });
 }

@@ -19,6 +19,31 @@ int Operator::level_dim(int l, int axis) const {
   return n >> l;
 }
 
+std::vector<int64_t> Operator::shape_key() const {
+  return {dim, nx, ny, nz, ndir, levels, c0};
+}
+
+OpArrays Operator::relative() const {
+  auto rel = [&](auto* p) { return p ? at(p, uint64_t(0) - reinterpret_cast<uint64_t>(block)) : p; };
+  OpArrays r;
+  r.b64 = rel(a.b64);
+  r.sT32 = rel(a.sT32);
+  r.sA32 = rel(a.sA32);
+  r.sT64 = rel(a.sT64);
+  r.sA64 = rel(a.sA64);
+  r.S32 = rel(a.S32);
+  r.S64 = rel(a.S64);
+  r.dc32 = rel(a.dc32);
+  r.dc64 = rel(a.dc64);
+  r.dsgn = rel(a.dsgn);
+  r.Sdiag32 = rel(a.Sdiag32);
+  for (int l = 0; l < MAX_LEVELS; ++l) {
+    r.fa[l] = rel(a.fa[l]);
+    r.fainv[l] = rel(a.fainv[l]);
+  }
+  return r;
+}
+
 namespace {
 
 // Kernel values P_mn = kappa(u_m . u_n), eq. (hg) ("sphere") or its circle
@@ -80,8 +105,8 @@ void build_coeffnet(Operator& op, const Model& m, const std::vector<double>& eps
   const int64_t cells = op.cells;
   std::vector<float> X(size_t(cells) * 3);
   std::vector<double> sT(cells), sA(cells);
-  RTE_HIP(hipMemcpy(sT.data(), op.sT64, cells * 8, hipMemcpyDeviceToHost));
-  RTE_HIP(hipMemcpy(sA.data(), op.sA64, cells * 8, hipMemcpyDeviceToHost));
+  RTE_HIP(hipMemcpy(sT.data(), op.a.sT64, cells * 8, hipMemcpyDeviceToHost));
+  RTE_HIP(hipMemcpy(sA.data(), op.a.sA64, cells * 8, hipMemcpyDeviceToHost));
   for (int64_t c = 0; c < cells; ++c) {
     X[3 * c + 0] = float(std::log(sT[c]));
     X[3 * c + 1] = float(sA[c] / sT[c]);
@@ -99,12 +124,8 @@ void build_coeffnet(Operator& op, const Model& m, const std::vector<double>& eps
     int64_t P = op.level_cells(l);
     float* F = tmp.alloc<float>(size_t(P) * c);
     launch_coef_conv(in, cin, in_dim, m.d_CW[l], m.d_CB[l], F, c, out_dim, op.dim, stride, s);
-    float* a = op.mem.alloc<float>(size_t(P) * C);
-    float* ai = op.mem.alloc<float>(size_t(P) * C);
-    launch_head(F, c, m.d_HAW[l], m.d_HAB[l], a, C, P, s);
-    launch_head(F, c, m.d_HIW[l], m.d_HIB[l], ai, C, P, s);
-    op.fa.push_back(a);
-    op.fainv.push_back(ai);
+    launch_head(F, c, m.d_HAW[l], m.d_HAB[l], op.a.fa[l], C, P, s);
+    launch_head(F, c, m.d_HIW[l], m.d_HIB[l], op.a.fainv[l], C, P, s);
     in = F;
     cin = c;
     for (int a2 = 0; a2 < 3; ++a2) in_dim[a2] = out_dim[a2];
@@ -164,6 +185,7 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
     RTE_REQUIRE(model->dim == dim && model->ndir == N, RTE_EINVAL, "model does not match the geometry");
     int div = 1 << (model->levels - 1);
     RTE_REQUIRE(nx % div == 0, RTE_EINVAL, "grid extent not divisible by 2^(levels-1) of the model");
+    RTE_REQUIRE(model->levels <= MAX_LEVELS, RTE_EINVAL, "too many MgNet levels");
   }
 
   Operator* op = new Operator();
@@ -226,17 +248,50 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
     for (size_t i = 0; i < S32.size(); ++i) S32[i] = float(op->S[i]);
     for (size_t i = 0; i < dc.size(); ++i) dc32[i] = float(dc[i]);
     for (int m = 0; m < N; ++m) Sd[m] = float(op->S[size_t(m) * N + m]);
-    op->b64 = op->mem.upload(b);
-    op->sT64 = op->mem.upload(sT);
-    op->sA64 = op->mem.upload(sA);
-    op->sT32 = op->mem.upload(sT32);
-    op->sA32 = op->mem.upload(sA32);
-    op->S64 = op->mem.upload(op->S);
-    op->S32 = op->mem.upload(S32);
-    op->dc64 = op->mem.upload(dc);
-    op->dc32 = op->mem.upload(dc32);
-    op->dsgn = op->mem.upload(sg);
-    op->Sdiag32 = op->mem.upload(Sd);
+    // one device block, laid out by shape only
+    if (model) {
+      op->levels = model->levels;
+      op->c0 = model->c0;
+    }
+    size_t off = 256;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) & ~size_t(255);
+      return o;
+    };
+    const size_t o_b = take(size_t(op->n) * 8), o_sT64 = take(cells * 8), o_sA64 = take(cells * 8);
+    const size_t o_sT32 = take(cells * 4), o_sA32 = take(cells * 4);
+    const size_t o_S64 = take(size_t(N) * N * 8), o_S32 = take(size_t(N) * N * 4);
+    const size_t o_dc64 = take(dc.size() * 8), o_dc32 = take(dc.size() * 4), o_sg = take(sg.size() * 4);
+    const size_t o_sd = take(size_t(N) * 4);
+    size_t o_fa[MAX_LEVELS] = {}, o_fi[MAX_LEVELS] = {};
+    for (int l = 0; l < op->levels; ++l) {
+      const size_t bytes = size_t(op->level_cells(l)) * (op->c0 << l) * 4;
+      o_fa[l] = take(bytes);
+      o_fi[l] = take(bytes);
+    }
+    op->block_bytes = off;
+    op->block = op->mem.alloc<char>(off);
+    char* B = op->block;
+    auto put = [&](size_t o, const void* src, size_t bytes) {
+      RTE_HIP(hipMemcpy(B + o, src, bytes, hipMemcpyHostToDevice));
+      return B + o;
+    };
+    op->a.b64 = reinterpret_cast<double*>(put(o_b, b.data(), b.size() * 8));
+    op->a.sT64 = reinterpret_cast<double*>(put(o_sT64, sT.data(), cells * 8));
+    op->a.sA64 = reinterpret_cast<double*>(put(o_sA64, sA.data(), cells * 8));
+    op->a.sT32 = reinterpret_cast<float*>(put(o_sT32, sT32.data(), cells * 4));
+    op->a.sA32 = reinterpret_cast<float*>(put(o_sA32, sA32.data(), cells * 4));
+    op->a.S64 = reinterpret_cast<double*>(put(o_S64, op->S.data(), op->S.size() * 8));
+    op->a.S32 = reinterpret_cast<float*>(put(o_S32, S32.data(), S32.size() * 4));
+    op->a.dc64 = reinterpret_cast<double*>(put(o_dc64, dc.data(), dc.size() * 8));
+    op->a.dc32 = reinterpret_cast<float*>(put(o_dc32, dc32.data(), dc32.size() * 4));
+    op->a.dsgn = reinterpret_cast<int*>(put(o_sg, sg.data(), sg.size() * 4));
+    op->a.Sdiag32 = reinterpret_cast<float*>(put(o_sd, Sd.data(), Sd.size() * 4));
+    for (int l = 0; l < op->levels; ++l) {
+      op->a.fa[l] = reinterpret_cast<float*>(B + o_fa[l]);
+      op->a.fainv[l] = reinterpret_cast<float*>(B + o_fi[l]);
+    }
     if (model) {
       const_cast<Model*>(model)->ensure_on_device();
       build_coeffnet(*op, *model, eps, stream);

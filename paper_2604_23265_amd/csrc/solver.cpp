@@ -29,9 +29,11 @@ size_t precond_bytes(const Operator& op, const Model& m) {
 // a stride-2 transposed-conv prolongation added to u and nu_post steps,
 // and the projection plus the diagonal skip.  A smoothing step is two
 // launches: t = a^{-1} (.) (f - A * u - a (.) u) and u += B * t.
-void precond_apply(const Operator& op, const Model& m, int kind, const double* v, float* z, char* ws,
+void precond_apply(const Target& T, const Model& m, int kind, const double* v, float* z, char* ws,
                    hipStream_t s) {
   ProfScope ps(RTE_K_PRECOND, s);
+  const Operator& op = *T.op;
+  const Slots& sl = T.sl;
   const int L = m.levels;
   std::vector<float*> f(L), u(L), t(L);
   std::vector<int64_t> P(L);
@@ -53,8 +55,9 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
     int d[3];
     dims(l, d);
     conv3_setup(c, op.dim, d, 1);
+    c.sl = sl;
     c.in = in; c.cin = w.cin; c.w = &w; c.out = out; c.cout = w.cout; c.mode = mode;
-    c.f = f[l]; c.a = op.fa[l]; c.ainv = op.fainv[l];
+    c.f = f[l]; c.a = T.arr.fa[l]; c.ainv = T.arr.fainv[l];
     launch_conv(c, kind, s);
   };
   // uz[l]: u_l is still zero; tready[l]: t_l already holds a^{-1} (.) f_l,
@@ -65,7 +68,7 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
   };
   auto smooth = [&](int l, const ConvW& B) {
     if (uz[l]) {
-      if (!tready[l]) launch_scale_fields(op.fainv[l], f[l], t[l], P[l] * C[l], s);
+      if (!tready[l]) launch_scale_fields(sl, T.arr.fainv[l], f[l], t[l], P[l] * C[l], s);
       tready[l] = false;
       conv_same(l, t[l], B, u[l], CONV_STORE);
       uz[l] = false;
@@ -76,7 +79,7 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
   };
 
   const bool want0 = first_steps(0) > 0;
-  launch_lift(op, m, v, f[0], want0 ? op.fainv[0] : nullptr, want0 ? t[0] : nullptr, s);
+  launch_lift(T, m, v, f[0], want0 ? T.arr.fainv[0] : nullptr, want0 ? t[0] : nullptr, s);
   tready[0] = want0;
   for (int l = 0; l < L - 1; ++l) {
     uz[l] = true;
@@ -90,40 +93,53 @@ void precond_apply(const Operator& op, const Model& m, int kind, const double* v
     int d[3];
     dims(l, d);
     conv3_setup(c, op.dim, d, 2);
+    c.sl = sl;
     const bool want = first_steps(l + 1) > 0;
     c.in = rin; c.cin = m.R[l].cin; c.w = &m.R[l]; c.out = f[l + 1]; c.cout = m.R[l].cout;
     c.mode = want ? CONV_STORE_T : CONV_STORE;
     c.out2 = want ? t[l + 1] : nullptr;
-    c.ainv = op.fainv[l + 1];
+    c.ainv = T.arr.fainv[l + 1];
     launch_conv(c, kind, s);
     tready[l + 1] = want;
   }
   uz[L - 1] = true;
   for (const ConvW& B : m.Bc) smooth(L - 1, B);
-  if (uz[L - 1]) launch_fill_f32(u[L - 1], 0.f, P[L - 1] * C[L - 1], s);
+  if (uz[L - 1]) launch_fill_f32(sl, u[L - 1], 0.f, P[L - 1] * C[L - 1], s);
   for (int l = L - 2; l >= 0; --l) {
     ConvLaunch c{};
     int d[3];
     dims(l + 1, d);
     convT4_setup(c, op.dim, d);
+    c.sl = sl;
     c.in = u[l + 1]; c.cin = m.Pr[l].cin; c.w = &m.Pr[l]; c.out = u[l]; c.cout = m.Pr[l].cout;
     c.mode = uz[l] ? CONV_STORE : CONV_ACCUM;
     launch_conv(c, kind, s);
     uz[l] = false;
     for (const ConvW& B : m.Bpost[l]) smooth(l, B);
   }
-  if (uz[0]) launch_fill_f32(u[0], 0.f, P[0] * C[0], s);
-  launch_proj(op, m, v, u[0], z, s);
+  if (uz[0]) launch_fill_f32(sl, u[0], 0.f, P[0] * C[0], s);
+  launch_proj(T, m, v, u[0], z, s);
 }
 
 constexpr int HMAX = 65;
+
+namespace {
+template <class T>
+T* off(size_t o) {
+  return reinterpret_cast<T*>(uintptr_t(o));
+}
+}  // namespace
 
 SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet) {
   SolveLayout L{};
   L.k = k;
   L.n = op.n;
   L.nblk = krylov_blocks(op.n);
-  size_t off = 0;
+  // nothing sits at offset 0: under a slot table a zero offset would read
+  // as a null argument
+  size_t off = 256;
+  L.off_x = off; off += align256(size_t(op.n) * 8);
+  L.off_b = off; off += align256(size_t(op.n) * 8);
   L.off_V = off; off += align256(size_t(k + 1) * op.n * 8);
   L.off_Z = off; off += align256(size_t(k) * op.n * 4);
   L.off_part1 = off; off += align256(size_t(L.nblk) * HMAX * 8);
@@ -136,18 +152,38 @@ SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet) 
   return L;
 }
 
+size_t batch_table_bytes(int capacity) {
+  return align256(size_t(capacity) * sizeof(SlotDesc)) + align256(size_t(capacity) * 8 * sizeof(double));
+}
+
 namespace {
 
+// Offsets of the small dense state inside off_small.
+struct Small {
+  size_t H, g, cs, sn, y, h1, h2, stat, bn;
+};
+Small small_of(const SolveLayout& L) {
+  Small q;
+  size_t p = L.off_small;
+  q.H = p; p += size_t(L.k + 1) * L.k * 8;
+  q.g = p; p += HMAX * 8;
+  q.cs = p; p += HMAX * 8;
+  q.sn = p; p += HMAX * 8;
+  q.y = p; p += HMAX * 8;
+  q.h1 = p; p += HMAX * 8;
+  q.h2 = p; p += HMAX * 8;
+  q.stat = p; p += 16 * 8;
+  q.bn = p;
+  return q;
+}
+
 struct GraphKey {
-  const Operator* op;
+  const void* tab;
   const Model* m;
-  int precond;
-  const char* ws;
-  const double* x;
-  const double* b;
-  int k;
+  int precond, k, zc;
+  std::vector<int64_t> shape;
   bool operator<(const GraphKey& o) const {
-    return std::tie(op, m, precond, ws, x, b, k) < std::tie(o.op, o.m, o.precond, o.ws, o.x, o.b, o.k);
+    return std::tie(tab, m, precond, k, zc, shape) < std::tie(o.tab, o.m, o.precond, o.k, o.zc, o.shape);
   }
 };
 
@@ -157,7 +193,7 @@ std::map<GraphKey, std::unique_ptr<std::vector<hipGraphExec_t>>>& graph_map() {
   return *m;
 }
 
-std::atomic<int64_t> g_steps{0};  // Arnoldi steps enqueued by every solve (timer sampling)
+std::atomic<int64_t> g_steps{0};  // Arnoldi steps enqueued by every batch (timer sampling)
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -165,19 +201,19 @@ double now_ms() {
 
 }  // namespace
 
-std::vector<hipGraphExec_t>* step_graphs(const Operator* op, const Model* m, int precond, const char* ws,
-                                         const double* x, const double* b, int k) {
+std::vector<hipGraphExec_t>* step_graphs(const void* tab, const Model* m, int precond, int k,
+                                         const std::vector<int64_t>& shape, int zc) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  auto& slot = graph_map()[GraphKey{op, m, precond, ws, x, b, k}];
+  auto& slot = graph_map()[GraphKey{tab, m, precond, k, zc, shape}];
   if (!slot) slot.reset(new std::vector<hipGraphExec_t>(size_t(k), nullptr));
   return slot.get();
 }
 
-void drop_step_graphs(const Operator* op) {
+void drop_step_graphs(const Model* m) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   auto& mp = graph_map();
   for (auto it = mp.begin(); it != mp.end();) {
-    if (it->first.op == op) {
+    if (it->first.m == m) {
       for (hipGraphExec_t e : *it->second)
         if (e) (void)hipGraphExecDestroy(e);
       it = mp.erase(it);
@@ -200,128 +236,288 @@ void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o) 
   }
 }
 
-// Flexible GMRES(k), right preconditioned (Saad): inner steps in reduced
-// precision (FP32 operator apply, FP32 or BF16 MgNet), orthogonalisation and
-// least squares in FP64, and the true residual b - L x recomputed in FP64
-// at every restart (iterative refinement on the FP64 iterate x).
-SolveRun::SolveRun(const Operator& op, const Model* m, const rte_solve_opts& o, char* ws, size_t ws_bytes,
-                   double* x, hipStream_t s)
-    : op_(op), m_(m), o_(o), x_(x), s_(s) {
-  validate_opts(op, m, &o);
-  mg_ = o.precond != RTE_PC_NONE;
-  kind_ = o.precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16;
-  lay_ = solve_layout(op, m, o.restart, mg_);
-  RTE_REQUIRE(ws != nullptr && x != nullptr, RTE_EINVAL, "null workspace or output");
-  RTE_REQUIRE(ws_bytes >= lay_.total, RTE_ENOMEM, "workspace too small: need " + std::to_string(lay_.total) + " bytes");
-  RTE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL, "workspace must be 256-byte aligned");
+Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capacity, char* tables,
+             hipStream_t s)
+    : shape_(shape), key_(shape.shape_key()), m_(m), k_(k), precond_(precond), cap_(capacity), s_(s) {
+  RTE_REQUIRE(capacity >= 1 && capacity <= 64, RTE_EINVAL, "batch capacity must be in [1, 64]");
+  RTE_REQUIRE(tables != nullptr && (reinterpret_cast<uintptr_t>(tables) & 255) == 0, RTE_EINVAL,
+              "batch tables must be 256-byte aligned");
+  mg_ = precond != RTE_PC_NONE;
+  kind_ = precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16;
+  lay_ = solve_layout(shape, m, k, mg_);
+  rel_ = shape.relative();
+  tab_ = reinterpret_cast<SlotDesc*>(tables);
+  rep_ = reinterpret_cast<double*>(tables + align256(size_t(capacity) * sizeof(SlotDesc)));
   if (mg_) const_cast<Model*>(m)->ensure_on_device();
-  const int k = o.restart;
-  V_ = reinterpret_cast<double*>(ws + lay_.off_V);
-  Z_ = reinterpret_cast<float*>(ws + lay_.off_Z);
-  part1_ = reinterpret_cast<double*>(ws + lay_.off_part1);
-  part2_ = reinterpret_cast<double*>(ws + lay_.off_part2);
-  partn_ = reinterpret_cast<double*>(ws + lay_.off_partn);
-  double* p = reinterpret_cast<double*>(ws + lay_.off_small);
-  H_ = p; p += size_t(k + 1) * k;
-  g_ = p; p += HMAX;
-  cs_ = p; p += HMAX;
-  sn_ = p; p += HMAX;
-  y_ = p; p += HMAX;
-  h1_ = p; p += HMAX;
-  h2_ = p; p += HMAX;
-  stat_ = p; p += 16;
-  bn_ = p;
-  mgws_ = ws + lay_.off_mg;
-  b_ = o.b ? o.b : op.b64;
   const char* env = std::getenv("RTE_GRAPHS");
   graphs_ = !(env && env[0] == '0');
-  if (graphs_) gcache_ = step_graphs(&op, m, o.precond, ws, x, b_, k);
-  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_), 3 * 8 * sizeof(double), hipHostMallocDefault));
-  for (auto& e : ev_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  slot_.resize(size_t(capacity));
+  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hdesc_), size_t(capacity) * sizeof(SlotDesc),
+                        hipHostMallocDefault));
+  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsnap_), 2 * size_t(capacity) * sizeof(SlotDesc),
+                        hipHostMallocDefault));
+  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hrep_), size_t(capacity) * 8 * sizeof(double),
+                        hipHostMallocDefault));
+  std::memset(hdesc_, 0, size_t(capacity) * sizeof(SlotDesc));
+  std::memset(hsnap_, 0, 2 * size_t(capacity) * sizeof(SlotDesc));
+  std::memset(hrep_, 0, size_t(capacity) * 8 * sizeof(double));
+  for (auto& e : ev_step_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  RTE_HIP(hipEventCreateWithFlags(&ev_rep_, hipEventDisableTiming));
+  upload_all();
 }
 
-SolveRun::~SolveRun() {
-  for (auto& e : ev_)
+Batch::~Batch() {
+  (void)hipStreamSynchronize(s_);
+  for (auto* v : {&waiting_, &draining_})
+    for (auto& mb : *v)
+      if (mb && mb->copied) (void)hipEventDestroy(mb->copied);
+  for (auto& mb : slot_)
+    if (mb && mb->copied) (void)hipEventDestroy(mb->copied);
+  for (auto& e : ev_step_)
     if (e) (void)hipEventDestroy(e);
-  if (host_) (void)hipHostFree(host_);
+  if (ev_rep_) (void)hipEventDestroy(ev_rep_);
+  if (hdesc_) (void)hipHostFree(hdesc_);
+  if (hsnap_) (void)hipHostFree(hsnap_);
+  if (hrep_) (void)hipHostFree(hrep_);
 }
 
-void SolveRun::read_into(int slot, const double* dev, int count) {
-  RTE_HIP(hipMemcpyAsync(host_ + 8 * slot, dev, size_t(count) * 8, hipMemcpyDeviceToHost, s_));
-  RTE_HIP(hipEventRecord(ev_[slot], s_));
+bool Batch::compatible(const Operator& op, const Model* m, int k, int precond) const {
+  return m == m_ && k == k_ && precond == precond_ && op.shape_key() == key_;
 }
 
-void SolveRun::start() {
-  t0_ = now_ms();
-  const int64_t n = op_.n;
-  if (o_.x0)
-    launch_copy_f64(o_.x0, x_, n, s_);
-  else
-    launch_fill_f64(x_, 0.0, n, s_);
-  launch_dots(b_, n, 1, b_, n, partn_, lay_.nblk, s_);
-  launch_start_cycle(partn_, lay_.nblk, nullptr, lay_.k, stat_, s_);
-  launch_copy_f64(stat_ + 4, bn_, 1, s_);
-  read_into(SLOT_R, stat_ + 4, 1);
-  phase_ = BNORM;
-  wait_slot_ = SLOT_R;
+int Batch::members() const {
+  int c = int(waiting_.size());
+  for (auto& mb : slot_)
+    if (mb) ++c;
+  return c;
 }
 
-bool SolveRun::ready() {
-  if (phase_ == DONE) return true;
-  hipError_t e = hipEventQuery(ev_[wait_slot_]);
-  if (e == hipErrorNotReady) return false;
-  RTE_HIP(e);
-  return true;
+bool Batch::full() const { return members() >= cap_; }
+
+bool Batch::idle() const { return phase_ == IDLE && members() == 0 && draining_.empty(); }
+
+void Batch::upload(int z) {
+  RTE_HIP(hipMemcpyAsync(tab_ + z, hdesc_ + z, sizeof(SlotDesc), hipMemcpyHostToDevice, s_));
 }
 
-void SolveRun::wait() {
-  if (phase_ == DONE) return;
-  RTE_HIP(hipEventSynchronize(ev_[wait_slot_]));
+void Batch::upload_all() {
+  RTE_HIP(hipMemcpyAsync(tab_, hdesc_, size_t(cap_) * sizeof(SlotDesc), hipMemcpyHostToDevice, s_));
 }
 
-void SolveRun::enqueue_restart() {
-  const int64_t n = op_.n;
-  launch_apply(op_, x_, 1, V_, 1, b_, true, s_);  // r = b - L x in FP64
-  launch_dots(V_, n, 1, V_, n, partn_, lay_.nblk, s_);
-  launch_start_cycle(partn_, lay_.nblk, g_, lay_.k, stat_, s_);
-  read_into(SLOT_R, stat_, 5);
-  wait_slot_ = SLOT_R;
+void Batch::add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws, double* out, double t_start) {
+  RTE_REQUIRE(o.restart == k_ && o.precond == precond_ && op.shape_key() == key_ &&
+                  (precond_ == RTE_PC_NONE || op.model == m_),
+              RTE_EINVAL, "solve does not match the batch");
+  RTE_REQUIRE(!full(), RTE_EINVAL, "batch is full");
+  RTE_REQUIRE(ws && out && (reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL,
+              "bad workspace or output");
+  std::unique_ptr<Member> mb(new Member());
+  mb->tag = tag;
+  mb->op = &op;
+  mb->o = o;
+  mb->ws = ws;
+  mb->out = out;
+  mb->t0 = t_start;
+  waiting_.push_back(std::move(mb));
+  if (phase_ == IDLE) boundary();
 }
 
-// Arnoldi step j: z_j = M(v_j); w = L z_j; CGS2 against v_0..v_j; Givens.
-void SolveRun::step_body(int j, hipStream_t s) {
-  const int64_t n = op_.n;
-  const int nb = lay_.nblk, k = lay_.k;
-  const double* Vj = V_ + size_t(j) * n;
-  double* Vn = V_ + size_t(j + 1) * n;
-  float* Zj = Z_ + size_t(j) * n;
+// Cycle boundary: admit waiting solves into free slots, then for every
+// occupied slot combine the finished cycle's steps into x (x += Z y), form
+// the FP64 true residual r = b - L x as v_0, and report beta = ||r|| and
+// ||b|| to the host.
+namespace {
+struct Quiet {
+  Quiet() { prof_quiet() = true; }
+  ~Quiet() { prof_quiet() = false; }
+};
+}  // namespace
+
+void Batch::boundary() {
+  Quiet quiet;
+  const int64_t n = lay_.n;
+  for (int z = 0; z < cap_ && !waiting_.empty(); ++z) {
+    if (slot_[z]) continue;
+    std::unique_ptr<Member> mb = std::move(waiting_.front());
+    waiting_.erase(waiting_.begin());
+    double* x = reinterpret_cast<double*>(mb->ws + lay_.off_x);
+    double* b = reinterpret_cast<double*>(mb->ws + lay_.off_b);
+    if (mb->o.x0)
+      RTE_HIP(hipMemcpyAsync(x, mb->o.x0, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
+    else
+      launch_fill_f64(Slots{}, x, 0.0, n, s_);
+    const double* bsrc = mb->o.b ? static_cast<const double*>(mb->o.b) : mb->op->a.b64;
+    RTE_HIP(hipMemcpyAsync(b, bsrc, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
+    SlotDesc d{};
+    d.ws = reinterpret_cast<uint64_t>(mb->ws);
+    d.op = reinterpret_cast<uint64_t>(mb->op->block);
+    d.occupied = 1;
+    d.rtol = mb->o.rtol;
+    hdesc_[z] = d;
+    upload(z);
+    mb->slot = z;
+    slot_[z] = std::move(mb);
+  }
+  zc_ = 0;
+  for (int z = 0; z < cap_; ++z)
+    if (slot_[z]) zc_ = z + 1;
+  if (zc_ == 0) {
+    phase_ = IDLE;
+    return;
+  }
+  const Slots so = slots(1);
+  const Target T{&shape_, rel_, so};
+  const Small q = small_of(lay_);
+  const int nb = lay_.nblk, k = k_;
+  double* x = off<double>(lay_.off_x);
+  double* b = off<double>(lay_.off_b);
+  double* V = off<double>(lay_.off_V);
+  double* partn = off<double>(lay_.off_partn);
+  double* stat = off<double>(q.stat);
+  launch_lsq(so, off<double>(q.H), off<double>(q.g), 0, k, off<double>(q.y), s_);
+  launch_xupdate(so, x, off<float>(lay_.off_Z), n, off<double>(q.y), 0, n, s_);
+  launch_dots(so, b, n, 1, b, n, partn, nb, s_);
+  launch_start_cycle(so, partn, nb, nullptr, k, stat, s_);
+  launch_copy_f64(so, stat + 4, off<double>(q.bn), 1, s_);
+  launch_apply(T, x, 1, V, 1, b, true, s_);
+  launch_dots(so, V, n, 1, V, n, partn, nb, s_);
+  launch_start_cycle(so, partn, nb, off<double>(q.g), k, stat, s_);
+  launch_report(so, stat, off<double>(q.bn), rep_, s_);
+  RTE_HIP(hipMemcpyAsync(hrep_, rep_, size_t(zc_) * 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
+  RTE_HIP(hipEventRecord(ev_rep_, s_));
+  phase_ = RESTART;
+}
+
+void Batch::finish_member(Member* mb, rte_status st) {
+  const int z = mb->slot;
+  mb->status = st;
+  mb->ms = now_ms() - mb->t0;
+  RTE_HIP(hipMemcpyAsync(mb->out, mb->ws + lay_.off_x, size_t(lay_.n) * 8, hipMemcpyDeviceToDevice, s_));
+  RTE_HIP(hipEventCreateWithFlags(&mb->copied, hipEventDisableTiming));
+  RTE_HIP(hipEventRecord(mb->copied, s_));
+  hdesc_[z] = SlotDesc{};
+  draining_.push_back(std::move(slot_[z]));
+}
+
+// The host's decision per slot after a boundary report, in the order of
+// the single-solve driver: a non-finite right-hand side, a zero one, a
+// breakdown in the last cycle, convergence of the true residual, the
+// iteration limit, and stagnation (three cycles that each reduce the true
+// residual by less than 0.1%).
+void Batch::decide() {
+  Quiet quiet;
+  int cont = 0;
+  for (int z = 0; z < zc_; ++z) {
+    Member* mb = slot_[z].get();
+    if (!mb) continue;
+    const double* r = hrep_ + 8 * z;
+    const double beta = r[0], bn = r[1];
+    const int jj = int(r[2]);
+    const bool bad = r[3] != 0.0;
+    mb->iters += jj;
+    if (jj > 0) ++mb->restarts;
+    if (mb->bnorm < 0) {
+      mb->bnorm = bn;
+      if (!std::isfinite(bn)) {
+        finish_member(mb, RTE_EINVAL);
+        continue;
+      }
+      if (bn == 0.0) {
+        launch_fill_f64(Slots{}, reinterpret_cast<double*>(mb->ws + lay_.off_x), 0.0, lay_.n, s_);
+        mb->rel = 0;
+        finish_member(mb, RTE_OK);
+        continue;
+      }
+      mb->prev = INFINITY;
+    }
+    mb->rel = beta / mb->bnorm;
+    if (bad || !std::isfinite(beta)) {
+      finish_member(mb, RTE_EBREAKDOWN);
+      continue;
+    }
+    if (mb->rel <= mb->o.rtol) {
+      finish_member(mb, RTE_OK);
+      continue;
+    }
+    if (mb->iters >= mb->o.max_iters) {
+      finish_member(mb, RTE_ENOCONV);
+      continue;
+    }
+    if (beta >= mb->prev * (1.0 - 1e-3)) {
+      if (++mb->stall >= 3) {
+        finish_member(mb, RTE_ENOCONV);
+        continue;
+      }
+    } else {
+      mb->stall = 0;
+    }
+    mb->prev = beta;
+    SlotDesc& d = hdesc_[z];
+    d.live = 1;
+    d.jj = 0;
+    d.bad = 0;
+    d.limit = std::min(k_, mb->o.max_iters - mb->iters);
+    ++cont;
+  }
+  upload_all();
+  nlive_ = cont;
+  if (cont == 0) {
+    boundary();
+    return;
+  }
+  const Small q = small_of(lay_);
+  launch_scale_by(slots(0), off<double>(lay_.off_V), off<double>(q.stat) + 3, lay_.n, s_);  // v_0 = r / beta
+  gcache_ = graphs_ ? step_graphs(tab_, m_, precond_, k_, key_, zc_) : nullptr;
+  j_wait_ = 0;
+  enqueue_step(0);
+  if (k_ > 1) enqueue_step(1);
+  phase_ = STEPS;
+}
+
+// Arnoldi step j for every live slot: z_j = M(v_j); w = L z_j; CGS2
+// against v_0..v_j in three passes (h1 = V^T w; w1 = w - V h1 with
+// h2 = V^T w1 and ||w1||^2; v_{j+1} = (w1 - V h2) / ||w1 - V h2||); Givens.
+void Batch::step_body(int j, int zc, hipStream_t s) {
+  const Slots sl{tab_, zc, 0};
+  const Target T{&shape_, rel_, sl};
+  const int64_t n = lay_.n;
+  const int nb = lay_.nblk, k = k_;
+  const Small q = small_of(lay_);
+  double* V = off<double>(lay_.off_V);
+  const double* Vj = V + size_t(j) * n;
+  double* Vn = V + size_t(j + 1) * n;
+  float* Zj = off<float>(lay_.off_Z) + size_t(j) * n;
+  double* part1 = off<double>(lay_.off_part1);
+  double* part2 = off<double>(lay_.off_part2);
+  double* h1 = off<double>(q.h1);
+  double* h2 = off<double>(q.h2);
+  double* stat = off<double>(q.stat);
   if (mg_)
-    precond_apply(op_, *m_, kind_, Vj, Zj, mgws_, s);
+    precond_apply(T, *m_, kind_, Vj, Zj, off<char>(lay_.off_mg), s);
   else
-    launch_cast_f64_f32(Vj, Zj, n, s);
-  launch_apply(op_, Zj, 0, Vn, 1, nullptr, false, s);
-  // CGS2 in three passes over V: h1 = V^T w; w1 = w - V h1 with h2 = V^T w1
-  // and ||w1||^2; then v_{j+1} = (w1 - V h2) / ||w1 - V h2||
-  launch_dots(V_, n, j + 1, Vn, n, part1_, nb, s);
-  launch_reduce(part1_, nb, j + 1, h1_, s);
-  launch_updots(V_, n, j + 1, h1_, Vn, n, part2_, nb, s);
-  launch_reduce(part2_, nb, j + 2, h2_, s);
-  launch_finish_step(h1_, h2_, j, k, H_, cs_, sn_, g_, bn_, stat_, s);
-  launch_update_scale(V_, n, j + 1, h2_, Vn, n, stat_ + 3, s);
+    launch_cast_f64_f32(sl, Vj, Zj, n, s);
+  launch_apply(T, Zj, 0, Vn, 1, nullptr, false, s);
+  launch_dots(sl, V, n, j + 1, Vn, n, part1, nb, s);
+  launch_reduce(sl, part1, nb, j + 1, h1, s);
+  launch_updots(sl, V, n, j + 1, h1, Vn, n, part2, nb, s);
+  launch_reduce(sl, part2, nb, j + 2, h2, s);
+  launch_finish_step(sl, h1, h2, j, k, off<double>(q.H), off<double>(q.cs), off<double>(q.sn), off<double>(q.g),
+                     off<double>(q.bn), stat, s);
+  launch_update_scale(sl, V, n, j + 1, h2, Vn, n, stat + 3, s);
 }
 
 namespace {
 
-// Capture the kernels of one Arnoldi step on a private stream (nothing runs
+// Capture the launches of one Arnoldi step on a private stream (nothing runs
 // during capture) and instantiate them as a graph.
-hipGraphExec_t capture_step(SolveRun& run, int j) {
+hipGraphExec_t capture_step(Batch& b, int j, int zc) {
   thread_local hipStream_t cap = nullptr;
   if (!cap) RTE_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   prof_capturing() = true;
   hipGraph_t g = nullptr;
   RTE_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   try {
-    run.step_body(j, cap);
+    b.step_body(j, zc, cap);
   } catch (...) {
     (void)hipStreamEndCapture(cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -339,121 +535,136 @@ hipGraphExec_t capture_step(SolveRun& run, int j) {
 
 }  // namespace
 
-// Replays the step's graph (captured on first use for this workspace);
-// while the kernel-class timer is on, one step in `every` runs eagerly with
-// all of its launches of the enabled classes timed.
-void SolveRun::enqueue_step(int j) {
+// Replays the step's graph (captured on first use); while the kernel-class
+// timer is on, one step in `every` runs eagerly with all of its launches of
+// the enabled classes timed.  The descriptors are copied back after every
+// step so the host can end a cycle early.
+void Batch::enqueue_step(int j) {
   const int stride = prof_stride();
   const bool sample = stride > 0 && (g_steps.fetch_add(1) % stride) == 0;
-  if (!graphs_ || sample) {
+  if (!gcache_ || sample) {
     prof_force() = sample;
+    prof_quiet() = !sample;
+    prof_scale() = double(nlive_);
     try {
-      step_body(j, s_);
+      step_body(j, zc_, s_);
     } catch (...) {
       prof_force() = false;
+      prof_quiet() = false;
+      prof_scale() = 1.0;
       throw;
     }
     prof_force() = false;
+    prof_quiet() = false;
+    prof_scale() = 1.0;
   } else {
     hipGraphExec_t& ge = (*gcache_)[j];
-    if (!ge) ge = capture_step(*this, j);
+    if (!ge) ge = capture_step(*this, j, zc_);
     RTE_HIP(hipGraphLaunch(ge, s_));
   }
-  read_into(j % 2, stat_, 2);
+  RTE_HIP(hipMemcpyAsync(hsnap_ + size_t(j % 2) * cap_, tab_, size_t(zc_) * sizeof(SlotDesc),
+                         hipMemcpyDeviceToHost, s_));
+  RTE_HIP(hipEventRecord(ev_step_[j % 2], s_));
   j_enq_ = j + 1;
 }
 
-void SolveRun::finish(rte_status st) {
-  status_ = st;
-  phase_ = DONE;
-  RTE_HIP(hipStreamSynchronize(s_));
-  ms_ = now_ms() - t0_;
+bool Batch::ready() {
+  hipEvent_t e = nullptr;
+  if (phase_ == RESTART) e = ev_rep_;
+  else if (phase_ == STEPS) e = ev_step_[j_wait_ % 2];
+  else return true;
+  const hipError_t r = hipEventQuery(e);
+  if (r == hipErrorNotReady) return false;
+  RTE_HIP(r);
+  return true;
 }
 
-void SolveRun::advance() {
-  if (phase_ == DONE) return;
-  const double* h = host_ + 8 * wait_slot_;
-  switch (phase_) {
-    case BNORM: {
-      bnorm_ = h[0];
-      if (!std::isfinite(bnorm_)) fail(RTE_EINVAL, "right-hand side is not finite");
-      if (bnorm_ == 0.0) {
-        launch_fill_f64(x_, 0.0, op_.n, s_);
-        rel_ = 0;
-        finish(RTE_OK);
-        return;
-      }
-      prev_ = INFINITY;
-      enqueue_restart();
-      phase_ = BETA;
-      return;
-    }
-    case BETA: {
-      const double beta = h[4];
-      rel_ = beta / bnorm_;
-      if (!std::isfinite(beta)) return finish(RTE_EBREAKDOWN);
-      if (rel_ <= o_.rtol) return finish(RTE_OK);
-      if (iters_ >= o_.max_iters) return finish(RTE_ENOCONV);
-      if (beta >= prev_ * (1.0 - 1e-3)) {
-        if (++stall_ >= 3) return finish(RTE_ENOCONV);
-      } else {
-        stall_ = 0;
-      }
-      prev_ = beta;
-      launch_scale_by(V_, stat_ + 3, op_.n, s_);
-      enqueue_step(0);
-      if (lay_.k > 1) enqueue_step(1);
-      j_wait_ = 0;
-      wait_slot_ = 0;
-      phase_ = STEPS;
-      return;
-    }
-    case STEPS: {
-      const double est = h[0];
-      const int flags = int(h[1]);
-      ++iters_;
-      const int j = j_wait_;
-      if (flags & 1) {
-        // non-finite: keep the iterate of the last completed cycle
-        --iters_;
-        enqueue_restart();
-        phase_ = FINAL;
-        return;
-      }
-      const bool stop = (flags & 2) || est <= o_.rtol || iters_ >= o_.max_iters || j + 1 == lay_.k;
-      if (stop) {
-        // a speculative step j + 1 may still be queued: it writes only column
-        // j + 1 of H, g[j + 1 ..], V_{j + 2} and Z_{j + 1}, none of which the
-        // update below reads
-        launch_lsq(H_, g_, j + 1, lay_.k, y_, s_);
-        launch_xupdate(x_, Z_, op_.n, y_, j + 1, op_.n, s_);
-        ++restarts_;
-        enqueue_restart();
-        phase_ = BETA;
-        return;
-      }
-      j_wait_ = j + 1;
-      wait_slot_ = j_wait_ % 2;
-      if (j + 2 < lay_.k && j_enq_ == j + 2) enqueue_step(j + 2);
-      return;
-    }
-    case FINAL: {
-      rel_ = h[4] / bnorm_;
-      return finish(RTE_EBREAKDOWN);
-    }
-    default:
-      return;
+void Batch::wait() {
+  if (phase_ == RESTART) {
+    RTE_HIP(hipEventSynchronize(ev_rep_));
+  } else if (phase_ == STEPS) {
+    RTE_HIP(hipEventSynchronize(ev_step_[j_wait_ % 2]));
+  } else {
+    for (auto& mb : draining_) RTE_HIP(hipEventSynchronize(mb->copied));
   }
 }
 
-void SolveRun::fill_stats(rte_solve_stats* st) const {
-  if (!st) return;
-  st->iterations = iters_;
-  st->restarts = restarts_;
-  st->converged = status_ == RTE_OK;
-  st->status = status_;
-  st->rel_residual = rel_;
-  st->ms_total = ms_;
+void Batch::advance() {
+  switch (phase_) {
+    case IDLE:
+      if (!waiting_.empty()) boundary();
+      return;
+    case RESTART:
+      decide();
+      return;
+    case STEPS: {
+      const int j = j_wait_;
+      const SlotDesc* snap = hsnap_ + size_t(j % 2) * cap_;
+      int live = 0;
+      for (int z = 0; z < zc_; ++z)
+        if (slot_[z] && snap[z].live) ++live;
+      nlive_ = live;
+      if (live == 0 || j + 1 == k_) {
+        // every slot has stopped: a step j + 1 already queued finds no live
+        // slot and changes nothing
+        boundary();
+        return;
+      }
+      j_wait_ = j + 1;
+      if (j + 2 < k_ && j_enq_ == j + 2) enqueue_step(j + 2);
+      return;
+    }
+  }
+}
+
+void Batch::collect(std::vector<Finished>& out) {
+  for (size_t i = 0; i < draining_.size();) {
+    Member* mb = draining_[i].get();
+    const hipError_t r = hipEventQuery(mb->copied);
+    if (r == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    RTE_HIP(r);
+    Finished f;
+    f.tag = mb->tag;
+    f.status = mb->status;
+    f.stats.iterations = mb->iters;
+    f.stats.restarts = mb->restarts;
+    f.stats.converged = mb->status == RTE_OK;
+    f.stats.status = mb->status;
+    f.stats.rel_residual = mb->rel;
+    f.stats.ms_total = mb->ms;
+    out.push_back(f);
+    (void)hipEventDestroy(mb->copied);
+    mb->copied = nullptr;
+    draining_.erase(draining_.begin() + long(i));
+  }
+}
+
+void Batch::abandon(rte_status st, std::vector<Finished>& out) {
+  (void)hipStreamSynchronize(s_);
+  auto give = [&](std::unique_ptr<Member>& mb, rte_status code) {
+    if (!mb) return;
+    Finished f{};
+    f.tag = mb->tag;
+    f.status = code;
+    f.stats.iterations = mb->iters;
+    f.stats.restarts = mb->restarts;
+    f.stats.status = code;
+    f.stats.rel_residual = mb->rel;
+    out.push_back(f);
+    if (mb->copied) (void)hipEventDestroy(mb->copied);
+    mb.reset();
+  };
+  for (auto& mb : draining_) give(mb, mb->status);
+  for (auto& mb : slot_) give(mb, st);
+  for (auto& mb : waiting_) give(mb, st);
+  draining_.clear();
+  waiting_.clear();
+  std::memset(hdesc_, 0, size_t(cap_) * sizeof(SlotDesc));
+  phase_ = IDLE;
+  zc_ = 0;
 }
 
 }  // namespace rte
