@@ -1,28 +1,29 @@
 // Discrete-ordinates operator apply (eq. (DORTE_2d), step-upwind finite
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
-// Layout: x, y direction-major [N][cells].  A 256-thread block owns 16
-// consecutive cells and all N directions (1024 blocks for a 128^2 grid, so
-// the chip holds many waves in flight).  The block stages x[:, tile] in LDS
-// (rows of 16 cells per direction); each thread then owns one cell and the
-// directions d, d + 16, ...: the scatter sum_n S_mn x_n reads S from LDS and
-// reuses each x_n read for all of the thread's directions; the upwind
-// neighbours come from global memory (the same or an adjacent row, cached)
-// and are requested before the scatter loop so their latency overlaps it.  Collision uses the
-// cancellation-free form sT (x - Sx) + sA Sx = sT x - sS Sx.
+// Layout: x, y direction-major [N][cells].  A 256-thread block owns TL
+// consecutive cells (64, or 16 for more than 64 directions) and all N
+// directions.  The block stages x[:, tile] in LDS (rows of TL cells per
+// direction); each thread then owns one cell and the directions d,
+// d + 256/TL, ...: the scatter sum_n S_mn x_n reads S from LDS and reuses
+// each x_n read for all of the thread's directions; the upwind neighbours
+// come from global memory (the same or an adjacent row, cached) and are
+// requested before the scatter loop so their latency overlaps it.
+// Collision uses the cancellation-free form sT (x - Sx) + sA Sx.
 #include "common.h"
 
 namespace rte {
 namespace {
 
-constexpr int TILE = 16;   // cells per block
-constexpr int DSLOTS = 16; // direction slots per block: thread t -> cell t % 16, slot t / 16
+// A block of 256 threads owns TL consecutive cells: thread t -> cell t % TL,
+// direction slot t / TL (256 / TL slots).  TL = 64 (one slot per wave) for
+// up to 64 directions, TL = 16 beyond.
 
 // Thread (cell c, slot d) computes directions m = d, d + 16, ... (< N, at
 // most DPT of them).  The block stages x[:, tile] (and S when it fits) in
 // LDS; the scatter sum_n S_mn x_n then reuses each x_n read for all of the
 // thread's directions.  Upwind neighbours are requested before the scatter.
-template <class T, class TI, class TO, bool RES, bool LDS_S, int DPT>
+template <class T, class TI, class TO, bool RES, bool LDS_S, int DPT, int TL>
 __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restrict__ x, TO* __restrict__ y,
                                                     const double* __restrict__ b,
                                                     const T* __restrict__ sT, const T* __restrict__ sA,
@@ -39,13 +40,17 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   S = at(S, bs.op);
   dc = at(dc, bs.op);
   sg = at(sg, bs.op);
+  constexpr int TILE = TL;
+  constexpr int DSLOTS = 256 / TL;
   extern __shared__ char smem[];
   T* xs = reinterpret_cast<T*>(smem);       // [N][TILE]
   T* Ss = xs + N * TILE;                    // [N][N + 1]: padded rows, so the direction
                                             // rows read by one wave sit in different banks
   const int ldS = N + 1;
   const int cl = threadIdx.x & (TILE - 1);
-  const int slot = threadIdx.x / TILE;
+  // with one slot per wave (TL = 64) the slot is wave-uniform: make it a
+  // scalar so the per-direction branches and loads stay scalar
+  const int slot = TILE == 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / TILE) : int(threadIdx.x) / TILE;
   const int c0 = int(blockIdx.x) * TILE;
   if (LDS_S) {
     for (int idx = threadIdx.x; idx < N * N; idx += 256) {
@@ -57,7 +62,8 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   for (int idx = threadIdx.x; idx < N * TILE; idx += 256) {
     const int m = idx / TILE, l = idx - m * TILE;
     const int cc = c0 + l;
-    xs[idx] = cc < cells ? T(x[int64_t(m) * cells + cc]) : T(0);
+    const T v = T(x[int64_t(m) * cells + (cc < cells ? cc : cells - 1)]);  // clamped: no branch around the load
+    xs[idx] = cc < cells ? v : T(0);
   }
   __syncthreads();
   const int c = c0 + cl;
@@ -70,22 +76,40 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   const int ext[3] = {nx, ny, nz};
   const int stride[3] = {1, nx, nx * ny};
   const T st = sT[c], sa = sA[c];
+  // Upwind neighbours of every direction this thread owns, requested
+  // together: addresses are clamped to a valid element and a neighbour
+  // outside the grid (the inflow, carried by b) is zeroed afterwards, so no
+  // branch separates the loads.
   T xc[DPT], str[DPT], acc[DPT];
+  T xnb[DPT][3];
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
     const int m = slot + DSLOTS * q;
-    xc[q] = str[q] = acc[q] = T(0);
-    if (m >= N) continue;
-    const int64_t o = int64_t(m) * cells + c;
-    xc[q] = xs[m * TILE + cl];
+    const int mc = m < N ? m : N - 1;
+    const int64_t o = int64_t(mc) * cells + c;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int sgn = sg[4 * m + a];
-      if (sgn == 0) continue;
+      if (a == 2 && nz == 1) {
+        xnb[q][a] = T(0);
+        continue;
+      }
+      const int sgn = sg[4 * mc + a];
       const int p = pos[a] - sgn;
-      const T xn = (p >= 0 && p < ext[a]) ? T(x[o - sgn * stride[a]]) : T(0);
-      str[q] += dc[4 * m + a] * (xc[q] - xn);
+      const bool inb = p >= 0 && p < ext[a];
+      const T v = T(x[inb ? o - sgn * stride[a] : o]);
+      xnb[q][a] = inb ? v : T(0);
     }
+  }
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + DSLOTS * q;
+    const int mc = m < N ? m : N - 1;
+    xc[q] = xs[mc * TILE + cl];
+    acc[q] = T(0);
+    T sacc = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sacc += dc[4 * mc + a] * (xc[q] - xnb[q][a]);
+    str[q] = sacc;
   }
 #pragma unroll 4
   for (int n = 0; n < N; ++n) {
@@ -109,11 +133,12 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   }
 }
 
-template <class T, class TI, class TO, bool RES, bool LDS_S>
+template <class T, class TI, class TO, bool RES, bool LDS_S, int TL>
 void go_dpt(const Target& Tg, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
             const T* dc, size_t lds, hipStream_t s, const ProfScope& ps) {
   const Operator& op = *Tg.op;
-  const dim3 grid(unsigned((op.cells + TILE - 1) / TILE), 1, unsigned(Tg.sl.count));
+  constexpr int DSLOTS = 256 / TL;
+  const dim3 grid(unsigned((op.cells + TL - 1) / TL), 1, unsigned(Tg.sl.count));
   const int dpt = (op.ndir + DSLOTS - 1) / DSLOTS;
   auto launch = [&](auto kern) {
     launch_k(kern, grid, dim3(256), uint32_t(lds), s, ps, Tg.sl, static_cast<const TI*>(x), static_cast<TO*>(y),
@@ -121,15 +146,15 @@ void go_dpt(const Target& Tg, const void* x, void* y, const double* b, const T* 
              int(op.cells));
   };
   if (dpt <= 1)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 1>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 1, TL>);
   else if (dpt <= 2)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 2>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 2, TL>);
   else if (dpt <= 4)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 4>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 4, TL>);
   else if (dpt <= 8)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 8>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 8, TL>);
   else
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 16>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 16, TL>);
 }
 
 template <class T, class TI, class TO, bool RES>
@@ -145,13 +170,24 @@ void go(const Target& Tg, const void* x, void* y, const double* b, hipStream_t s
     sT = A.sT32; sA = A.sA32; S = A.S32; dc = A.dc32;
   }
   const int N = Tg.op->ndir;
-  const size_t lx = size_t(N) * TILE * sizeof(T);
+  const bool wide = N <= 64;
+  const int tl = wide ? 64 : 16;
+  const size_t lx = size_t(N) * tl * sizeof(T);
   const size_t ls = size_t(N) * (N + 1) * sizeof(T);
   constexpr size_t kLds = 48 * 1024;
-  if (lx + ls <= kLds)
-    go_dpt<T, TI, TO, RES, true>(Tg, x, y, b, sT, sA, S, dc, lx + ls, s, ps);
-  else
-    go_dpt<T, TI, TO, RES, false>(Tg, x, y, b, sT, sA, S, dc, lx, s, ps);
+  const bool lds_s = lx + ls <= kLds;
+  const size_t lds = lds_s ? lx + ls : lx;
+  if (wide) {
+    if (lds_s)
+      go_dpt<T, TI, TO, RES, true, 64>(Tg, x, y, b, sT, sA, S, dc, lds, s, ps);
+    else
+      go_dpt<T, TI, TO, RES, false, 64>(Tg, x, y, b, sT, sA, S, dc, lds, s, ps);
+  } else {
+    if (lds_s)
+      go_dpt<T, TI, TO, RES, true, 16>(Tg, x, y, b, sT, sA, S, dc, lds, s, ps);
+    else
+      go_dpt<T, TI, TO, RES, false, 16>(Tg, x, y, b, sT, sA, S, dc, lds, s, ps);
+  }
   RTE_HIP(hipGetLastError());
 }
 

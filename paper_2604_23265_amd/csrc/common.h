@@ -9,6 +9,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rte.h"
@@ -98,11 +99,18 @@ __device__ inline bool slot_open(const Slots& sl, int z, SlotBase& b) {
   return (sl.gate ? d->occupied : d->live) != 0;
 }
 
+// p + base (bytes).  On the device the sum is formed by byte-pointer
+// arithmetic on the kernel argument, so the compiler still knows the
+// result points to global memory (and keeps global, not flat, loads).
 template <class T>
 __host__ __device__ inline T* at(T* p, uint64_t base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<C*>(p) + base);
+#else
   return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + base);
+#endif
 }
-
 
 // ------------------------------------------------------------ the model ---
 // A convolution in GEMM layout: w[tap][cout][cin] (input channels fastest).
@@ -308,7 +316,7 @@ inline void launch_k(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t 
 // solver internals shared with the server
 struct SolveLayout {
   int k;
-  int64_t n;
+  int64_t n, ldv, ldz;
   int nblk;
   size_t off_x, off_b, off_V, off_Z, off_part1, off_part2, off_partn, off_small, off_mg, total;
   size_t mg_bytes;

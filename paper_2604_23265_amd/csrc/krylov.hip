@@ -54,15 +54,47 @@ __device__ inline void load_column(const double* __restrict__ V, int64_t ldv, in
   for (int i = 0; i < NV; ++i) v[i] = V[int64_t(i < nv ? i : nv - 1) * ldv + e];
 }
 
-// Block sums of acc[0 .. cnt-1] (cnt uniform) written to part[blk][base + i].
-template <int NV>
-__device__ inline void block_store(double* acc, int cnt, double* __restrict__ part, int base, double* red) {
+// Block sums of acc[0 .. NV-1] (NV a power of two <= 64), the first cnt of
+// them written to part[blk][i].  Within a wave a reduce-scatter halves the
+// values each lane carries at every butterfly step (lane bit set: keep the
+// upper half), so after log2(NV) steps each lane holds one index, named by
+// its high lane bits; the remaining steps add the lanes that share an
+// index.  About NV shuffles instead of 6 NV.  The four waves' partials then
+// meet in LDS and are added in wave order.  The order of every addition is
+// fixed, so results are reproducible.
+template <int M, int O>
+__device__ inline void reduce_scatter(double* acc, int lane, int& idx) {
+  if constexpr (O >= 1) {
+    if constexpr (M > 1) {
+      constexpr int H = M / 2;
+      const bool up = (lane & O) != 0;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    if (i < cnt) {  // uniform: every thread reaches the same barriers
-      const double s = block_sum(acc[i], red);
-      if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + base + i] = s;
+      for (int k = 0; k < H; ++k) {
+        const double send = up ? acc[k] : acc[k + H];
+        const double keep = up ? acc[k + H] : acc[k];
+        acc[k] = keep + __shfl_xor(send, O, 64);
+      }
+      if (up) idx += H;
+      reduce_scatter<H, O / 2>(acc, lane, idx);
+    } else {
+      acc[0] += __shfl_xor(acc[0], O, 64);
+      reduce_scatter<1, O / 2>(acc, lane, idx);
     }
+  }
+}
+
+template <int NV>
+__device__ inline void block_store(double* acc, int cnt, double* __restrict__ part, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int idx = 0;  // index whose wave sum this lane ends up holding
+  reduce_scatter<NV, 32>(acc, lane, idx);
+  __syncthreads();
+  constexpr int LANES_PER = 64 / NV;  // lanes sharing an index; one of them writes
+  if ((lane & (LANES_PER - 1)) == 0) red[wave * NV + idx] = acc[0];
+  __syncthreads();
+  if (int(threadIdx.x) < cnt) {
+    const int i = threadIdx.x;
+    part[int64_t(blockIdx.x) * HMAX + i] = ((red[i] + red[NV + i]) + red[2 * NV + i]) + red[3 * NV + i];
   }
 }
 
@@ -76,7 +108,7 @@ __global__ __launch_bounds__(KT) void dots_kernel(Slots sl, const double* __rest
   V = at(V, bs.ws);
   w = at(w, bs.ws);
   part = at(part, bs.ws);
-  __shared__ double red[KT / 64];
+  __shared__ double red[4 * NV];
   int64_t beg, end;
   chunk_of(n, nblk, beg, end);
   double acc[NV];
@@ -89,7 +121,7 @@ __global__ __launch_bounds__(KT) void dots_kernel(Slots sl, const double* __rest
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] += v[i] * we;
   }
-  block_store<NV>(acc, nv, part, 0, red);
+  block_store<NV>(acc, nv, part, red);
 }
 
 // First Gram-Schmidt correction and the second pass's dots in one read of
@@ -107,7 +139,8 @@ __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __re
   h = at(h, bs.ws);
   w = at(w, bs.ws);
   part = at(part, bs.ws);
-  __shared__ double red[KT / 64];
+  __shared__ double red[4 * NV];
+  __shared__ double rww[KT / 64];
   __shared__ double hs[NV];
   if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
   __syncthreads();
@@ -136,9 +169,9 @@ __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __re
     w[e] = x;
     ww += x * x;
   }
-  block_store<NV>(acc, nv, part, 0, red);
-  const double s = block_sum(ww, red);
+  const double s = block_sum(ww, rww);
   if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + nv] = s;
+  block_store<NV>(acc, nv, part, red);
 }
 
 // Second correction and normalisation: w = (w - sum_i h_i V_i) * f[0].
@@ -361,10 +394,10 @@ unsigned ew_grid(int64_t n) {
 
 }  // namespace
 
-// Partial-sum blocks for a length-n reduction: about 1024 elements per block
-// (four per thread), at most 2048 blocks; depends on n only.
+// Partial-sum blocks for a length-n reduction: about 2048 elements per block
+// (eight per thread), at most 2048 blocks; depends on n only.
 int krylov_blocks(int64_t n) {
-  int64_t b = (n + 1023) / 1024;
+  int64_t b = (n + 2047) / 2048;
   if (b < 1) b = 1;
   if (b > 2048) b = 2048;
   return int(b);

@@ -758,9 +758,9 @@ __device__ inline float diag_of(const float* dc, const float* Sd, float st, floa
   return dc[4 * m + 3] + st * (1.f - smm) + sa * smm;
 }
 
-constexpr int PT = 16;  // pixels per block of the lift / projection kernels
+constexpr int PT = 64;  // pixels per block of the lift kernel
 
-// f0[p][c] = sum_m Win[c][m] v[m][p] / d[m][p] for a tile of 16 pixels; when
+// f0[p][c] = sum_m Win[c][m] v[m][p] / d[m][p] for a tile of 64 pixels; when
 // t0 is given also t0 = ainv0 (.) f0 (the first smoothing step's input).
 // LDS holds v~ as [m][pixel] and W_in transposed as [m][c], so the
 // channel-fastest thread order reads consecutive banks.
@@ -791,14 +791,15 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
     wt[m * C0 + c] = Win[idx];
   }
   {
+    // loads at a clamped pixel, zeroed afterwards: no branch around them
     const int64_t p = p0 + (threadIdx.x & (PT - 1));
-    const float st = p < P ? sT[p] : 0.f, sa = p < P ? sA[p] : 0.f;
+    const int64_t pc = p < P ? p : P - 1;
+    const float st = sT[pc], sa = sA[pc];
 #pragma unroll 4
     for (int idx = threadIdx.x; idx < N * PT; idx += 256) {
       const int m = idx / PT;
-      float val = 0.f;
-      if (p < P) val = float(v[int64_t(m) * P + p]) / diag_of(dc, Sd, st, sa, m);
-      vt[idx] = val;
+      const float val = float(v[int64_t(m) * P + pc]) / diag_of(dc, Sd, st, sa, m);
+      vt[idx] = p < P ? val : 0.f;
     }
   }
   __syncthreads();
@@ -815,10 +816,11 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
   }
 }
 
-// z[m][p] = s v[m][p] / d[m][p] + sum_c Wout[m][c] u0[p][c] for 16 pixels:
-// thread t owns pixel t % 16 and directions t / 16 + 16 q; u0 rows are
-// padded in LDS (conflict-free) and v is requested before the sum.
-template <int DPT>
+// z[m][p] = s v[m][p] / d[m][p] + sum_c Wout[m][c] u0[p][c] for PP pixels
+// (64 for up to 64 directions, else 16): thread t owns pixel t % PP and
+// directions t / PP + (256 / PP) q; u0 rows are padded in LDS
+// (conflict-free) and v is requested before the sum.
+template <int DPT, int PP>
 __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __restrict__ v,
                                                    const float* __restrict__ u0, const float* __restrict__ sT,
                                                    const float* __restrict__ sA, const float* __restrict__ dc,
@@ -835,24 +837,27 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
   Sd = at(Sd, bs.op);
   extern __shared__ float sm[];
   const int ld = C0 + 1;
-  float* us = sm;              // [PT][C0 + 1]
-  float* ws = sm + PT * ld;    // [N][C0]
-  const int64_t p0 = int64_t(blockIdx.x) * PT;
-  for (int idx = threadIdx.x; idx < PT * C0; idx += 256) {
+  float* us = sm;              // [PP][C0 + 1]
+  float* ws = sm + PP * ld;    // [N][C0]
+  const int64_t p0 = int64_t(blockIdx.x) * PP;
+  for (int idx = threadIdx.x; idx < PP * C0; idx += 256) {
     const int pl = idx / C0, c = idx - pl * C0;
     const int64_t p = p0 + pl;
-    us[pl * ld + c] = p < P ? u0[p * C0 + c] : 0.f;
+    const float u = u0[(p < P ? p : P - 1) * C0 + c];
+    us[pl * ld + c] = p < P ? u : 0.f;
   }
 #pragma unroll 4
   for (int idx = threadIdx.x; idx < N * C0; idx += 256) ws[idx] = Wout[idx];
-  const int pl = threadIdx.x & (PT - 1);
-  const int slot = threadIdx.x / PT;
+  const int pl = threadIdx.x & (PP - 1);
+  const int slot = PP == 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / PP) : int(threadIdx.x) / PP;
+  constexpr int NSLOT = 256 / PP;
   const int64_t p = p0 + pl;
   double vv[DPT];
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
-    const int m = slot + 16 * q;
-    vv[q] = (p < P && m < N) ? v[int64_t(m) * P + p] : 0.0;
+    const int m = slot + NSLOT * q;
+    const double val = v[int64_t(m < N ? m : N - 1) * P + (p < P ? p : P - 1)];
+    vv[q] = (p < P && m < N) ? val : 0.0;
   }
   __syncthreads();
   if (p >= P) return;
@@ -865,13 +870,13 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
     const float u = us[pl * ld + c];
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
-      const int m = slot + 16 * q;
+      const int m = slot + NSLOT * q;
       if (m < N) acc[q] += ws[m * C0 + c] * u;
     }
   }
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
-    const int m = slot + 16 * q;
+    const int m = slot + NSLOT * q;
     if (m >= N) break;
     const int64_t o = int64_t(m) * P + p;
     z[o] = sc * (float(vv[q]) / diag_of(dc, Sd, st, sa, m)) + acc[q];
@@ -1124,24 +1129,27 @@ void launch_lift(const Target& T, const Model& m, const double* v, float* f0, co
 
 void launch_proj(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s) {
   const Operator& op = *T.op;
-  const size_t lds = (size_t(PT) * (m.c0 + 1) + size_t(op.ndir) * m.c0) * sizeof(float);
+  const bool wide = op.ndir <= 64;
+  const int pp = wide ? 64 : 16;
+  const size_t lds = (size_t(pp) * (m.c0 + 1) + size_t(op.ndir) * m.c0) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "projection tile does not fit in LDS");
-  const dim3 grid(unsigned((op.cells + PT - 1) / PT), 1, unsigned(T.sl.count));
-  const int dpt = (op.ndir + 15) / 16;
+  RTE_REQUIRE(op.ndir <= 256, RTE_EINVAL, "too many directions for the projection");
+  const dim3 grid(unsigned((op.cells + pp - 1) / pp), 1, unsigned(T.sl.count));
+  const int dpt = (op.ndir + 256 / pp - 1) / (256 / pp);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
                        T.arr.Sdiag32, m.d_w_out, m.s, z, op.ndir, m.c0, op.cells);
   };
-  if (dpt <= 1)
-    go(proj_kernel<1>);
-  else if (dpt <= 2)
-    go(proj_kernel<2>);
-  else if (dpt <= 4)
-    go(proj_kernel<4>);
-  else if (dpt <= 8)
-    go(proj_kernel<8>);
-  else
-    go(proj_kernel<16>);
+  if (wide) {
+    if (dpt <= 1) go(proj_kernel<1, 64>);
+    else if (dpt <= 2) go(proj_kernel<2, 64>);
+    else if (dpt <= 4) go(proj_kernel<4, 64>);
+    else if (dpt <= 8) go(proj_kernel<8, 64>);
+    else go(proj_kernel<16, 64>);
+  } else {
+    if (dpt <= 8) go(proj_kernel<8, 16>);
+    else go(proj_kernel<16, 16>);
+  }
   RTE_HIP(hipGetLastError());
 }
 

@@ -140,8 +140,13 @@ SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet) 
   size_t off = 256;
   L.off_x = off; off += align256(size_t(op.n) * 8);
   L.off_b = off; off += align256(size_t(op.n) * 8);
-  L.off_V = off; off += align256(size_t(k + 1) * op.n * 8);
-  L.off_Z = off; off += align256(size_t(k) * op.n * 4);
+  // basis vectors sit ldv (ldz) elements apart: a multiple of 256 bytes
+  // plus 256, so the same element of successive vectors does not fall on
+  // the same HBM channel (a power-of-two spacing would)
+  L.ldv = ((op.n + 31) / 32) * 32 + 32;
+  L.ldz = ((op.n + 63) / 64) * 64 + 64;
+  L.off_V = off; off += align256(size_t(k + 1) * L.ldv * 8);
+  L.off_Z = off; off += align256(size_t(k) * L.ldz * 4);
   L.off_part1 = off; off += align256(size_t(L.nblk) * HMAX * 8);
   L.off_part2 = off; off += align256(size_t(L.nblk) * HMAX * 8);
   L.off_partn = off; off += align256(size_t(L.nblk) * HMAX * 8);
@@ -375,7 +380,7 @@ void Batch::boundary() {
   double* partn = off<double>(lay_.off_partn);
   double* stat = off<double>(q.stat);
   launch_lsq(so, off<double>(q.H), off<double>(q.g), 0, k, off<double>(q.y), s_);
-  launch_xupdate(so, x, off<float>(lay_.off_Z), n, off<double>(q.y), 0, n, s_);
+  launch_xupdate(so, x, off<float>(lay_.off_Z), lay_.ldz, off<double>(q.y), 0, n, s_);
   launch_dots(so, b, n, 1, b, n, partn, nb, s_);
   launch_start_cycle(so, partn, nb, nullptr, k, stat, s_);
   launch_copy_f64(so, stat + 4, off<double>(q.bn), 1, s_);
@@ -484,9 +489,10 @@ void Batch::step_body(int j, int zc, hipStream_t s) {
   const int nb = lay_.nblk, k = k_;
   const Small q = small_of(lay_);
   double* V = off<double>(lay_.off_V);
-  const double* Vj = V + size_t(j) * n;
-  double* Vn = V + size_t(j + 1) * n;
-  float* Zj = off<float>(lay_.off_Z) + size_t(j) * n;
+  const int64_t ldv = lay_.ldv;
+  const double* Vj = V + size_t(j) * ldv;
+  double* Vn = V + size_t(j + 1) * ldv;
+  float* Zj = off<float>(lay_.off_Z) + size_t(j) * lay_.ldz;
   double* part1 = off<double>(lay_.off_part1);
   double* part2 = off<double>(lay_.off_part2);
   double* h1 = off<double>(q.h1);
@@ -497,13 +503,13 @@ void Batch::step_body(int j, int zc, hipStream_t s) {
   else
     launch_cast_f64_f32(sl, Vj, Zj, n, s);
   launch_apply(T, Zj, 0, Vn, 1, nullptr, false, s);
-  launch_dots(sl, V, n, j + 1, Vn, n, part1, nb, s);
+  launch_dots(sl, V, ldv, j + 1, Vn, n, part1, nb, s);
   launch_reduce(sl, part1, nb, j + 1, h1, s);
-  launch_updots(sl, V, n, j + 1, h1, Vn, n, part2, nb, s);
+  launch_updots(sl, V, ldv, j + 1, h1, Vn, n, part2, nb, s);
   launch_reduce(sl, part2, nb, j + 2, h2, s);
   launch_finish_step(sl, h1, h2, j, k, off<double>(q.H), off<double>(q.cs), off<double>(q.sn), off<double>(q.g),
                      off<double>(q.bn), stat, s);
-  launch_update_scale(sl, V, n, j + 1, h2, Vn, n, stat + 3, s);
+  launch_update_scale(sl, V, ldv, j + 1, h2, Vn, n, stat + 3, s);
 }
 
 namespace {
