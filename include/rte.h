@@ -176,8 +176,9 @@ typedef struct {
   double ms_total;        /* wall time of the solve                               */
 } rte_solve_stats;
 
-/* Workspace for rte_solve: Krylov bases V (FP64, k+1 vectors), Z (FP32, k
- * vectors), reduction scratch and, for MgNet, the level activations.
+/* Workspace for rte_solve: a one-slot batch table, the iterate and right-hand
+ * side (FP64), Krylov bases V (FP64, k+1 vectors), Z (FP32, k vectors),
+ * reduction scratch and, for MgNet, the level activations.
  * Errors: RTE_EINVAL. */
 rte_status rte_workspace_bytes(const rte_operator* op, const mgnet_model* model,
                                const rte_solve_opts* opts, size_t* bytes);
@@ -187,7 +188,8 @@ rte_status rte_workspace_bytes(const rte_operator* op, const mgnet_model* model,
  * operator applies and preconditioning in FP32 (or BF16 convolutions),
  * orthogonalisation (two-pass classical Gram-Schmidt), Hessenberg least
  * squares and the restart residual b - L x in FP64 on the device.
- * psi_out: device double [n], the solution x (also used as the iterate).
+ * psi_out: device double [n], the solution x (written when the solve ends;
+ * the iterate lives in the workspace, so x0 may alias psi_out).
  * stats (host) is filled on RTE_OK, RTE_ENOCONV and RTE_EBREAKDOWN.
  * Blocks the calling thread until the solve ends.
  * Errors: RTE_EINVAL, RTE_ENOMEM (workspace smaller than required),
@@ -197,20 +199,27 @@ rte_status rte_solve(const rte_operator* op, const mgnet_model* model, const rte
                      void* stream);
 
 /* ---- serving: continuous batching of independent solves ----
- * A server owns a worker thread and `max_slots` HIP streams.  Requests are
- * admitted in arrival order when a slot is free and their workspace fits in
- * the caller-provided device arena (admission by HBM footprint); admitted
- * solves advance concurrently, one Krylov step per slot per scheduling
- * round, and retire as they finish, freeing slot and arena space for the
- * next request.  Each solve runs exactly the kernels rte_solve runs, so its
- * result does not depend on what else is in flight. */
+ * A server owns a worker thread.  Requests are admitted in arrival order
+ * while fewer than `max_slots` solves are active and the request's
+ * workspace fits in the caller-provided device arena (admission by HBM
+ * footprint).  Admitted requests of one shape (grid, directions, model,
+ * restart length, preconditioner) form a batch: every kernel launch of a
+ * batch covers all of its solves, a request that arrives while the batch
+ * runs joins at its next restart boundary, and a solve that meets its
+ * tolerance stops taking steps without a host round trip.  Batches of
+ * different shapes run on streams of their own and overlap on the device.
+ * Finished solves free their arena range for the next request.  Each solve
+ * performs exactly the arithmetic rte_solve performs, so its result does not
+ * depend on what else is in flight (bitwise). */
 typedef struct {
   int64_t submitted, completed, active, queued;
   size_t arena_bytes, arena_in_use, arena_peak;
 } rte_server_stats;
 
 /* arena: device memory of arena_bytes owned by the caller, which must
- * outlive the server.  max_slots: 1..64.  Errors: RTE_EINVAL, RTE_EDEVICE. */
+ * outlive the server; per-solve workspaces and each batch's slot table come
+ * from it.  max_slots: 1..64, the most solves active at once and the width
+ * of a batch.  Errors: RTE_EINVAL, RTE_EDEVICE. */
 rte_status rte_server_create(void* arena, size_t arena_bytes, int max_slots, rte_server** out);
 /* Queue a solve.  op, model and psi_out (device double [n]) must stay valid
  * until the ticket is polled as finished.  Errors: RTE_EINVAL, RTE_ENOMEM
