@@ -133,6 +133,118 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   }
 }
 
+// FP32 apply with one direction slot per wave (up to 128 directions): a
+// block owns 64 consecutive cells, lane = cell, wave w = directions w,
+// w + 4, ... (at most DPT of them).  The scatter's matrix entries are then
+// the same for the whole wave and come from scalar loads of the slot-packed
+// S (one LDS read of x_n feeds DPT FMAs); upwind neighbours are requested
+// at clamped addresses before the scatter and zeroed outside the grid.
+template <class TO, int DPT, bool D3>
+__global__ __launch_bounds__(256) void apply_slot_kernel(Slots sl, const float* __restrict__ x, TO* __restrict__ y,
+                                                         const float* __restrict__ sT, const float* __restrict__ sA,
+                                                         const float* __restrict__ Sp, const float* __restrict__ dc,
+                                                         const int* __restrict__ sg, int N, int nx, int ny, int nz,
+                                                         int cells) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  x = at(x, bs.ws);
+  y = at(y, bs.ws);
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  Sp = at(Sp, bs.op);
+  dc = at(dc, bs.op);
+  sg = at(sg, bs.op);
+  constexpr int NA = D3 ? 3 : 2;
+  extern __shared__ float xs[];  // [N][64]
+  const int lane = threadIdx.x & 63;
+  const int slot = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int c0 = int(blockIdx.x) * 64;
+  const int c = c0 + lane;
+  const int cc = c < cells ? c : cells - 1;
+  // stage x[:, tile]: this thread's rows are its own directions, so the
+  // loads of all of them are issued together
+  float xown[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    const float v = x[int64_t(m < N ? m : N - 1) * cells + cc];
+    xown[q] = c < cells ? v : 0.f;
+  }
+  const int rr = cc / nx;
+  const int i = cc - rr * nx;
+  const int k = rr / ny;
+  const int j = rr - k * ny;
+  const int pos[3] = {i, j, k};
+  const int ext[3] = {nx, ny, nz};
+  const int stride[3] = {1, nx, nx * ny};
+  float xnb[DPT][NA];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    const int mc = m < N ? m : N - 1;
+    const int64_t o = int64_t(mc) * cells + cc;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int sgn = sg[4 * mc + a];
+      const int p = pos[a] - sgn;
+      const bool inb = p >= 0 && p < ext[a];
+      const float v = x[inb ? o - sgn * stride[a] : o];
+      xnb[q][a] = inb ? v : 0.f;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    if (m < N) xs[m * 64 + lane] = xown[q];
+  }
+  __syncthreads();
+  float acc[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) acc[q] = 0.f;
+  const float* __restrict__ sp = Sp + slot * N * DPT;
+#pragma unroll 2
+  for (int n = 0; n < N; ++n) {
+    const float xv = xs[n * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) acc[q] += sp[n * DPT + q] * xv;
+  }
+  if (c >= cells) return;
+  const float st = sT[c], sa = sA[c];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    if (m >= N) break;
+    const float xc = xown[q];
+    float str = 0.f;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) str += dc[4 * m + a] * (xc - xnb[q][a]);
+    const float val = str + st * (xc - acc[q]) + sa * acc[q];
+    y[int64_t(m) * cells + c] = TO(val);
+  }
+}
+
+template <class TO, bool D3>
+void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const ProfScope& ps) {
+  const Operator& op = *Tg.op;
+  const OpArrays& A = Tg.arr;
+  const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(Tg.sl.count));
+  const size_t lds = size_t(op.ndir) * 64 * sizeof(float);
+  auto launch = [&](auto kern) {
+    launch_k(kern, grid, dim3(256), uint32_t(lds), s, ps, Tg.sl, static_cast<const float*>(x), static_cast<TO*>(y),
+             A.sT32, A.sA32, A.Sp32, A.dc32, static_cast<const int*>(A.dsgn), op.ndir, op.nx, op.ny, op.nz,
+             int(op.cells));
+  };
+  switch (slot_budget(op.ndir)) {
+    case 1: launch(apply_slot_kernel<TO, 1, D3>); break;
+    case 2: launch(apply_slot_kernel<TO, 2, D3>); break;
+    case 4: launch(apply_slot_kernel<TO, 4, D3>); break;
+    case 8: launch(apply_slot_kernel<TO, 8, D3>); break;
+    case 16: launch(apply_slot_kernel<TO, 16, D3>); break;
+    default: launch(apply_slot_kernel<TO, 32, D3>); break;
+  }
+  RTE_HIP(hipGetLastError());
+}
+
 template <class T, class TI, class TO, bool RES, bool LDS_S, int TL>
 void go_dpt(const Target& Tg, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
             const T* dc, size_t lds, hipStream_t s, const ProfScope& ps) {
@@ -210,6 +322,12 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
   if (fp64) {
     RTE_REQUIRE(tin == 1 && tout == 1, RTE_EINVAL, "FP64 apply takes FP64 vectors");
     go<double, double, double, false>(Tg, x, y, nullptr, s, ps);
+  } else if (tin == 0 && Tg.arr.Sp32 && slot_budget(op.ndir) > 0) {
+    const bool d3 = op.nz > 1;
+    if (tout == 0)
+      d3 ? go_slot<float, true>(Tg, x, y, s, ps) : go_slot<float, false>(Tg, x, y, s, ps);
+    else
+      d3 ? go_slot<double, true>(Tg, x, y, s, ps) : go_slot<double, false>(Tg, x, y, s, ps);
   } else if (tin == 0 && tout == 0) {
     go<float, float, float, false>(Tg, x, y, nullptr, s, ps);
   } else if (tin == 0 && tout == 1) {

@@ -140,6 +140,11 @@ struct Model {
   DevArena* dev = nullptr;
   const float* d_w_in = nullptr;
   const float* d_w_out = nullptr;
+  // the 1x1 weights by wave slot: W_in as [4][ndir][c0/4] (entry (s, m, q) =
+  // W_in[s + 4q][m]); W_out as [4][c0][slot_budget(ndir)] (entry (s, c, q) =
+  // W_out[s + 4q][c], zero past ndir)
+  const float* d_w_in_p = nullptr;
+  const float* d_w_out_p = nullptr;
   std::vector<const float*> d_CW, d_CB, d_HAW, d_HAB, d_HIW, d_HIB;
   void ensure_on_device();  // uploads once, on the current device
   ~Model();
@@ -147,6 +152,16 @@ struct Model {
 
 // --------------------------------------------------------- the operator ---
 constexpr int MAX_LEVELS = 8;
+
+// Kernels that give each of a block's four waves one "direction slot" (the
+// directions s, s + 4, s + 8, ...) hold ceil(N / 4) values per thread,
+// rounded up to a compile-time budget; 0 when N is beyond the largest.
+inline int slot_budget(int N) {
+  const int need = (N + 3) / 4;
+  for (int b : {1, 2, 4, 8, 16, 32})
+    if (need <= b) return b;
+  return 0;
+}
 
 // The operator's device arrays.  They live in one block whose layout
 // depends only on the shape (dim, grid, directions, model levels and
@@ -163,6 +178,7 @@ struct OpArrays {
   double* dc64 = nullptr;
   int* dsgn = nullptr;        // per direction: sign(u_x), sign(u_y), sign(u_z)   [N][4]
   float* Sdiag32 = nullptr;   // S_mm                    [N]
+  float* Sp32 = nullptr;      // S by direction slot: [4][N][slot_budget(N)], entry (s, n, q) = S_{s+4q, n}
   float* fa[MAX_LEVELS] = {};     // CoeffNet fields per level [cells_l][C_l]
   float* fainv[MAX_LEVELS] = {};
 };

@@ -111,6 +111,21 @@ void Model::ensure_on_device() {
     for (auto& c : Bc) up(c);
     d_w_in = a->upload(w_in);
     d_w_out = a->upload(w_out);
+    {
+      const int cq = c0 / 4, dp = slot_budget(ndir);
+      std::vector<float> wi(size_t(4) * ndir * cq), wo(size_t(4) * c0 * (dp > 0 ? dp : 0), 0.f);
+      for (int sl = 0; sl < 4; ++sl)
+        for (int m = 0; m < ndir; ++m)
+          for (int q = 0; q < cq; ++q) wi[(size_t(sl) * ndir + m) * cq + q] = w_in[size_t(sl + 4 * q) * ndir + m];
+      for (int sl = 0; sl < 4 && dp > 0; ++sl)
+        for (int c = 0; c < c0; ++c)
+          for (int q = 0; q < dp; ++q) {
+            const int m = sl + 4 * q;
+            if (m < ndir) wo[(size_t(sl) * c0 + c) * dp + q] = w_out[size_t(m) * c0 + c];
+          }
+      d_w_in_p = a->upload(wi);
+      if (!wo.empty()) d_w_out_p = a->upload(wo);
+    }
     for (int l = 0; l < levels; ++l) {
       d_CW.push_back(a->upload(CW[l]));
       d_CB.push_back(a->upload(CB[l]));

@@ -28,6 +28,7 @@
 //   RESID_T out = a^{-1} (.) (f - conv - a (.) u)
 //   STORE_T out = conv, out2 = a^{-1} (.) conv
 #include <algorithm>
+#include <type_traits>
 #include <cstring>
 
 #include "common.h"
@@ -883,6 +884,151 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
   }
 }
 
+// Lift and projection with one direction (or channel) slot per wave: a
+// block owns 64 pixels, lane = pixel, wave w = rows w, w + 4, ... of the
+// 1x1 weights, which are then wave-uniform and come from scalar loads of
+// the slot-packed copies (one LDS read feeds CQ or DPT FMAs).  The lift's
+// channels-last output goes through LDS so its stores are coalesced.
+// Same sums, in the same order, as lift_kernel / proj_kernel.
+template <int CQ, int DPT>
+__global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* __restrict__ v,
+                                                        const float* __restrict__ sT, const float* __restrict__ sA,
+                                                        const float* __restrict__ dc, const float* __restrict__ Sd,
+                                                        const float* __restrict__ Wp, float* __restrict__ f0,
+                                                        const float* __restrict__ ainv, float* __restrict__ t0, int N,
+                                                        int64_t P) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  v = at(v, bs.ws);
+  f0 = at(f0, bs.ws);
+  if (t0) {
+    t0 = at(t0, bs.ws);
+    ainv = at(ainv, bs.op);
+  }
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  dc = at(dc, bs.op);
+  Sd = at(Sd, bs.op);
+  constexpr int C0 = 4 * CQ;
+  extern __shared__ float sm[];  // [N][64] scaled v, then [64][C0 + 1] output
+  const int lane = threadIdx.x & 63;
+  const int slot = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int64_t p0 = int64_t(blockIdx.x) * 64;
+  const int64_t p = p0 + lane;
+  const int64_t pc = p < P ? p : P - 1;
+  const float st = sT[pc], sa = sA[pc];
+  double vo[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    vo[q] = v[int64_t(m < N ? m : N - 1) * P + pc];
+  }
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    if (m < N) sm[m * 64 + lane] = p < P ? float(vo[q]) / diag_of(dc, Sd, st, sa, m) : 0.f;
+  }
+  __syncthreads();
+  float acc[CQ];
+#pragma unroll
+  for (int q = 0; q < CQ; ++q) acc[q] = 0.f;
+  const float* __restrict__ wp = Wp + slot * N * CQ;
+#pragma unroll 2
+  for (int m = 0; m < N; ++m) {
+    const float xv = sm[m * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) acc[q] += wp[m * CQ + q] * xv;
+  }
+  __syncthreads();
+  constexpr int LD = C0 + 1;
+#pragma unroll
+  for (int q = 0; q < CQ; ++q) sm[lane * LD + slot + 4 * q] = acc[q];
+  __syncthreads();
+  float ai[CQ];
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int idx = int(threadIdx.x) + 256 * k;
+    const int pl = idx / C0, c = idx - (idx / C0) * C0;
+    const int64_t pp = p0 + pl;
+    ai[k] = t0 ? ainv[(pp < P ? pp : P - 1) * C0 + c] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int idx = int(threadIdx.x) + 256 * k;
+    const int pl = idx / C0, c = idx - (idx / C0) * C0;
+    const int64_t pp = p0 + pl;
+    if (pp >= P) continue;
+    const float val = sm[pl * LD + c];
+    f0[pp * C0 + c] = val;
+    if (t0) t0[pp * C0 + c] = ai[k] * val;
+  }
+}
+
+template <int DPT, int CQ>
+__global__ __launch_bounds__(256) void proj_slot_kernel(Slots sl, const double* __restrict__ v,
+                                                        const float* __restrict__ u0, const float* __restrict__ sT,
+                                                        const float* __restrict__ sA, const float* __restrict__ dc,
+                                                        const float* __restrict__ Sd, const float* __restrict__ Wp,
+                                                        float sc, float* __restrict__ z, int N, int64_t P) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  v = at(v, bs.ws);
+  u0 = at(u0, bs.ws);
+  z = at(z, bs.ws);
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  dc = at(dc, bs.op);
+  Sd = at(Sd, bs.op);
+  constexpr int C0 = 4 * CQ;
+  constexpr int LD = C0 + 1;
+  extern __shared__ float us[];  // [64][C0 + 1]
+  const int lane = threadIdx.x & 63;
+  const int slot = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int64_t p0 = int64_t(blockIdx.x) * 64;
+  const int64_t p = p0 + lane;
+  const int64_t pc = p < P ? p : P - 1;
+  float ut[CQ];
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int idx = int(threadIdx.x) + 256 * k;
+    const int pl = idx / C0, c = idx - (idx / C0) * C0;
+    const int64_t pp = p0 + pl;
+    const float u = u0[(pp < P ? pp : P - 1) * C0 + c];
+    ut[k] = pp < P ? u : 0.f;
+  }
+  double vv[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    vv[q] = v[int64_t(m < N ? m : N - 1) * P + pc];
+  }
+#pragma unroll
+  for (int k = 0; k < CQ; ++k) {
+    const int idx = int(threadIdx.x) + 256 * k;
+    const int pl = idx / C0, c = idx - (idx / C0) * C0;
+    us[pl * LD + c] = ut[k];
+  }
+  __syncthreads();
+  float acc[DPT];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) acc[q] = 0.f;
+  const float* __restrict__ wp = Wp + slot * C0 * DPT;
+#pragma unroll 2
+  for (int c = 0; c < C0; ++c) {
+    const float u = us[lane * LD + c];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) acc[q] += wp[c * DPT + q] * u;
+  }
+  if (p >= P) return;
+  const float st = sT[p], sa = sA[p];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int m = slot + 4 * q;
+    if (m >= N) break;
+    z[int64_t(m) * P + p] = sc * (float(vv[q]) / diag_of(dc, Sd, st, sa, m)) + acc[q];
+  }
+}
+
 __global__ void scale_fields_kernel(Slots sl, const float* __restrict__ ainv, const float* __restrict__ f,
                                     float* __restrict__ t, int64_t n) {
   SlotBase bs;
@@ -1116,9 +1262,67 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   RTE_HIP(hipGetLastError());
 }
 
+namespace {
+// Dispatch of the slot-per-wave lift / projection; false when the shape has
+// no instantiation (the 16-pixel kernels run instead).
+template <int DPT>
+bool lift_slot_go(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
+                  hipStream_t s) {
+  const Operator& op = *T.op;
+  const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(T.sl.count));
+  const size_t lds = std::max(size_t(op.ndir) * 64, size_t(64) * (m.c0 + 1)) * sizeof(float);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, T.arr.sT32, T.arr.sA32, T.arr.dc32, T.arr.Sdiag32,
+                       m.d_w_in_p, f0, ainv, t0, op.ndir, op.cells);
+  };
+  switch (m.c0 / 4) {
+    case 4: go(lift_slot_kernel<4, DPT>); return true;
+    case 8: go(lift_slot_kernel<8, DPT>); return true;
+    case 12: go(lift_slot_kernel<12, DPT>); return true;
+    case 16: go(lift_slot_kernel<16, DPT>); return true;
+    case 32: go(lift_slot_kernel<32, DPT>); return true;
+    default: return false;
+  }
+}
+template <int DPT>
+bool proj_slot_go(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s) {
+  const Operator& op = *T.op;
+  const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(T.sl.count));
+  const size_t lds = size_t(64) * (m.c0 + 1) * sizeof(float);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+                       T.arr.Sdiag32, m.d_w_out_p, m.s, z, op.ndir, op.cells);
+  };
+  switch (m.c0 / 4) {
+    case 4: go(proj_slot_kernel<DPT, 4>); return true;
+    case 8: go(proj_slot_kernel<DPT, 8>); return true;
+    case 12: go(proj_slot_kernel<DPT, 12>); return true;
+    case 16: go(proj_slot_kernel<DPT, 16>); return true;
+    case 32: go(proj_slot_kernel<DPT, 32>); return true;
+    default: return false;
+  }
+}
+template <class F>
+bool by_budget(int N, F&& f) {
+  switch (slot_budget(N)) {
+    case 1: return f(std::integral_constant<int, 1>());
+    case 2: return f(std::integral_constant<int, 2>());
+    case 4: return f(std::integral_constant<int, 4>());
+    case 8: return f(std::integral_constant<int, 8>());
+    case 16: return f(std::integral_constant<int, 16>());
+    case 32: return f(std::integral_constant<int, 32>());
+    default: return false;
+  }
+}
+}  // namespace
+
 void launch_lift(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
                  hipStream_t s) {
   const Operator& op = *T.op;
+  if (m.d_w_in_p && by_budget(op.ndir, [&](auto b) { return lift_slot_go<decltype(b)::value>(T, m, v, f0, ainv, t0, s); })) {
+    RTE_HIP(hipGetLastError());
+    return;
+  }
   const size_t lds = (size_t(op.ndir) * PT + size_t(m.c0) * op.ndir) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "lift tile does not fit in LDS");
   const dim3 grid(unsigned((op.cells + PT - 1) / PT), 1, unsigned(T.sl.count));
@@ -1129,6 +1333,10 @@ void launch_lift(const Target& T, const Model& m, const double* v, float* f0, co
 
 void launch_proj(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s) {
   const Operator& op = *T.op;
+  if (m.d_w_out_p && by_budget(op.ndir, [&](auto b) { return proj_slot_go<decltype(b)::value>(T, m, v, u0, z, s); })) {
+    RTE_HIP(hipGetLastError());
+    return;
+  }
   const bool wide = op.ndir <= 64;
   const int pp = wide ? 64 : 16;
   const size_t lds = (size_t(pp) * (m.c0 + 1) + size_t(op.ndir) * m.c0) * sizeof(float);

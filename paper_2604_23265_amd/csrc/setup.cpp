@@ -37,6 +37,7 @@ OpArrays Operator::relative() const {
   r.dc64 = rel(a.dc64);
   r.dsgn = rel(a.dsgn);
   r.Sdiag32 = rel(a.Sdiag32);
+  r.Sp32 = rel(a.Sp32);
   for (int l = 0; l < MAX_LEVELS; ++l) {
     r.fa[l] = rel(a.fa[l]);
     r.fainv[l] = rel(a.fainv[l]);
@@ -264,6 +265,16 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
     const size_t o_S64 = take(size_t(N) * N * 8), o_S32 = take(size_t(N) * N * 4);
     const size_t o_dc64 = take(dc.size() * 8), o_dc32 = take(dc.size() * 4), o_sg = take(sg.size() * 4);
     const size_t o_sd = take(size_t(N) * 4);
+    // S packed by direction slot for the one-slot-per-wave apply
+    const int dp = slot_budget(N);
+    std::vector<float> Sp(size_t(4) * N * (dp > 0 ? dp : 0), 0.f);
+    for (int sl = 0; sl < 4 && dp > 0; ++sl)
+      for (int n = 0; n < N; ++n)
+        for (int q = 0; q < dp; ++q) {
+          const int m = sl + 4 * q;
+          if (m < N) Sp[(size_t(sl) * N + n) * dp + q] = float(op->S[size_t(m) * N + n]);
+        }
+    const size_t o_sp = take(Sp.size() * 4);
     size_t o_fa[MAX_LEVELS] = {}, o_fi[MAX_LEVELS] = {};
     for (int l = 0; l < op->levels; ++l) {
       const size_t bytes = size_t(op->level_cells(l)) * (op->c0 << l) * 4;
@@ -288,6 +299,7 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
     op->a.dc32 = reinterpret_cast<float*>(put(o_dc32, dc32.data(), dc32.size() * 4));
     op->a.dsgn = reinterpret_cast<int*>(put(o_sg, sg.data(), sg.size() * 4));
     op->a.Sdiag32 = reinterpret_cast<float*>(put(o_sd, Sd.data(), Sd.size() * 4));
+    if (!Sp.empty()) op->a.Sp32 = reinterpret_cast<float*>(put(o_sp, Sp.data(), Sp.size() * 4));
     for (int l = 0; l < op->levels; ++l) {
       op->a.fa[l] = reinterpret_cast<float*>(B + o_fa[l]);
       op->a.fainv[l] = reinterpret_cast<float*>(B + o_fi[l]);
