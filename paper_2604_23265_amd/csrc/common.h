@@ -252,14 +252,18 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s);
 void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride);
 void convT4_setup(ConvLaunch& c, int dim, const int in_dim[3]);
 
-void launch_lift(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
-                 hipStream_t s);
-void launch_proj(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s);
+// vscale (nullable, workspace-relative under a slot table): v is taken times
+// vscale[0]
+void launch_lift(const Target& T, const Model& m, const double* v, const double* vscale, float* f0,
+                 const float* ainv, float* t0, hipStream_t s);
+void launch_proj(const Target& T, const Model& m, const double* v, const double* vscale, const float* u0,
+                 float* z, hipStream_t s);
 void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count,
                          hipStream_t s);
 void launch_fill_f32(const Slots& sl, float* p, float v, int64_t count, hipStream_t s);
 void launch_fill_f64(const Slots& sl, double* p, double v, int64_t count, hipStream_t s);
-void launch_cast_f64_f32(const Slots& sl, const double* src, float* dst, int64_t count, hipStream_t s);
+void launch_cast_f64_f32(const Slots& sl, const double* src, const double* scale, float* dst, int64_t count,
+                         hipStream_t s);
 void launch_copy_f64(const Slots& sl, const double* src, double* dst, int64_t count, hipStream_t s);
 
 // CoeffNet (setup)
@@ -274,6 +278,10 @@ int krylov_blocks(int64_t n);
 void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* w, int64_t n,
                  double* part, int nblk, hipStream_t s);
 void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double* out, hipStream_t s);
+// Lagged CGS2, first pass of step j >= 1: V[j] <- (V[j] - sum_{i<j} h_i V_i) * fsc[0]
+// (completing the previous basis vector), then part: V_i^T w for i <= j.
+void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int j, const double* h, const double* fsc,
+                        const double* w, int64_t n, double* part, int nblk, hipStream_t s);
 // w <- w - V h; part: V^T w (first nv) and w.w (index nv)
 void launch_updots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
                    int64_t n, double* part, int nblk, hipStream_t s);
@@ -344,7 +352,7 @@ SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet);
 size_t precond_bytes(const Operator& op, const Model& m);
 void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o);
 void precond_apply(const Target& T, const Model& m, int kind, const double* v, float* z, char* ws,
-                   hipStream_t s);
+                   hipStream_t s, const double* vscale = nullptr);
 
 // Device tables of a batch: the slot descriptors and the per-slot report.
 size_t batch_table_bytes(int capacity);

@@ -174,6 +174,62 @@ __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __re
   block_store<NV>(acc, nv, part, red);
 }
 
+// First pass of step j >= 1 of the lagged CGS2: complete the previous basis
+// vector in place, V[j] <- (V[j] - sum_{i<j} h_i V_i) * fsc[0], and in the
+// same read of V form part[blk][i] = V_i . w for i <= j (V_j completed).
+// The column of V_0 .. V_{j-1} is held (HOLD) or reloaded as in updots.
+template <int NV, bool HOLD>
+__global__ __launch_bounds__(KT) void finish_dots_kernel(Slots sl, double* __restrict__ V, int64_t ldv, int j,
+                                                         const double* __restrict__ h,
+                                                         const double* __restrict__ fsc,
+                                                         const double* __restrict__ w, int64_t n,
+                                                         double* __restrict__ part, int nblk) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  V = at(V, bs.ws);
+  h = at(h, bs.ws);
+  fsc = at(fsc, bs.ws);
+  w = at(w, bs.ws);
+  part = at(part, bs.ws);
+  __shared__ double red[4 * NV];
+  __shared__ double ru[KT / 64];
+  __shared__ double hs[NV];
+  if (threadIdx.x < NV) hs[threadIdx.x] = int(threadIdx.x) < j ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  const double sc = fsc[0];
+  double* __restrict__ Vj = V + int64_t(j) * ldv;
+  int64_t beg, end;
+  chunk_of(n, nblk, beg, end);
+  double acc[NV];
+  double accu = 0.0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
+    const double we = w[e];
+    double u = Vj[e];
+    if constexpr (HOLD) {
+      double v[NV];
+      load_column<NV>(V, ldv, j, e, v);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) u -= hs[i] * v[i];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v[i] * we;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) u -= hs[i] * V[int64_t(i < j ? i : j - 1) * ldv + e];
+      __asm__ volatile("" ::: "memory");  // compiler fence: reload the column, do not keep it live
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += V[int64_t(i < j ? i : j - 1) * ldv + e] * we;
+    }
+    u *= sc;
+    Vj[e] = u;
+    accu += u * we;
+  }
+  const double su = block_sum(accu, ru);
+  if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + j] = su;
+  block_store<NV>(acc, j, part, red);
+}
+
 // Second correction and normalisation: w = (w - sum_i h_i V_i) * f[0].
 template <int NV>
 __global__ __launch_bounds__(KT) void update_scale_kernel(Slots sl, const double* __restrict__ V, int64_t ldv,
@@ -275,6 +331,8 @@ __global__ void finish_kernel(Slots sl, const double* __restrict__ h1, const dou
   stat[1] = double(flags);
   stat[2] = hn;
   stat[3] = hn > 0 ? 1.0 / hn : 0.0;
+  // the next preconditioner input is w1 / ||w1|| (w1 left in V[j + 1])
+  stat[5] = h2[j + 1] > 0 ? 1.0 / sqrt(h2[j + 1]) : 0.0;
   if (!isfinite(stat[0])) {
     flags |= 1;
     stat[1] = double(flags);
@@ -314,6 +372,7 @@ __global__ __launch_bounds__(KT) void start_cycle_kernel(Slots sl, const double*
   if (g) g[0] = beta;
   stat[3] = beta > 0 ? 1.0 / beta : 0.0;
   stat[4] = beta;
+  stat[5] = 1.0;  // v_0 = r / beta is complete: the first preconditioner input needs no scale
 }
 
 __global__ void scale_kernel(Slots sl, double* __restrict__ w, const double* __restrict__ f, int64_t n) {
@@ -438,6 +497,27 @@ void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const do
 void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double* out, hipStream_t s) {
   ProfScope ps(RTE_K_ORTH, s, true);
   launch_k(reduce_kernel, z3(unsigned(nv), sl), dim3(KT), 0, s, ps, sl, part, nblk, out);
+  RTE_HIP(hipGetLastError());
+}
+
+namespace {
+template <int NV>
+void fdots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, double* V, int64_t ldv, int j,
+              const double* h, const double* fsc, const double* w, int64_t n, double* part, int nblk) {
+  launch_k(finish_dots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
+}
+}  // namespace
+
+void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int j, const double* h, const double* fsc,
+                        const double* w, int64_t n, double* part, int nblk, hipStream_t s) {
+  RTE_REQUIRE(j >= 1 && j <= 64, RTE_EINVAL, "too many basis vectors");
+  ProfScope ps(RTE_K_ORTH, s, true);
+  ps.work = 8.0 * double(n) * (j + 3);  // V_0..V_{j-1}, V_j read and written, w
+  const dim3 g = z3(unsigned(nblk), sl);
+  if (j <= 8) fdots_go<8>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
+  else if (j <= 16) fdots_go<16>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
+  else if (j <= 32) fdots_go<32>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
+  else fdots_go<64>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 

@@ -766,6 +766,7 @@ constexpr int PT = 64;  // pixels per block of the lift kernel
 // LDS holds v~ as [m][pixel] and W_in transposed as [m][c], so the
 // channel-fastest thread order reads consecutive banks.
 __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __restrict__ v,
+                                                   const double* __restrict__ vs,
                                                    const float* __restrict__ sT, const float* __restrict__ sA,
                                                    const float* __restrict__ dc, const float* __restrict__ Sd,
                                                    const float* __restrict__ Win, float* __restrict__ f0,
@@ -774,6 +775,7 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   v = at(v, bs.ws);
+  const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   f0 = at(f0, bs.ws);
   if (t0) {
     t0 = at(t0, bs.ws);
@@ -799,7 +801,7 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
 #pragma unroll 4
     for (int idx = threadIdx.x; idx < N * PT; idx += 256) {
       const int m = idx / PT;
-      const float val = float(v[int64_t(m) * P + pc]) / diag_of(dc, Sd, st, sa, m);
+      const float val = float(v[int64_t(m) * P + pc] * vsc) / diag_of(dc, Sd, st, sa, m);
       vt[idx] = p < P ? val : 0.f;
     }
   }
@@ -823,6 +825,7 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
 // (conflict-free) and v is requested before the sum.
 template <int DPT, int PP>
 __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __restrict__ v,
+                                                   const double* __restrict__ vs,
                                                    const float* __restrict__ u0, const float* __restrict__ sT,
                                                    const float* __restrict__ sA, const float* __restrict__ dc,
                                                    const float* __restrict__ Sd, const float* __restrict__ Wout,
@@ -830,6 +833,7 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   v = at(v, bs.ws);
+  const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   u0 = at(u0, bs.ws);
   z = at(z, bs.ws);
   sT = at(sT, bs.op);
@@ -880,7 +884,7 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
     const int m = slot + NSLOT * q;
     if (m >= N) break;
     const int64_t o = int64_t(m) * P + p;
-    z[o] = sc * (float(vv[q]) / diag_of(dc, Sd, st, sa, m)) + acc[q];
+    z[o] = sc * (float(vv[q] * vsc) / diag_of(dc, Sd, st, sa, m)) + acc[q];
   }
 }
 
@@ -892,6 +896,7 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
 // Same sums, in the same order, as lift_kernel / proj_kernel.
 template <int CQ, int DPT>
 __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* __restrict__ v,
+                                                        const double* __restrict__ vs,
                                                         const float* __restrict__ sT, const float* __restrict__ sA,
                                                         const float* __restrict__ dc, const float* __restrict__ Sd,
                                                         const float* __restrict__ Wp, float* __restrict__ f0,
@@ -900,6 +905,7 @@ __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* 
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   v = at(v, bs.ws);
+  const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   f0 = at(f0, bs.ws);
   if (t0) {
     t0 = at(t0, bs.ws);
@@ -926,7 +932,7 @@ __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* 
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
     const int m = slot + 4 * q;
-    if (m < N) sm[m * 64 + lane] = p < P ? float(vo[q]) / diag_of(dc, Sd, st, sa, m) : 0.f;
+    if (m < N) sm[m * 64 + lane] = p < P ? float(vo[q] * vsc) / diag_of(dc, Sd, st, sa, m) : 0.f;
   }
   __syncthreads();
   float acc[CQ];
@@ -966,6 +972,7 @@ __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* 
 
 template <int DPT, int CQ>
 __global__ __launch_bounds__(256) void proj_slot_kernel(Slots sl, const double* __restrict__ v,
+                                                        const double* __restrict__ vs,
                                                         const float* __restrict__ u0, const float* __restrict__ sT,
                                                         const float* __restrict__ sA, const float* __restrict__ dc,
                                                         const float* __restrict__ Sd, const float* __restrict__ Wp,
@@ -973,6 +980,7 @@ __global__ __launch_bounds__(256) void proj_slot_kernel(Slots sl, const double* 
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   v = at(v, bs.ws);
+  const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   u0 = at(u0, bs.ws);
   z = at(z, bs.ws);
   sT = at(sT, bs.op);
@@ -1025,7 +1033,7 @@ __global__ __launch_bounds__(256) void proj_slot_kernel(Slots sl, const double* 
   for (int q = 0; q < DPT; ++q) {
     const int m = slot + 4 * q;
     if (m >= N) break;
-    z[int64_t(m) * P + p] = sc * (float(vv[q]) / diag_of(dc, Sd, st, sa, m)) + acc[q];
+    z[int64_t(m) * P + p] = sc * (float(vv[q] * vsc) / diag_of(dc, Sd, st, sa, m)) + acc[q];
   }
 }
 
@@ -1049,13 +1057,15 @@ __global__ void fill_kernel(Slots sl, T* p, T v, int64_t n) {
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
 }
 
-__global__ void cast_kernel(Slots sl, const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+__global__ void cast_kernel(Slots sl, const double* __restrict__ a, const double* __restrict__ scale,
+                            float* __restrict__ b, int64_t n) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   a = at(a, bs.ws);
   b = at(b, bs.ws);
+  const double sc = scale ? at(scale, bs.ws)[0] : 1.0;
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (; i < n; i += int64_t(gridDim.x) * blockDim.x) b[i] = float(a[i]);
+  for (; i < n; i += int64_t(gridDim.x) * blockDim.x) b[i] = float(a[i] * sc);
 }
 
 __global__ void copy64_kernel(Slots sl, const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -1266,14 +1276,14 @@ namespace {
 // Dispatch of the slot-per-wave lift / projection; false when the shape has
 // no instantiation (the 16-pixel kernels run instead).
 template <int DPT>
-bool lift_slot_go(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
-                  hipStream_t s) {
+bool lift_slot_go(const Target& T, const Model& m, const double* v, const double* vs, float* f0,
+                  const float* ainv, float* t0, hipStream_t s) {
   const Operator& op = *T.op;
   const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(T.sl.count));
   const size_t lds = std::max(size_t(op.ndir) * 64, size_t(64) * (m.c0 + 1)) * sizeof(float);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, T.arr.sT32, T.arr.sA32, T.arr.dc32, T.arr.Sdiag32,
-                       m.d_w_in_p, f0, ainv, t0, op.ndir, op.cells);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, vs, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+                       T.arr.Sdiag32, m.d_w_in_p, f0, ainv, t0, op.ndir, op.cells);
   };
   switch (m.c0 / 4) {
     case 4: go(lift_slot_kernel<4, DPT>); return true;
@@ -1285,12 +1295,13 @@ bool lift_slot_go(const Target& T, const Model& m, const double* v, float* f0, c
   }
 }
 template <int DPT>
-bool proj_slot_go(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s) {
+bool proj_slot_go(const Target& T, const Model& m, const double* v, const double* vs, const float* u0, float* z,
+                  hipStream_t s) {
   const Operator& op = *T.op;
   const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(T.sl.count));
   const size_t lds = size_t(64) * (m.c0 + 1) * sizeof(float);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, vs, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
                        T.arr.Sdiag32, m.d_w_out_p, m.s, z, op.ndir, op.cells);
   };
   switch (m.c0 / 4) {
@@ -1316,24 +1327,27 @@ bool by_budget(int N, F&& f) {
 }
 }  // namespace
 
-void launch_lift(const Target& T, const Model& m, const double* v, float* f0, const float* ainv, float* t0,
-                 hipStream_t s) {
+void launch_lift(const Target& T, const Model& m, const double* v, const double* vs, float* f0,
+                 const float* ainv, float* t0, hipStream_t s) {
   const Operator& op = *T.op;
-  if (m.d_w_in_p && by_budget(op.ndir, [&](auto b) { return lift_slot_go<decltype(b)::value>(T, m, v, f0, ainv, t0, s); })) {
+  if (m.d_w_in_p &&
+      by_budget(op.ndir, [&](auto b) { return lift_slot_go<decltype(b)::value>(T, m, v, vs, f0, ainv, t0, s); })) {
     RTE_HIP(hipGetLastError());
     return;
   }
   const size_t lds = (size_t(op.ndir) * PT + size_t(m.c0) * op.ndir) * sizeof(float);
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "lift tile does not fit in LDS");
   const dim3 grid(unsigned((op.cells + PT - 1) / PT), 1, unsigned(T.sl.count));
-  hipLaunchKernelGGL(lift_kernel, grid, dim3(256), lds, s, T.sl, v, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+  hipLaunchKernelGGL(lift_kernel, grid, dim3(256), lds, s, T.sl, v, vs, T.arr.sT32, T.arr.sA32, T.arr.dc32,
                      T.arr.Sdiag32, m.d_w_in, f0, ainv, t0, op.ndir, m.c0, op.cells);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_proj(const Target& T, const Model& m, const double* v, const float* u0, float* z, hipStream_t s) {
+void launch_proj(const Target& T, const Model& m, const double* v, const double* vs, const float* u0,
+                 float* z, hipStream_t s) {
   const Operator& op = *T.op;
-  if (m.d_w_out_p && by_budget(op.ndir, [&](auto b) { return proj_slot_go<decltype(b)::value>(T, m, v, u0, z, s); })) {
+  if (m.d_w_out_p &&
+      by_budget(op.ndir, [&](auto b) { return proj_slot_go<decltype(b)::value>(T, m, v, vs, u0, z, s); })) {
     RTE_HIP(hipGetLastError());
     return;
   }
@@ -1345,7 +1359,7 @@ void launch_proj(const Target& T, const Model& m, const double* v, const float* 
   const dim3 grid(unsigned((op.cells + pp - 1) / pp), 1, unsigned(T.sl.count));
   const int dpt = (op.ndir + 256 / pp - 1) / (256 / pp);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, vs, u0, T.arr.sT32, T.arr.sA32, T.arr.dc32,
                        T.arr.Sdiag32, m.d_w_out, m.s, z, op.ndir, m.c0, op.cells);
   };
   if (wide) {
@@ -1381,8 +1395,9 @@ void launch_fill_f64(const Slots& sl, double* p, double v, int64_t count, hipStr
   RTE_HIP(hipGetLastError());
 }
 
-void launch_cast_f64_f32(const Slots& sl, const double* src, float* dst, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(cast_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, src, dst, count);
+void launch_cast_f64_f32(const Slots& sl, const double* src, const double* scale, float* dst, int64_t count,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, src, scale, dst, count);
   RTE_HIP(hipGetLastError());
 }
 

@@ -30,7 +30,7 @@ size_t precond_bytes(const Operator& op, const Model& m) {
 // and the projection plus the diagonal skip.  A smoothing step is two
 // launches: t = a^{-1} (.) (f - A * u - a (.) u) and u += B * t.
 void precond_apply(const Target& T, const Model& m, int kind, const double* v, float* z, char* ws,
-                   hipStream_t s) {
+                   hipStream_t s, const double* vscale) {
   ProfScope ps(RTE_K_PRECOND, s);
   const Operator& op = *T.op;
   const Slots& sl = T.sl;
@@ -79,7 +79,7 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
   };
 
   const bool want0 = first_steps(0) > 0;
-  launch_lift(T, m, v, f[0], want0 ? T.arr.fainv[0] : nullptr, want0 ? t[0] : nullptr, s);
+  launch_lift(T, m, v, vscale, f[0], want0 ? T.arr.fainv[0] : nullptr, want0 ? t[0] : nullptr, s);
   tready[0] = want0;
   for (int l = 0; l < L - 1; ++l) {
     uz[l] = true;
@@ -118,7 +118,7 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
     for (const ConvW& B : m.Bpost[l]) smooth(l, B);
   }
   if (uz[0]) launch_fill_f32(sl, u[0], 0.f, P[0] * C[0], s);
-  launch_proj(T, m, v, u[0], z, s);
+  launch_proj(T, m, v, vscale, u[0], z, s);
 }
 
 constexpr int HMAX = 65;
@@ -479,9 +479,18 @@ void Batch::decide() {
   phase_ = STEPS;
 }
 
-// Arnoldi step j for every live slot: z_j = M(v_j); w = L z_j; CGS2
-// against v_0..v_j in three passes (h1 = V^T w; w1 = w - V h1 with
-// h2 = V^T w1 and ||w1||^2; v_{j+1} = (w1 - V h2) / ||w1 - V h2||); Givens.
+// Arnoldi step j for every live slot, with the second Gram-Schmidt
+// correction of each new basis vector lagged into the next step:
+//   the previous step left w1 = w - V h1 (once corrected, unnormalised) in
+//   V[j]; the preconditioner takes v^_j = w1 / ||w1|| (stat[5]), which is
+//   all flexible GMRES needs of its input (Z_j = M(v^_j) is what enters
+//   A Z = V H);
+//   pass 1 completes v_j = (w1 - V h2) / ||w1 - V h2|| (stat[3], h2 from the
+//   previous step) in place and forms h1 = V^T w in the same read of V;
+//   pass 2 forms w1 = w - V h1 with h2 = V^T w1 and ||w1||^2 in one read;
+//   the finishing kernel sets column j of H (h1 + h2 over
+//   ||w1 - V h2|| = sqrt(||w1||^2 - ||h2||^2)) and the Givens rotation.
+// Two passes over V per step instead of three.
 void Batch::step_body(int j, int zc, hipStream_t s) {
   const Slots sl{tab_, zc, 0};
   const Target T{&shape_, rel_, sl};
@@ -490,7 +499,7 @@ void Batch::step_body(int j, int zc, hipStream_t s) {
   const Small q = small_of(lay_);
   double* V = off<double>(lay_.off_V);
   const int64_t ldv = lay_.ldv;
-  const double* Vj = V + size_t(j) * ldv;
+  double* Vj = V + size_t(j) * ldv;
   double* Vn = V + size_t(j + 1) * ldv;
   float* Zj = off<float>(lay_.off_Z) + size_t(j) * lay_.ldz;
   double* part1 = off<double>(lay_.off_part1);
@@ -499,17 +508,19 @@ void Batch::step_body(int j, int zc, hipStream_t s) {
   double* h2 = off<double>(q.h2);
   double* stat = off<double>(q.stat);
   if (mg_)
-    precond_apply(T, *m_, kind_, Vj, Zj, off<char>(lay_.off_mg), s);
+    precond_apply(T, *m_, kind_, Vj, Zj, off<char>(lay_.off_mg), s, stat + 5);
   else
-    launch_cast_f64_f32(sl, Vj, Zj, n, s);
+    launch_cast_f64_f32(sl, Vj, stat + 5, Zj, n, s);
   launch_apply(T, Zj, 0, Vn, 1, nullptr, false, s);
-  launch_dots(sl, V, ldv, j + 1, Vn, n, part1, nb, s);
+  if (j == 0)
+    launch_dots(sl, V, ldv, 1, Vn, n, part1, nb, s);
+  else
+    launch_finish_dots(sl, V, ldv, j, h2, stat + 3, Vn, n, part1, nb, s);
   launch_reduce(sl, part1, nb, j + 1, h1, s);
   launch_updots(sl, V, ldv, j + 1, h1, Vn, n, part2, nb, s);
   launch_reduce(sl, part2, nb, j + 2, h2, s);
   launch_finish_step(sl, h1, h2, j, k, off<double>(q.H), off<double>(q.cs), off<double>(q.sn), off<double>(q.g),
                      off<double>(q.bn), stat, s);
-  launch_update_scale(sl, V, ldv, j + 1, h2, Vn, n, stat + 3, s);
 }
 
 namespace {
