@@ -1,6 +1,7 @@
 """End-to-end oracle solve: build, precondition, FGMRES (test infrastructure)."""
 import numpy as np
 
+from . import comparators
 from . import discretisation as dsc
 from . import krylov, network
 
@@ -21,8 +22,13 @@ class Problem:
     def precond(self, v):
         return network.vcycle(self.net, self.fields, self.diag, v, self.D).reshape(-1)
 
-    def solve(self, rtol=1e-10, restart=30, max_iters=20000, use_net=True, record=None):
-        M = self.precond if (use_net and self.net is not None) else None
+    def block_jacobi(self, v):
+        return comparators.block_jacobi(self.D, v).reshape(-1)
+
+    def solve(self, rtol=1e-10, restart=30, max_iters=20000, use_net=True, record=None, precond=None):
+        """precond: "net" (the default when a network is loaded), "bj" or "none"."""
+        kind = precond if precond is not None else ("net" if (use_net and self.net is not None) else "none")
+        M = {"net": self.precond, "bj": self.block_jacobi, "none": None}[kind]
         x, st = krylov.fgmres(self.apply, self.b.reshape(-1), M, restart, rtol, max_iters,
                               record=record)
         return x.reshape(self.D.N, self.D.cells), st

@@ -392,3 +392,50 @@ def test_arnoldi_identities_and_preconditioned_solution():
     # preconditioning changes the path, not the answer
     x0, _ = P.solve(rtol=1e-12, restart=15, use_net=False)
     assert np.linalg.norm(x - x0) / np.linalg.norm(x0) < 1e-9
+
+
+# ------------------------------------ Block-Jacobi comparator (pin 11) ---
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_block_jacobi_blocks_are_the_diagonal_blocks_of_L(dim):
+    """The formula-built cell blocks equal the cell-diagonal blocks of the dense
+    operator assembled column by column from apply_L."""
+    from oracle import comparators
+    prob = problems.make(n=3, ndir=8, dim=dim, eps=0.3, seed=5, nz=2 if dim == 3 else None)
+    D = dsc.Discretisation(prob)
+    A = direct.dense_matrix(D)
+    B = comparators.cell_blocks(D)
+    for c in range(D.cells):
+        idx = np.arange(D.N) * D.cells + c
+        assert np.allclose(A[np.ix_(idx, idx)], B[c], rtol=0, atol=1e-12 * np.abs(A).max())
+
+
+def test_block_jacobi_is_exact_on_one_cell():
+    """On a one-cell grid L has no neighbour couplings: Block-Jacobi is L^{-1}."""
+    prob = problems.make(n=1, ndir=8, eps=0.05, seed=2, sigma_t=3.0)
+    P = osolve.Problem(prob)
+    v = np.random.default_rng(3).normal(size=P.D.n)
+    z = P.block_jacobi(v)
+    exact = np.linalg.solve(direct.dense_matrix(P.D), v)
+    assert np.linalg.norm(z - exact) <= 1e-12 * np.linalg.norm(exact)
+
+
+def test_block_jacobi_without_scattering_is_the_diagonal():
+    """sS = 0 (sigma_a = sigma_T / eps^2): each block is diagonal, z = v / (stream + sT)."""
+    eps, st = 0.5, 2.0
+    prob = problems.make(n=4, ndir=8, eps=eps, sigma_t=st, sigma_a=st / eps ** 2, seed=1)
+    P = osolve.Problem(prob)
+    assert np.abs(P.D.sS).max() < 1e-12
+    v = np.random.default_rng(4).normal(size=(P.D.N, P.D.cells))
+    stream = np.abs(P.D.dirs[:, :2]).sum(axis=1) / P.D.h
+    z = P.block_jacobi(v).reshape(P.D.N, P.D.cells)
+    assert np.allclose(z, v / (stream[:, None] + P.D.sT[None, :]), rtol=1e-13, atol=0)
+
+
+def test_block_jacobi_fgmres_reaches_the_lu_solution():
+    prob = problems.make(n=6, ndir=8, eps=0.1, seed=7)
+    P = osolve.Problem(prob)
+    x, st = P.solve(rtol=1e-12, restart=20, precond="bj")
+    assert st["converged"]
+    ref = direct.lu_solve(P.D)
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-9
