@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true",
+                    help="skip the Block-Jacobi and unpreconditioned batches")
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
     ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
     ap.add_argument("--serving-requests", type=int, default=0, help="requests of the C3 stream (0 = skip)")
@@ -196,7 +198,8 @@ def main():
 
     def batch(mode):
         """One step: every instance of the batch submitted at once and solved to rtol."""
-        tk = [srv.submit(op, o, model=model, precond=mode, **kw) for op, o in zip(ops, outs)]
+        mdl = model if mode in ("bf16", "fp32") else None
+        tk = [srv.submit(op, o, model=mdl, precond=mode, **kw) for op, o in zip(ops, outs)]
         res = {}
         while len(res) < len(tk):
             for x in tk:
@@ -300,6 +303,20 @@ def main():
                             "latency_ms": {"p50": percentile([s["ms_total"] for s in sts32], 50),
                                            "p99": percentile([s["ms_total"] for s in sts32], 99)}}
         out["bf16_over_fp32"] = value / out["fp32_path"]["value"]
+    if not args.no_comparators:
+        # the paper's comparators on the same batch: cell-wise Block-Jacobi
+        # and no preconditioner (one timed batch each)
+        comp = {}
+        for mode, label in (("bj", "block_jacobi"), ("none", "unpreconditioned")):
+            log("timed: 1 batch of %s solves" % label)
+            dtc, stc, _ = run(mode, 1)
+            comp[label] = {"value": args.batch / dtc, "unit": "solves/s",
+                           "iterations_per_solve": float(np.mean([s["iterations"] for s in stc])),
+                           "ms_per_step": dtc * 1e3}
+        comp["mgnet_bf16_iterations_per_solve"] = float(np.mean(its))
+        comp["note"] = ("FGMRES(30) to the same 1e-6 FP64 residual; the MgNet weights are seeded, not trained, "
+                        "so the iteration counts compare an untrained network with the classical preconditioner")
+        out["comparators"] = comp
     if not args.no_single:
         log("single solves: instance 0 alone, %d times" % args.steps)
         ws = torch.empty(ops[0].workspace_bytes(model, precond="bf16", **kw), dtype=torch.uint8, device="cuda")

@@ -57,9 +57,13 @@ typedef enum {
  * z = 0, else SPHERE. */
 enum { RTE_HG_AUTO = 0, RTE_HG_FLATLAND = 1, RTE_HG_SPHERE = 2 };
 enum { RTE_FP32 = 0, RTE_FP64 = 1 };
-/* Preconditioner of rte_solve: none, MgNet with BF16 MFMA convolutions, or
- * MgNet with FP32 MFMA convolutions (FP32 accumulation in both). */
-enum { RTE_PC_NONE = 0, RTE_PC_MGNET_BF16 = 1, RTE_PC_MGNET_FP32 = 2 };
+/* Preconditioner of rte_solve: none, MgNet with BF16 MFMA convolutions,
+ * MgNet with FP32 MFMA convolutions (FP32 accumulation in both), or the
+ * cell-wise Block-Jacobi comparator of the paper's experiments (Sec. 4):
+ * per cell the N x N block of L coupling that cell's directions,
+ * diag_m(sum_a |u_{m,a}|/h) + sT_c I - sS_c S, solved in FP32 (up to 64
+ * directions; no model needed). */
+enum { RTE_PC_NONE = 0, RTE_PC_MGNET_BF16 = 1, RTE_PC_MGNET_FP32 = 2, RTE_PC_BLOCK_JACOBI = 3 };
 
 typedef struct rte_operator rte_operator;
 typedef struct mgnet_model mgnet_model;
@@ -147,11 +151,12 @@ rte_status rte_apply(const rte_operator* op, const void* x, void* y, int precisi
 rte_status rte_residual(const rte_operator* op, const double* x, double* r, void* stream);
 
 /* z = M(v): one MgNet V-cycle (Sec. 3.3) with the operator's CoeffNet
- * fields.  v: device double [n]; z: device float [n].  precond is
- * RTE_PC_MGNET_BF16 or RTE_PC_MGNET_FP32.  The workspace (device memory of
- * at least rte_precond_workspace_bytes) holds the level activations.
- * Errors: RTE_EINVAL (no fields built, model mismatch), RTE_ENOMEM (small
- * workspace). */
+ * fields (precond RTE_PC_MGNET_BF16 or RTE_PC_MGNET_FP32), or the
+ * Block-Jacobi solve (RTE_PC_BLOCK_JACOBI; model, workspace may be NULL).
+ * v: device double [n]; z: device float [n].  The workspace (device memory
+ * of at least rte_precond_workspace_bytes) holds the level activations.
+ * Errors: RTE_EINVAL (no fields built, model mismatch, more than 64
+ * directions for Block-Jacobi), RTE_ENOMEM (small workspace). */
 rte_status rte_precond_workspace_bytes(const rte_operator* op, const mgnet_model* model,
                                        size_t* bytes);
 rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, int precond,

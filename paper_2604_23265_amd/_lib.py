@@ -11,7 +11,7 @@ STATUS_NAMES = {0: "RTE_OK", -1: "RTE_EINVAL", -2: "RTE_ENOMEM", -3: "RTE_EDEVIC
                 -5: "RTE_EBREAKDOWN", -6: "RTE_EAGAIN", -7: "RTE_EFORMAT", -8: "RTE_ENOTFOUND"}
 HG_AUTO, HG_FLATLAND, HG_SPHERE = 0, 1, 2
 FP32, FP64 = 0, 1
-PC_NONE, PC_MGNET_BF16, PC_MGNET_FP32 = 0, 1, 2
+PC_NONE, PC_MGNET_BF16, PC_MGNET_FP32, PC_BLOCK_JACOBI = 0, 1, 2, 3
 ARR_RHS, ARR_SCATTER, ARR_SIGMA, ARR_FIELD_A, ARR_FIELD_AINV = 0, 1, 2, 3, 4
 K_APPLY, K_RESIDUAL, K_CONV, K_ORTH, K_PRECOND = 0, 1, 2, 3, 4
 

@@ -9,7 +9,7 @@ from . import _lib as L
 from ._lib import check, lib
 
 _KERNEL = {"auto": L.HG_AUTO, "flatland": L.HG_FLATLAND, "sphere": L.HG_SPHERE}
-PRECOND = {"none": L.PC_NONE, "bf16": L.PC_MGNET_BF16, "fp32": L.PC_MGNET_FP32}
+PRECOND = {"none": L.PC_NONE, "bf16": L.PC_MGNET_BF16, "fp32": L.PC_MGNET_FP32, "bj": L.PC_BLOCK_JACOBI}
 
 
 def _torch():
@@ -161,9 +161,14 @@ class Operator:
         return nb.value
 
     def precond(self, model, v, mode="bf16", z=None, workspace=None, stream=None):
+        """z = M(v): the MgNet V-cycle ("bf16", "fp32") or Block-Jacobi ("bj", no model)."""
         torch = _torch()
         if z is None:
             z = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        if mode == "bj":
+            check(lib().rte_precond_apply(self._h, model.handle if model else None, PRECOND[mode], _dptr(v),
+                                          _dptr(z), None, 0, _stream(stream)))
+            return z
         if workspace is None:
             workspace = torch.empty(self.precond_workspace(model), dtype=torch.uint8, device="cuda")
         check(lib().rte_precond_apply(self._h, model.handle, PRECOND[mode], _dptr(v), _dptr(z),
@@ -190,7 +195,7 @@ class Operator:
     def solve(self, model=None, psi=None, workspace=None, stream=None, raise_on_noconv=False, **kw):
         """Returns (psi tensor [n] float64, stats dict)."""
         torch = _torch()
-        if kw.get("precond", "bf16") != "none" and model is None:
+        if kw.get("precond", "bf16") in ("bf16", "fp32") and model is None:
             model = self.model
         o = self.opts(**kw)
         if psi is None:

@@ -267,10 +267,16 @@ rte_status rte_precond_workspace_bytes(const rte_operator* h, const mgnet_model*
 rte_status rte_precond_apply(const rte_operator* h, const mgnet_model* model, int precond, const double* v,
                              float* z, void* ws, size_t ws_bytes, void* stream) {
   return guarded([&] {
-    RTE_REQUIRE(h && model && v && z && ws, RTE_EINVAL, "rte_precond_apply: null argument");
-    RTE_REQUIRE(precond == RTE_PC_MGNET_BF16 || precond == RTE_PC_MGNET_FP32, RTE_EINVAL,
-                "rte_precond_apply: precond must be an MgNet mode");
+    RTE_REQUIRE(h && v && z, RTE_EINVAL, "rte_precond_apply: null argument");
     const Operator& o = *h->op;
+    if (precond == RTE_PC_BLOCK_JACOBI) {
+      RTE_REQUIRE(o.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
+      launch_block_jacobi(Target::single(o), v, nullptr, z, S(stream));
+      return;
+    }
+    RTE_REQUIRE(model && ws, RTE_EINVAL, "rte_precond_apply: null argument");
+    RTE_REQUIRE(precond == RTE_PC_MGNET_BF16 || precond == RTE_PC_MGNET_FP32, RTE_EINVAL,
+                "rte_precond_apply: unknown preconditioner");
     Model& m = *model->m;
     RTE_REQUIRE(o.model == &m, RTE_EINVAL, "operator was not built with this model");
     RTE_REQUIRE(ws_bytes >= precond_bytes(o, m), RTE_ENOMEM, "rte_precond_apply: workspace too small");
@@ -287,7 +293,8 @@ rte_status rte_workspace_bytes(const rte_operator* h, const mgnet_model* model, 
     RTE_REQUIRE(h && opts && bytes, RTE_EINVAL, "rte_workspace_bytes: null argument");
     const Model* m = model ? model->m.get() : nullptr;
     validate_opts(*h->op, m, opts);
-    *bytes = batch_table_bytes(1) + solve_layout(*h->op, m, opts->restart, opts->precond != RTE_PC_NONE).total;
+    const bool mg = opts->precond == RTE_PC_MGNET_BF16 || opts->precond == RTE_PC_MGNET_FP32;
+    *bytes = batch_table_bytes(1) + solve_layout(*h->op, m, opts->restart, mg).total;
   });
 }
 
@@ -301,7 +308,8 @@ rte_status rte_solve(const rte_operator* h, const mgnet_model* model, const rte_
     validate_opts(op, m, opts);
     RTE_REQUIRE(ws != nullptr && psi != nullptr, RTE_EINVAL, "null workspace or output");
     const size_t tb = batch_table_bytes(1);
-    const size_t need = tb + solve_layout(op, m, opts->restart, opts->precond != RTE_PC_NONE).total;
+    const bool mg = opts->precond == RTE_PC_MGNET_BF16 || opts->precond == RTE_PC_MGNET_FP32;
+    const size_t need = tb + solve_layout(op, m, opts->restart, mg).total;
     RTE_REQUIRE(ws_bytes >= need, RTE_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
     RTE_REQUIRE((reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL, "workspace must be 256-byte aligned");
     char* w = static_cast<char*>(ws);

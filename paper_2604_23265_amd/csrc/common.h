@@ -221,6 +221,8 @@ struct ApplyGeom {
 // compute precision follows `fp64`.
 void launch_apply(const Target& T, const void* x, int tin, void* y, int tout, const double* b, bool fp64,
                   hipStream_t s);
+// z = B^{-1} v cell by cell (Block-Jacobi), FP32; v times vscale[0] when given
+void launch_block_jacobi(const Target& T, const double* v, const double* vscale, float* z, hipStream_t s);
 
 // MgNet pieces
 // STORE_T: out = conv and out2 = a^{-1} (.) conv (a level's first smoothing input)
@@ -418,7 +420,7 @@ class Batch {
   std::vector<int64_t> key_;
   const Model* m_;
   int k_, precond_, kind_, cap_;
-  bool mg_;
+  bool mg_, bj_;
   SolveLayout lay_;
   OpArrays rel_;
   SlotDesc* tab_;           // device [cap]

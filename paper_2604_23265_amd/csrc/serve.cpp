@@ -270,7 +270,8 @@ rte_status rte_submit(rte_server* h, const rte_operator* op, const mgnet_model* 
     r->m = m;
     r->o = *opts;
     r->x = psi_out;
-    r->need = Server::align(solve_layout(*r->op, m, opts->restart, opts->precond != RTE_PC_NONE).total);
+    const bool mg = opts->precond == RTE_PC_MGNET_BF16 || opts->precond == RTE_PC_MGNET_FP32;
+    r->need = Server::align(solve_layout(*r->op, m, opts->restart, mg).total);
     RTE_REQUIRE(r->need + Server::align(batch_table_bytes(s.max_slots)) <= s.bytes, RTE_ENOMEM,
                 "request workspace exceeds the arena");
     r->t_submit = now_ms();

@@ -233,9 +233,11 @@ void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o) 
   RTE_REQUIRE(o->restart >= 1 && o->restart <= 64, RTE_EINVAL, "restart must be in [1, 64]");
   RTE_REQUIRE(std::isfinite(o->rtol) && o->rtol > 0, RTE_EINVAL, "rtol must be positive");
   RTE_REQUIRE(o->max_iters >= 1, RTE_EINVAL, "max_iters must be >= 1");
-  RTE_REQUIRE(o->precond >= RTE_PC_NONE && o->precond <= RTE_PC_MGNET_FP32, RTE_EINVAL,
+  RTE_REQUIRE(o->precond >= RTE_PC_NONE && o->precond <= RTE_PC_BLOCK_JACOBI, RTE_EINVAL,
               "unknown preconditioner");
-  if (o->precond != RTE_PC_NONE) {
+  if (o->precond == RTE_PC_BLOCK_JACOBI)
+    RTE_REQUIRE(op.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
+  if (o->precond == RTE_PC_MGNET_BF16 || o->precond == RTE_PC_MGNET_FP32) {
     RTE_REQUIRE(m != nullptr, RTE_EINVAL, "MgNet preconditioning needs a model");
     RTE_REQUIRE(op.model == m, RTE_EINVAL, "operator was not built with this model (CoeffNet fields missing)");
   }
@@ -247,7 +249,8 @@ Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capa
   RTE_REQUIRE(capacity >= 1 && capacity <= 64, RTE_EINVAL, "batch capacity must be in [1, 64]");
   RTE_REQUIRE(tables != nullptr && (reinterpret_cast<uintptr_t>(tables) & 255) == 0, RTE_EINVAL,
               "batch tables must be 256-byte aligned");
-  mg_ = precond != RTE_PC_NONE;
+  mg_ = precond == RTE_PC_MGNET_BF16 || precond == RTE_PC_MGNET_FP32;
+  bj_ = precond == RTE_PC_BLOCK_JACOBI;
   kind_ = precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16;
   lay_ = solve_layout(shape, m, k, mg_);
   rel_ = shape.relative();
@@ -310,8 +313,7 @@ void Batch::upload_all() {
 }
 
 void Batch::add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws, double* out, double t_start) {
-  RTE_REQUIRE(o.restart == k_ && o.precond == precond_ && op.shape_key() == key_ &&
-                  (precond_ == RTE_PC_NONE || op.model == m_),
+  RTE_REQUIRE(o.restart == k_ && o.precond == precond_ && op.shape_key() == key_ && (!mg_ || op.model == m_),
               RTE_EINVAL, "solve does not match the batch");
   RTE_REQUIRE(!full(), RTE_EINVAL, "batch is full");
   RTE_REQUIRE(ws && out && (reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL,
@@ -509,6 +511,8 @@ void Batch::step_body(int j, int zc, hipStream_t s) {
   double* stat = off<double>(q.stat);
   if (mg_)
     precond_apply(T, *m_, kind_, Vj, Zj, off<char>(lay_.off_mg), s, stat + 5);
+  else if (bj_)
+    launch_block_jacobi(T, Vj, stat + 5, Zj, s);
   else
     launch_cast_f64_f32(sl, Vj, stat + 5, Zj, n, s);
   launch_apply(T, Zj, 0, Vn, 1, nullptr, false, s);

@@ -139,7 +139,27 @@ def test_vcycle(name, mode, tol):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("mode", ["none", "fp32", "bf16"])
+def test_block_jacobi(name):
+    """Block-Jacobi (FP32 elimination per cell) against the oracle's FP64 cell solves."""
+    say("case", name, "block-jacobi")
+    prob, model, op, P = setup_case(name)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(P.D.n)
+    z = host(op.precond(None, dev(v), mode="bj")).astype(np.float64)
+    ref = P.block_jacobi(v)
+    err = rel(z, ref)
+    # FP32 elimination of each block is backward stable: its forward error is a
+    # small multiple of cond(B_c) * 2^-24 (C4-like media, eps = 1e-3 and
+    # sigma_T up to 100, give cond ~ 1e3); 1e-5 otherwise (the FP32 path)
+    from oracle import comparators
+    kappa = float(np.linalg.cond(comparators.cell_blocks(P.D)).max())
+    tol = max(1e-5, 4 * kappa * 2.0 ** -24)
+    say("  block-jacobi rel err", err, "cond", kappa, "tol", tol)
+    assert err < tol
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mode", ["none", "fp32", "bf16", "bj"])
 def test_solve_matches_reference(name, mode):
     say("case", name, mode)
     prob, model, op, P = setup_case(name)
@@ -226,6 +246,16 @@ def test_c2_full_apply_and_vcycle(c2_full):
         z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
         say("  vcycle", mode, rel(z, zref))
         assert rel(z, zref) < tol
+
+
+def test_c2_full_block_jacobi(c2_full):
+    prob, model, op, P = c2_full
+    say("case c2 full block-jacobi")
+    x = np.random.default_rng(9).standard_normal(P.D.n)
+    z = host(op.precond(None, dev(x), mode="bj")).astype(np.float64)
+    err = rel(z, P.block_jacobi(x))
+    say("  rel err", err)
+    assert err < 1e-5
 
 
 @pytest.mark.parametrize("mode", ["bf16", "fp32"])
