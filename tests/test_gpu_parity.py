@@ -248,6 +248,43 @@ def test_c2_full_apply_and_vcycle(c2_full):
         assert rel(z, zref) < tol
 
 
+@pytest.fixture(scope="module")
+def c2_trained():
+    """The full C2 workload with the weights trained offline for its family."""
+    import os
+    from paper_2604_23265_amd import api
+    torch_cuda()
+    prob = configs.c2(0)
+    path = os.path.join(os.path.dirname(api.__file__), "weights", "c2_mgnet.mgn1")
+    blob = open(path, "rb").read()
+    model = api.Model(blob)
+    op = api.Operator(prob, model=model)
+    P = osolve.Problem(prob, blob)
+    return prob, model, op, P
+
+
+@pytest.mark.parametrize("mode,tol", [("fp32", 1e-5), ("bf16", 4 * 2.0 ** -8)])
+def test_c2_trained_vcycle(c2_trained, mode, tol):
+    prob, model, op, P = c2_trained
+    say("case c2 trained vcycle", mode)
+    x = np.random.default_rng(12).standard_normal(P.D.n)
+    z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
+    err = rel(z, P.precond(x))
+    say("  rel err", err)
+    assert err < tol
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp32"])
+def test_c2_trained_solve(c2_trained, mode):
+    """Trained weights: the solve meets rtol in the oracle's FP64 residual in a few
+    tens of iterations (the seeded network needs well over a thousand)."""
+    prob, model, op, P = c2_trained
+    x, st = op.solve(model=model, precond=mode, rtol=1e-8, restart=30, max_iters=500)
+    say("  stats", st)
+    assert st["converged"] == 1 and st["iterations"] <= 40
+    assert osolve.relative_residual(P, host(x)) <= 1e-8 * 1.01
+
+
 def test_c2_full_block_jacobi(c2_full):
     prob, model, op, P = c2_full
     say("case c2 full block-jacobi")

@@ -84,3 +84,20 @@ def test_mgn1_layout_and_order():
     size = 48 + sum(8 + 4 * a.ndim + 4 * a.size for a in t.values())
     assert len(blob) == size
     assert np.allclose(t[weights.tag(weights.K_WIN)], np.eye(8))
+
+
+def test_trained_weights_record():
+    """The committed trained weights are the ones their record describes and
+    parse as an MGN1 network of the C2 shape."""
+    import hashlib
+    import json
+    import os
+    from oracle import network
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_23265_amd", "weights")
+    blob = open(os.path.join(root, "c2_mgnet.mgn1"), "rb").read()
+    rec = json.load(open(os.path.join(root, "c2_mgnet.json")))
+    assert hashlib.sha256(blob).hexdigest() == rec["sha256"]
+    net = network.Net(blob)
+    hdr, _ = configs.problem_weights(configs.c2(0))
+    for k in ("dim", "ndir", "c0", "levels", "nu_pre", "nu_post", "nu_coarse", "coef_ch"):
+        assert net.hdr[k] == hdr[k]

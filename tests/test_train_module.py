@@ -1,0 +1,49 @@
+"""The PyTorch network used for offline training computes what the library and
+the oracle compute: the operator L and the V-cycle with CoeffNet fields, in
+FP64 on the CPU, against the oracle on a small problem."""
+import numpy as np
+import pytest
+
+import problems
+from oracle import discretisation as dsc
+from oracle import network
+from oracle import solve as osolve
+from rte_inputs import configs, weights
+
+torch = pytest.importorskip("torch")
+
+
+def _setup():
+    from paper_2604_23265_amd import train_mgnet as T
+    prob = problems.make(n=16, ndir=8, eps=0.05, g=0.5, seed=3,
+                         mg=dict(c0=16, levels=3, nu_pre=2, nu_post=1, nu_coarse=2, coef_ch=3, seed=11))
+    hdr, t = configs.problem_weights(prob)
+    blob = weights.pack_mgn1(hdr, t)
+    P = osolve.Problem(prob, blob)
+    md = T.Medium([prob], P.D.S, "cpu", torch.float64)
+    net = T.MgNet(hdr, t, "cpu", torch.float64)
+    return T, prob, P, md, net
+
+
+def test_training_operator_is_the_discrete_operator():
+    T, prob, P, md, net = _setup()
+    psi = np.random.default_rng(1).standard_normal((P.D.N, P.D.cells))
+    ref = dsc.apply_L(P.D, psi).reshape(P.D.N, -1)
+    got = T.apply_L(torch.as_tensor(psi.reshape(1, P.D.N, P.D.ny, P.D.nx)), md).numpy().reshape(P.D.N, -1)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_training_network_is_the_vcycle():
+    T, prob, P, md, net = _setup()
+    with torch.no_grad():
+        fields = net.coeffnet(md.X)
+        a_ref, ai_ref = network.coeffnet(P.net, P.D)
+        for l in range(P.net.L):
+            assert np.allclose(fields[0][l][0].numpy(), a_ref[l], rtol=1e-12, atol=1e-13)
+            assert np.allclose(fields[1][l][0].numpy(), ai_ref[l], rtol=1e-12, atol=1e-13)
+        v = np.random.default_rng(2).standard_normal(P.D.n)
+        z = net(torch.as_tensor(v.reshape(1, P.D.N, P.D.ny, P.D.nx)), md, fields).numpy().reshape(-1)
+    ref = P.precond(v)
+    assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
+    # the blob written back is the blob read
+    assert net.blob() == weights.pack_mgn1(*configs.problem_weights(prob))
