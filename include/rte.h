@@ -191,7 +191,8 @@ rte_status rte_workspace_bytes(const rte_operator* op, const mgnet_model* model,
 /* Right-preconditioned flexible GMRES(k) (Krylov solve of Sec. 3 and Sec. 4.2,
  * flexible because the preconditioner runs in reduced precision): inner
  * operator applies and preconditioning in FP32 (or BF16 convolutions),
- * orthogonalisation (two-pass classical Gram-Schmidt), Hessenberg least
+ * orthogonalisation (classical Gram-Schmidt with reorthogonalisation, the second
+ * correction of each basis vector completed in the next step), Hessenberg least
  * squares and the restart residual b - L x in FP64 on the device.
  * psi_out: device double [n], the solution x (written when the solve ends;
  * the iterate lives in the workspace, so x0 may alias psi_out).
