@@ -97,12 +97,19 @@ def serving_leg(args, api, torch, configs, weights):
     Poisson arrivals at 0.7x that rate give arrival-to-completion p50/p99."""
     reqs = [configs.c3_request(r) for r in range(args.serving_requests)]
     models = {}
+    used = {}
     ops = []
     for p in reqs:
         N = p["dirs"].shape[0]
         if N not in models:
-            hdr, t = configs.problem_weights(p)
-            models[N] = api.Model(weights.pack_mgn1(hdr, t))
+            path = os.path.join(ROOT, "paper_2604_23265_amd", "weights", "c3_n%d.mgn1" % N)
+            if args.weights == "trained" and os.path.exists(path):
+                models[N] = api.Model(open(path, "rb").read())
+                used[N] = "trained (weights/c3_n%d.mgn1)" % N
+            else:
+                hdr, t = configs.problem_weights(p)
+                models[N] = api.Model(weights.pack_mgn1(hdr, t))
+                used[N] = "seeded"
         ops.append(api.Operator(p, model=models[N]))
     outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
     kw = dict(restart=30, rtol=1e-6, max_iters=args.serving_max_iters, precond="bf16")
@@ -144,6 +151,7 @@ def serving_leg(args, api, torch, configs, weights):
             "arrival_rate": rate, "completed_ok": ok, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
             "iterations_mean": float(np.mean(its)), "iterations_max": int(np.max(its)),
             "arena_peak_gb": q["arena_peak"] / 2 ** 30, "max_iters": args.serving_max_iters,
+            "weights": {str(k): v for k, v in sorted(used.items())},
             "stream": "seeded C3 draws: grid {64,128,256}^2, 16/32 directions, eps log-uniform [1e-3,1], "
                       "g ~ U[0,0.8], lognormal GRF sigma_T; BF16 MgNet FGMRES(30) to 1e-6"}
 
@@ -165,7 +173,7 @@ def main():
                     help="skip the Block-Jacobi and unpreconditioned batches")
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
     ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
-    ap.add_argument("--serving-requests", type=int, default=0, help="requests of the C3 stream (0 = skip)")
+    ap.add_argument("--serving-requests", type=int, default=64, help="requests of the C3 stream (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-arena-gb", type=int, default=16)
     ap.add_argument("--serving-max-iters", type=int, default=3000)

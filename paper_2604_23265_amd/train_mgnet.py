@@ -36,7 +36,8 @@ def _torch():
 # ------------------------------------------------------------ operator ---
 
 class Medium:
-    """Tensors of a batch of problems sharing grid, directions and scattering."""
+    """Tensors of a batch of problems sharing grid and directions.  S is one
+    scattering matrix [N, N] for all of them or one per problem [B, N, N]."""
 
     def __init__(self, probs, S, device, dtype):
         torch = _torch()
@@ -54,13 +55,15 @@ class Medium:
         # diffusive scaling of eq. (RTE)
         self.sT = t(st / eps)[:, None]
         self.sA = t(eps * sa)[:, None]
-        self.S = t(np.asarray(S, float).reshape(self.N, self.N))
+        S = np.asarray(S, float)
+        S = np.broadcast_to(S.reshape(-1, self.N, self.N), (len(probs), self.N, self.N))
+        self.S = t(S)
         self.dcx = t(np.abs(dirs[:, 0]) / h)[None, :, None, None]
         self.dcy = t(np.abs(dirs[:, 1]) / h)[None, :, None, None]
         self.sgx = t(np.sign(dirs[:, 0]))[None, :, None, None]
         self.sgy = t(np.sign(dirs[:, 1]))[None, :, None, None]
         sS = self.sT - self.sA
-        self.diag = self.dcx + self.dcy + self.sT - sS * torch.diagonal(self.S)[None, :, None, None]
+        self.diag = self.dcx + self.dcy + self.sT - sS * torch.diagonal(self.S, dim1=1, dim2=2)[:, :, None, None]
         # CoeffNet input [log sT, sA / sT, log eps]
         self.X = torch.cat([torch.log(self.sT), self.sA / self.sT, t(np.log(eps))[:, None]], dim=1)
 
@@ -76,7 +79,7 @@ def apply_L(psi, md):
     zero = torch.zeros_like(psi)
     nbx = torch.where(md.sgx > 0, left, torch.where(md.sgx < 0, right, zero))
     nby = torch.where(md.sgy > 0, down, torch.where(md.sgy < 0, up, zero))
-    Spsi = torch.einsum("mn,bnyx->bmyx", md.S, psi)
+    Spsi = torch.einsum("bmn,bnyx->bmyx", md.S, psi)
     return md.dcx * (psi - nbx) + md.dcy * (psi - nby) + md.sT * (psi - Spsi) + md.sA * Spsi
 
 
@@ -152,7 +155,14 @@ class MgNet:
 FAMILIES = {
     # media of the C2 family with seeds disjoint from the benchmark's (2000 + s, s < 10)
     "c2": lambda s: configs.c2(10000 + s),
+    # the serving stream's family (grids 64/128/256, log-uniform eps in [1e-3, 1],
+    # g in [0, 0.8]) for one direction count, seeds disjoint from the stream's
+    # (3000 + r, r < 4096)
+    "c3_n16": lambda s: configs.c3_request(100000 + s, ndir_choices=(16,)),
+    "c3_n32": lambda s: configs.c3_request(100000 + s, ndir_choices=(32,)),
 }
+# batch per grid size (a step's cost grows with the grid)
+BATCH_OF_GRID = {64: 16, 128: 8, 256: 2, 512: 1}
 
 
 def rhs_pool(count, N, ny, nx, rng):
@@ -173,7 +183,8 @@ def rhs_pool(count, N, ny, nx, rng):
     return out
 
 
-def train(family, S, steps, batch, lr, seed, log, device="cuda", media_pool=64, rhs_count=256):
+def train(family, scatter, steps, batch, lr, seed, log, device="cuda", media_pool=64, rhs_count=256):
+    """scatter(prob) -> S [N, N] of a problem (the library's matrix)."""
     torch = _torch()
     dtype = torch.float32
     probs = [FAMILIES[family](s) for s in range(media_pool)]
@@ -181,17 +192,27 @@ def train(family, S, steps, batch, lr, seed, log, device="cuda", media_pool=64, 
     net = MgNet(hdr, t, device, dtype)
     opt = torch.optim.AdamW(net.params(), lr=lr, weight_decay=1e-5)
     rng = np.random.default_rng(seed)
-    mds = [Medium(probs[i:i + batch], S, device, dtype) for i in range(0, media_pool, batch)]
-    N, ny, nx = mds[0].N, mds[0].ny, mds[0].nx
-    log("building %d right-hand sides" % rhs_count)
-    pool = torch.as_tensor(rhs_pool(rhs_count, N, ny, nx, rng), device=device)
+    by_grid = {}
+    for p in probs:
+        by_grid.setdefault(p["n"][0], []).append(p)
+    groups, pools = [], {}
+    for n, ps in sorted(by_grid.items()):
+        bsz = batch if len(by_grid) == 1 else BATCH_OF_GRID.get(n, 1)
+        for i in range(0, len(ps), bsz):
+            chunk = ps[i:i + bsz]
+            groups.append(Medium(chunk, np.stack([scatter(p) for p in chunk]), device, dtype))
+        N = ps[0]["dirs"].shape[0]
+        log("building %d right-hand sides on %dx%d" % (rhs_count, n, n))
+        pools[n] = torch.as_tensor(rhs_pool(rhs_count, N, n, n, rng), device=device)
+    log("%d media in %d groups" % (len(probs), len(groups)))
     hist = []
     t0 = time.time()
     for it in range(steps):
         lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
         for gp in opt.param_groups:
             gp["lr"] = lr_t
-        md = mds[it % len(mds)]
+        md = groups[int(rng.integers(0, len(groups)))]
+        pool = pools[md.nx]
         B = md.sT.shape[0]
         i = torch.as_tensor(rng.integers(0, rhs_count, (2, B)), device=device)
         c = torch.as_tensor(rng.standard_normal((2, B)), dtype=dtype, device=device)
@@ -205,7 +226,7 @@ def train(family, S, steps, batch, lr, seed, log, device="cuda", media_pool=64, 
         opt.step()
         hist.append(float(loss.detach()))
         if it % 50 == 0 or it == steps - 1:
-            log("step %d loss %.4f lr %.2e (%.0f s)" % (it, float(loss), lr_t, time.time() - t0))
+            log("step %d loss %.4f lr %.2e (%.0f s)" % (it, hist[-1], lr_t, time.time() - t0))
     return net, hist
 
 
@@ -227,10 +248,21 @@ def main(argv=None):
         print(*a, flush=True)
 
     torch.cuda.set_device(0)
-    # the scattering matrix is the library's (HG kernel and normalisation of Sec. 2.1)
-    op = api.Operator(FAMILIES[args.family](0))
-    S = op.array(L.ARR_SCATTER).cpu().numpy()
-    net, hist = train(args.family, S, args.steps, args.batch, args.lr, args.seed, log, media_pool=args.media)
+    # scattering matrices are the library's (HG kernel and normalisation of Sec. 2.1)
+    cache = {}
+
+    def scatter(p):
+        # S depends on the directions, weights, g and kernel only: a small grid suffices
+        key = (p["dirs"].shape[0], float(p["g"]))
+        if key not in cache:
+            small = configs._problem("S", 2, (4, 4, 1), p["dirs"], p["weights"], p["g"], p.get("kernel", "auto"),
+                                     np.ones((4, 4)), np.zeros((4, 4)), np.ones((4, 4)), 1.0, None, None, None)
+            op = api.Operator(small)
+            cache[key] = op.array(L.ARR_SCATTER).cpu().numpy().reshape(p["dirs"].shape[0], -1)
+            op.close()
+        return cache[key]
+
+    net, hist = train(args.family, scatter, args.steps, args.batch, args.lr, args.seed, log, media_pool=args.media)
     blob = net.blob()
     with open(args.out, "wb") as fh:
         fh.write(blob)

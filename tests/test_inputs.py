@@ -101,3 +101,20 @@ def test_trained_weights_record():
     hdr, _ = configs.problem_weights(configs.c2(0))
     for k in ("dim", "ndir", "c0", "levels", "nu_pre", "nu_post", "nu_coarse", "coef_ch"):
         assert net.hdr[k] == hdr[k]
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_serving_weights_records(N):
+    import hashlib
+    import json
+    import os
+    from oracle import network
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_23265_amd", "weights")
+    blob = open(os.path.join(root, "c3_n%d.mgn1" % N), "rb").read()
+    rec = json.load(open(os.path.join(root, "c3_n%d.json" % N)))
+    assert hashlib.sha256(blob).hexdigest() == rec["sha256"]
+    net = network.Net(blob)
+    p = configs.c3_request(0, ndir_choices=(N,))
+    hdr, _ = configs.problem_weights(p)
+    for k in ("dim", "ndir", "c0", "levels", "nu_pre", "nu_post", "nu_coarse", "coef_ch"):
+        assert net.hdr[k] == hdr[k]

@@ -20,7 +20,7 @@ def _setup():
     hdr, t = configs.problem_weights(prob)
     blob = weights.pack_mgn1(hdr, t)
     P = osolve.Problem(prob, blob)
-    md = T.Medium([prob], P.D.S, "cpu", torch.float64)
+    md = T.Medium([prob], P.D.S[None], "cpu", torch.float64)
     net = T.MgNet(hdr, t, "cpu", torch.float64)
     return T, prob, P, md, net
 
