@@ -163,8 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed batches")
     ap.add_argument("--weights", default="trained", choices=["trained", "seeded"],
                     help="MgNet weights: trained offline for the family, or the seeded initial ones")
-    ap.add_argument("--batch", type=int, default=10, help="independent instances per step")
-    ap.add_argument("--arena-gb", type=float, default=8.0)
+    ap.add_argument("--batch", type=int, default=32, help="independent instances per step")
+    ap.add_argument("--arena-gb", type=float, default=16.0)
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
