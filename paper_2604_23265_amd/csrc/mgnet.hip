@@ -523,20 +523,23 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const ConvArgs A0) {
 constexpr int TILE_ROW_WORDS = 20;  // 32 BF16 (16 words) + 4 words of padding
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-template <int CK>
+template <int CK, int NI>
 struct TileGeom {
   static constexpr int NTAP = CK == 2 ? 4 : 9;
   static constexpr int S = CK == 1 ? 2 : 1;                       // input step per virtual pixel
   static constexpr int FP = CK == 0 ? 10 : (CK == 1 ? 17 : 9);    // footprint extent per axis
   static constexpr int FPIX = FP * FP;
   static constexpr int NCLS = CK == 2 ? 4 : 1;
+  static constexpr int NCO = 16 * NI;                             // output channels per block
   static constexpr int IN_PIECES = (FPIX * 8 + 255) / 256;        // float4 loads per thread
-  static constexpr int W_PIECES = (NTAP * 128 + 255) / 256;       // 16-byte weight loads per thread
+  static constexpr int W_PIECES = (NTAP * NCO * 4 + 255) / 256;   // 16-byte weight loads per thread
 };
 
-template <int CK, int MODE>
+// NI = 2 or 4 column tiles of 16 output channels per block (32 or 64
+// channels): with 64 the input footprint is staged once per 64 outputs.
+template <int CK, int MODE, int NI>
 __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
-  using G = TileGeom<CK>;
+  using G = TileGeom<CK, NI>;
   const int slot_z = int(blockIdx.z) / G::NCLS;
   const int cls = int(blockIdx.z) - slot_z * G::NCLS;
   SlotBase bs;
@@ -550,7 +553,7 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
   const uint16_t* __restrict__ W = static_cast<const uint16_t*>(A0.w);
 
   __shared__ uint32_t xin[G::FPIX * TILE_ROW_WORDS];
-  __shared__ uint32_t wsm[G::NTAP * 32 * TILE_ROW_WORDS];
+  __shared__ uint32_t wsm[G::NTAP * G::NCO * TILE_ROW_WORDS];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -559,7 +562,7 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
   const int npx = gx >> 3;
   const int patch = blockIdx.x;
   const int py0 = (patch / npx) * 8, px0 = (patch - (patch / npx) * npx) * 8;
-  const int co0 = blockIdx.y * 32;
+  const int co0 = blockIdx.y * G::NCO;
   const int W0 = A0.in_dim[0], W1 = A0.in_dim[1];
   const int cin = A0.cin, cout = A0.cout;
   const int nchunk = cin >> 5;
@@ -582,12 +585,12 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
   constexpr bool NEED_F = MODE == CONV_RESID_R || MODE == CONV_RESID_T;
   constexpr bool NEED_I = MODE == CONV_RESID_T || MODE == CONV_STORE_T;
   constexpr bool NEED_U = MODE == CONV_ACCUM || NEED_F;
-  float ef[8], ea[8], ei[8], eu[8];
+  float ef[4 * NI], ea[4 * NI], ei[4 * NI], eu[4 * NI];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
-      const int q = j * 2 + ni;
+    for (int ni = 0; ni < NI; ++ni) {
+      const int q = j * NI + ni;
       const size_t o = oidx[j] + ni * 16;
       if (NEED_F) {
         ef[q] = fF[o];
@@ -615,8 +618,9 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
 #pragma unroll
     for (int i = 0; i < G::W_PIECES; ++i) {
       const int idx = int(threadIdx.x) + 256 * i;
-      const int idc = idx < G::NTAP * 128 ? idx : G::NTAP * 128 - 1;
-      const int t = idc >> 7, rem = idc & 127, co = rem >> 2, q8 = rem & 3;
+      constexpr int PER_TAP = G::NCO * 4;
+      const int idc = idx < G::NTAP * PER_TAP ? idx : G::NTAP * PER_TAP - 1;
+      const int t = idc / PER_TAP, rem = idc - (idc / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
       rw[i] = *reinterpret_cast<const v4u*>(
           W + (size_t((cls * G::NTAP + t) * cout + co0 + co)) * cin + c * 32 + q8 * 8);
     }
@@ -636,16 +640,19 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
 #pragma unroll
     for (int i = 0; i < G::W_PIECES; ++i) {
       const int idx = int(threadIdx.x) + 256 * i;
-      if (idx < G::NTAP * 128) {
-        const int t = idx >> 7, rem = idx & 127, co = rem >> 2, q8 = rem & 3;
-        *reinterpret_cast<v4u*>(wsm + (t * 32 + co) * TILE_ROW_WORDS + q8 * 4) = rw[i];
+      constexpr int PER_TAP = G::NCO * 4;
+      if (idx < G::NTAP * PER_TAP) {
+        const int t = idx / PER_TAP, rem = idx - (idx / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
+        *reinterpret_cast<v4u*>(wsm + (t * G::NCO + co) * TILE_ROW_WORDS + q8 * 4) = rw[i];
       }
     }
   };
 
   // this lane's A pixel: patch (li % 8, 2 wave + li / 8)
   const int lx = li & 7, ly = 2 * wave + (li >> 3);
-  v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+  v4f acc[NI];
+#pragma unroll
+  for (int ni = 0; ni < NI; ++ni) acc[ni] = v4f{0.f, 0.f, 0.f, 0.f};
   load_chunk(0);
   for (int c = 0; c < nchunk; ++c) {
     if (c > 0) __syncthreads();  // the previous chunk's reads are done
@@ -663,8 +670,8 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
       const int fy = G::S * (py0 + ly) + dy - oy0;
       const v8bf av = *reinterpret_cast<const v8bf*>(xin + (fy * G::FP + fx) * TILE_ROW_WORDS + grp * 4);
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) {
-        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + (t * 32 + ni * 16 + li) * TILE_ROW_WORDS + grp * 4);
+      for (int ni = 0; ni < NI; ++ni) {
+        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + (t * G::NCO + ni * 16 + li) * TILE_ROW_WORDS + grp * 4);
         acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
       }
     }
@@ -673,8 +680,8 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
-      const int q = j * 2 + ni;
+    for (int ni = 0; ni < NI; ++ni) {
+      const int q = j * NI + ni;
       const size_t o = oidx[j] + ni * 16;
       const float v = acc[ni][j];
       if constexpr (MODE == CONV_STORE) {
@@ -692,15 +699,24 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
     }
 }
 
-template <int CK>
-void tile_dispatch(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, const ProfScope& ps) {
+template <int CK, int NI>
+void tile_dispatch2(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, const ProfScope& ps) {
   switch (mode) {
-    case CONV_STORE: launch_k(conv_tile_kernel<CK, CONV_STORE>, grid, dim3(256), 0, s, ps, a); break;
-    case CONV_ACCUM: launch_k(conv_tile_kernel<CK, CONV_ACCUM>, grid, dim3(256), 0, s, ps, a); break;
-    case CONV_STORE_T: launch_k(conv_tile_kernel<CK, CONV_STORE_T>, grid, dim3(256), 0, s, ps, a); break;
-    case CONV_RESID_R: launch_k(conv_tile_kernel<CK, CONV_RESID_R>, grid, dim3(256), 0, s, ps, a); break;
-    default: launch_k(conv_tile_kernel<CK, CONV_RESID_T>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_STORE: launch_k(conv_tile_kernel<CK, CONV_STORE, NI>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_ACCUM: launch_k(conv_tile_kernel<CK, CONV_ACCUM, NI>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_STORE_T: launch_k(conv_tile_kernel<CK, CONV_STORE_T, NI>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_RESID_R: launch_k(conv_tile_kernel<CK, CONV_RESID_R, NI>, grid, dim3(256), 0, s, ps, a); break;
+    default: launch_k(conv_tile_kernel<CK, CONV_RESID_T, NI>, grid, dim3(256), 0, s, ps, a); break;
   }
+}
+
+template <int CK>
+void tile_dispatch(const ConvArgs& a, int gx, int gy, int nz, int mode, hipStream_t s, const ProfScope& ps) {
+  const unsigned patches = unsigned((gx / 8) * (gy / 8));
+  if (a.cout % 64 == 0)
+    tile_dispatch2<CK, 4>(a, dim3(patches, unsigned(a.cout / 64), unsigned(nz)), mode, s, ps);
+  else
+    tile_dispatch2<CK, 2>(a, dim3(patches, unsigned(a.cout / 32), unsigned(nz)), mode, s, ps);
 }
 
 template <bool KSPLIT, int MODE>
@@ -1243,10 +1259,10 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   }
   if (ck >= 0) {
     a.w = c.w->d16;
-    const dim3 gt(unsigned((gxv / 8) * (gyv / 8)), unsigned(c.cout / 32), unsigned(c.nclass * c.sl.count));
-    if (ck == 0) tile_dispatch<0>(a, gt, c.mode, s, ps);
-    else if (ck == 1) tile_dispatch<1>(a, gt, c.mode, s, ps);
-    else tile_dispatch<2>(a, gt, c.mode, s, ps);
+    const int nz = c.nclass * c.sl.count;
+    if (ck == 0) tile_dispatch<0>(a, gxv, gyv, nz, c.mode, s, ps);
+    else if (ck == 1) tile_dispatch<1>(a, gxv, gyv, nz, c.mode, s, ps);
+    else tile_dispatch<2>(a, gxv, gyv, nz, c.mode, s, ps);
   } else if (lds_ok) {
     const int rows = ksplit ? 16 : 64;
     const int width = gxv >= rows ? rows : gxv;
