@@ -269,7 +269,7 @@ def main():
         "config": {
             "workload": "2D 128x128 grid, 32 directions, HG g=0.5, eps=0.01, lognormal GRF sigma_T "
                         "(std 0.5, corr 0.1), sigma_a=0.05, q=1, unit left inflow; 4-level MgNet, "
-                        "32 channels, seeded weights; FGMRES(30), FP64 Arnoldi, rtol 1e-6",
+                        "32 channels; FGMRES(30), FP64 Arnoldi, rtol 1e-6",
             "step": "%d independent instances (GRF seeds 2000..%d) solved concurrently through the "
                     "continuous-batching server" % (args.batch, 2000 + args.batch - 1),
             "grid": [128, 128], "directions": 32, "unknowns": int(ops[0].n), "restart": 30, "rtol": 1e-6,
