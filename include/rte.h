@@ -210,9 +210,11 @@ rte_status rte_solve(const rte_operator* op, const mgnet_model* model, const rte
  * workspace fits in the caller-provided device arena (admission by HBM
  * footprint).  Admitted requests of one shape (grid, directions, model,
  * restart length, preconditioner) form a batch: every kernel launch of a
- * batch covers all of its solves, a request that arrives while the batch
- * runs joins at its next restart boundary, and a solve that meets its
- * tolerance stops taking steps without a host round trip.  Batches of
+ * batch covers all of its solves, each solve runs its own restart cycles
+ * (the restart decision is taken on the device), a request that arrives
+ * while the batch runs joins at the batch's next Arnoldi step, and a solve
+ * that meets its tolerance stops taking steps without a host round trip.
+ * Batches of
  * different shapes run on streams of their own and overlap on the device.
  * Finished solves free their arena range for the next request.  Each solve
  * performs exactly the arithmetic rte_solve performs, so its result does not

@@ -28,6 +28,7 @@ struct Prof {
   struct Rec {
     hipEvent_t e0, e1;
     double work, bytes;
+    std::shared_ptr<double> scale;  // null: 1; negative: not known yet
   };
   std::vector<Rec> pending[RTE_K_COUNT];
   std::vector<hipEvent_t> pool;
@@ -45,19 +46,26 @@ struct Prof {
     RTE_HIP(hipEventCreate(&e));
     return e;
   }
+  // folds in the records whose work multiplier is known; the others stay
   void drain(int c) {
+    std::vector<Rec> keep;
     for (auto& pr : pending[c]) {
+      if (pr.scale && *pr.scale < 0) {
+        keep.push_back(pr);
+        continue;
+      }
       RTE_HIP(hipEventSynchronize(pr.e1));
       float t = 0;
       RTE_HIP(hipEventElapsedTime(&t, pr.e0, pr.e1));
+      const double sc = pr.scale ? *pr.scale : 1.0;
       ms[c] += t;
-      work[c] += pr.work;
-      bytes[c] += pr.bytes;
+      work[c] += pr.work * sc;
+      bytes[c] += pr.bytes * sc;
       count[c] += 1;
       pool.push_back(pr.e0);
       pool.push_back(pr.e1);
     }
-    pending[c].clear();
+    pending[c].swap(keep);
   }
 };
 Prof& prof() {
@@ -81,8 +89,8 @@ bool& prof_quiet() {
   return v;
 }
 
-double& prof_scale() {
-  thread_local double v = 1.0;
+std::shared_ptr<double>& prof_scale() {
+  thread_local std::shared_ptr<double> v;
   return v;
 }
 
@@ -111,8 +119,7 @@ ProfScope::~ProfScope() {
   std::lock_guard<std::mutex> lk(P.mu);
   try {
     if (!ext) (void)hipEventRecord(e1, s);
-    const double sc = prof_scale();
-    P.pending[cls].push_back({e0, e1, work * sc, (bytes < 0 ? work : bytes) * sc});
+    P.pending[cls].push_back({e0, e1, work, bytes < 0 ? work : bytes, prof_scale()});
     if (P.pending[cls].size() >= 65536) P.drain(cls);
   } catch (...) {
   }

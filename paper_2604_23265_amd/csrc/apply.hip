@@ -32,8 +32,8 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
                                                     int nz, int cells) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  x = at(x, bs.ws);
-  y = at(y, bs.ws);
+  x = at(x, bs.ws + bs.dx);
+  y = at(y, bs.ws + bs.dy);
   if (RES) b = at(b, bs.ws);
   sT = at(sT, bs.op);
   sA = at(sA, bs.op);
@@ -147,8 +147,8 @@ __global__ __launch_bounds__(256) void apply_slot_kernel(Slots sl, const float* 
                                                          int cells) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  x = at(x, bs.ws);
-  y = at(y, bs.ws);
+  x = at(x, bs.ws + bs.dx);
+  y = at(y, bs.ws + bs.dy);
   sT = at(sT, bs.op);
   sA = at(sA, bs.op);
   Sp = at(Sp, bs.op);
@@ -363,8 +363,8 @@ __global__ __launch_bounds__(256) void block_jacobi_kernel(Slots sl, const doubl
                                                            int N, int cells) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  v = at(v, bs.ws);
-  z = at(z, bs.ws);
+  v = at(v, bs.ws + bs.dx);
+  z = at(z, bs.ws + bs.dy);
   const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   sT = at(sT, bs.op);
   sA = at(sA, bs.op);

@@ -67,27 +67,53 @@ uint16_t bf16_rne(float f);
 // offset from the slot's workspace base or operator-block base, both read
 // from the slot table.  With no table a launch covers one solve and its
 // array arguments are absolute addresses.
+//
+// Every slot runs its own restart cycle: jj is the slot's Arnoldi step
+// within its cycle, so one launch can advance slots that sit at different
+// steps.  A cycle ends on the device (the step kernel clears live and sets
+// edge); the next boundary launches, gated on edge, form the true residual
+// and take the restart-or-finish decision on the device as well.  The host
+// only admits solves, launches boundaries and copies finished results out.
 struct SlotDesc {
-  uint64_t ws;       // workspace base of the solve held by the slot
-  uint64_t op;       // operator-block base of that solve
-  int32_t live;      // 1 while the solve takes Arnoldi steps in this cycle
-  int32_t occupied;  // 1 while the slot holds a solve
-  int32_t jj;        // Arnoldi steps completed in this cycle
-  int32_t limit;     // Arnoldi steps allowed in this cycle
-  double rtol;       // stop the cycle once |g_{j+1}| / ||b|| <= rtol
-  int32_t bad;       // a non-finite value appeared in this cycle
+  uint64_t ws;        // workspace base of the solve held by the slot
+  uint64_t op;        // operator-block base of that solve
+  int32_t live;       // 1 while the solve takes Arnoldi steps
+  int32_t occupied;   // 1 while the slot holds a solve
+  int32_t jj;         // Arnoldi steps taken in the current cycle
+  int32_t limit;      // Arnoldi steps allowed in the current cycle
+  double rtol;        // stop the cycle once |g_{j+1}| / ||b|| <= rtol
+  int32_t bad;        // a non-finite value appeared in the current cycle
+  int32_t edge;       // at a cycle boundary (ended cycle, or a new solve)
+  int32_t iters;      // Arnoldi steps of the completed cycles
+  int32_t max_iters;  // the solve's iteration limit
+  int32_t restarts;   // completed cycles with at least one step
+  int32_t stall;      // consecutive boundaries that cut the residual by < 0.1 %
+  int32_t done;       // 0 running; 1 finished; 2 finished with x = 0 (b = 0)
+  int32_t code;       // rte_status of a finished solve
+  int32_t steps;      // Arnoldi steps taken, discarded cycles included
   int32_t pad;
+  double bnorm;       // ||b||, negative until the first boundary
+  double prev;        // true residual norm at the previous boundary
+  double rel;         // true relative residual at the last boundary
 };
-static_assert(sizeof(SlotDesc) == 48, "slot descriptor layout");
+static_assert(sizeof(SlotDesc) == 104, "slot descriptor layout");
 
+// Launch-wide slot selection.  gate picks the slots a launch runs for;
+// jx and jy are the bytes one Arnoldi step index adds to a launch's
+// step-indexed input and output operand (V_j, Z_j, V_{j+1}), applied with
+// the slot's own jj.
+enum SlotGate { GATE_LIVE = 0, GATE_OCCUPIED = 1, GATE_EDGE = 2 };
 struct Slots {
   SlotDesc* tab = nullptr;
   int count = 1;  // slots covered by the launch (grid z extent)
-  int gate = 0;   // 0: live slots run, 1: occupied slots run
+  int gate = GATE_LIVE;
+  int64_t jx = 0, jy = 0;
 };
 
 struct SlotBase {
   uint64_t ws = 0, op = 0;
+  uint64_t dx = 0, dy = 0;  // step-indexed operand offsets (bytes)
+  int jj = 0;
 };
 
 // Reads slot z's bases; false when the slot sits this launch out.
@@ -96,7 +122,11 @@ __device__ inline bool slot_open(const Slots& sl, int z, SlotBase& b) {
   const SlotDesc* d = sl.tab + z;
   b.ws = d->ws;
   b.op = d->op;
-  return (sl.gate ? d->occupied : d->live) != 0;
+  b.jj = d->jj;
+  b.dx = uint64_t(int64_t(b.jj) * sl.jx);
+  b.dy = uint64_t(int64_t(b.jj) * sl.jy);
+  const int open = sl.gate == GATE_LIVE ? d->live : sl.gate == GATE_OCCUPIED ? d->occupied : d->edge;
+  return open != 0;
 }
 
 // p + base (bytes).  On the device the sum is formed by byte-pointer
@@ -280,30 +310,36 @@ int krylov_blocks(int64_t n);
 void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* w, int64_t n,
                  double* part, int nblk, hipStream_t s);
 void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double* out, hipStream_t s);
-// Lagged CGS2, first pass of step j >= 1: V[j] <- (V[j] - sum_{i<j} h_i V_i) * fsc[0]
-// (completing the previous basis vector), then part: V_i^T w for i <= j.
-void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int j, const double* h, const double* fsc,
-                        const double* w, int64_t n, double* part, int nblk, hipStream_t s);
-// w <- w - V h; part: V^T w (first nv) and w.w (index nv)
-void launch_updots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
-                   int64_t n, double* part, int nblk, hipStream_t s);
-// w <- (w - V h) * f[0]
-void launch_update_scale(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
-                         int64_t n, const double* f, hipStream_t s);
-// Hessenberg column j, Givens, |g_{j+1}|/||b||; under a slot table it also
-// records the step in the slot's descriptor and ends the slot's cycle when
-// the estimate meets rtol, the step limit is reached or breakdown occurs.
-void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int j, int k, double* H,
+// The Arnoldi step kernels below run under a slot table and take each
+// slot's step j from its descriptor; jmax bounds j over the launch's slots
+// (it picks the register budget).
+// Lagged CGS2, first pass: V[j] <- (V[j] - sum_{i<j} h_i V_i) * fsc[0]
+// (completing the current basis vector; for j = 0 the scaling of the
+// residual), then part: V_i^T w for i <= j, with w = V[j + 1].
+void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int jmax, const double* h, const double* fsc,
+                        int64_t n, double* part, int nblk, hipStream_t s);
+// Second pass, w = V[j + 1]: w <- w - V h; part: V^T w (first j + 1) and
+// w.w (index j + 1)
+void launch_updots(const Slots& sl, const double* V, int64_t ldv, int jmax, const double* h, int64_t n,
+                   double* part, int nblk, hipStream_t s);
+// Hessenberg column j, Givens, |g_{j+1}|/||b||; records the step in the
+// slot's descriptor and ends the slot's cycle (live off, edge on) when the
+// estimate meets rtol, the step limit is reached or breakdown occurs.
+// A slot whose step exceeds jmax (the bound the launch was sized for) has
+// its cycle discarded as a breakdown.
+void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int k, int jmax, double* H,
                         double* cs, double* sn, double* g, const double* bnorm, double* stat, hipStream_t s);
-void launch_scale_by(const Slots& sl, double* w, const double* stat_inv, int64_t n, hipStream_t s);
+// beta = ||r|| from partial sums; g = beta e_1 (when given); stat[3] = stat[5]
+// = 1/beta, stat[4] = beta.
 void launch_start_cycle(const Slots& sl, const double* partn, int nblk, double* g, int k, double* stat,
                         hipStream_t s);
 // jj: steps to combine; under a slot table each slot's own count is used
 void launch_lsq(const Slots& sl, const double* H, const double* g, int jj, int k, double* y, hipStream_t s);
 void launch_xupdate(const Slots& sl, double* x, const float* Z, int64_t ldz, const double* y, int jj,
                     int64_t n, hipStream_t s);
-// rep[z][0..5] = beta, ||b||, jj, bad, live, occupied of every occupied slot
-void launch_report(const Slots& sl, const double* stat, const double* bn, double* rep, hipStream_t s);
+// At a cycle boundary (slots at the edge): the restart-or-finish decision
+// from stat[4] = ||b - L x|| and bn[0] = ||b||, recorded in the descriptor.
+void launch_decide(const Slots& sl, const double* stat, const double* bn, int k, hipStream_t s);
 
 // kernel-class timing.  A sampled scope owns an event pair.  With ext =
 // true the enclosed launch goes through launch_k, and the dispatch itself
@@ -326,7 +362,10 @@ struct ProfScope {
 // launch of an enabled class is timed.
 bool& prof_capturing();
 bool& prof_force();
-double& prof_scale();  // work multiplier of timed launches (slots they cover)
+// Work multiplier of the launches timed while it is set: the number of
+// slots they covered, filled in once the host knows it (negative until
+// then; a null pointer means 1).
+std::shared_ptr<double>& prof_scale();
 bool& prof_quiet();    // batch bookkeeping launches outside sampled steps are not timed
 int prof_stride();  // 0 when no class is being timed, else the smallest `every`
 
@@ -361,12 +400,14 @@ size_t batch_table_bytes(int capacity);
 
 // A group of flexible GMRES(k) solves of one shape (Saad's right-
 // preconditioned FGMRES with FP64 Arnoldi and an FP64 true residual at every
-// restart) advanced together on one stream.  Every launch covers all of the
-// group's slots; a solve that meets its tolerance inside a cycle stops
-// taking steps on the device (its slot turns not-live) without a host round
-// trip.  Solves join and leave at cycle boundaries, where the host reads one
-// report per slot.  At most two Arnoldi steps are in flight ahead of the
-// host's check for a cycle whose slots have all stopped.
+// restart) advanced together on one stream.  The group advances in ticks:
+// a tick is the boundary launches (only when some slot waits at a cycle
+// edge or a solve was admitted in it), one Arnoldi step of every live slot
+// and a copy of the slot table to the host.  Each slot runs its own cycle
+// at its own step, so a solve joins at the next tick and a restart costs
+// its own slot one tick, not the group a synchronisation.  At most two
+// ticks are in flight; the host reads each tick's table copy in order to
+// admit, launch boundaries and copy finished results out.
 class Batch {
  public:
   struct Finished {
@@ -380,18 +421,20 @@ class Batch {
   Batch& operator=(const Batch&) = delete;
   bool compatible(const Operator& op, const Model* m, int k, int precond) const;
   bool full() const;      // every slot is taken or promised to a waiting solve
-  bool idle() const;      // nothing in flight, occupied or waiting
+  bool idle() const;      // nothing in flight, occupied, waiting or draining
   int members() const;    // occupied + waiting
-  // A solve to join at the next cycle boundary; ws holds solve_layout bytes.
+  // A solve to join at the next tick; ws holds solve_layout bytes.
   void add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws, double* out, double t_start);
-  bool ready();           // the awaited device result has arrived (non-blocking)
+  bool ready();           // the oldest tick in flight has completed (non-blocking)
   void wait();
-  void advance();         // take the next host decision
+  void advance();         // read the oldest completed tick, then keep two ticks in flight
   // Solves whose result has reached the caller's output buffer.
   void collect(std::vector<Finished>& out);
   // After a device error: waits for the stream and hands back every solve.
   void abandon(rte_status st, std::vector<Finished>& out);
-  void step_body(int j, int zc, hipStream_t s);  // the launches of Arnoldi step j
+  // The launches of one Arnoldi step of every live slot; jmax bounds the
+  // slots' steps (one less than the register budget of the dot kernels).
+  void step_body(int jmax, int zc, hipStream_t s);
 
  private:
   struct Member {
@@ -402,19 +445,22 @@ class Batch {
     double* out = nullptr;
     double t0 = 0, ms = 0;
     int slot = -1;
-    int iters = 0, restarts = 0, stall = 0;
-    double bnorm = -1, prev = 0, rel = 0;
+    int iters = 0, restarts = 0, steps_seen = 0;
+    double rel = 0;
+    int64_t since = 0;       // tick that admitted the solve
+    int64_t bnd_tick = -1;   // last tick whose boundary launches cover the solve
+    bool edge_pending = false;
     rte_status status = RTE_EAGAIN;
     hipEvent_t copied = nullptr;
   };
-  enum Phase { IDLE, RESTART, STEPS };
-  void boundary();
-  void decide();
-  void enqueue_step(int j);
-  void finish_member(Member* mb, rte_status st);
+  void enqueue_tick();
+  void boundary_launches(int zc);
+  void admit(int z);
+  void process(int64_t t);
+  void fill();
+  void finish_member(int z, const SlotDesc& d);
   void upload(int slot);
   void upload_all();
-  Slots slots(int gate) const { return Slots{tab_, zc_, gate}; }
 
   const Operator& shape_;
   std::vector<int64_t> key_;
@@ -423,22 +469,19 @@ class Batch {
   bool mg_, bj_;
   SolveLayout lay_;
   OpArrays rel_;
-  SlotDesc* tab_;           // device [cap]
-  double* rep_;             // device [cap][8]
+  SlotDesc* tab_;               // device [cap]
   hipStream_t s_;
-  SlotDesc* hdesc_ = nullptr;   // pinned mirror of the host-set fields
-  SlotDesc* hsnap_ = nullptr;   // pinned [2][cap]: descriptors after steps
-  double* hrep_ = nullptr;      // pinned [cap][8]
-  hipEvent_t ev_step_[2] = {nullptr, nullptr};
-  hipEvent_t ev_rep_ = nullptr;
+  SlotDesc* hdesc_ = nullptr;   // pinned: admission descriptors (one per slot)
+  SlotDesc* hsnap_ = nullptr;   // pinned [2][cap]: the table after each tick
+  hipEvent_t ev_tick_[2] = {nullptr, nullptr};
+  int tick_zc_[2] = {0, 0};
+  std::shared_ptr<double> tick_scale_[2];
   std::vector<std::unique_ptr<Member>> slot_;  // occupant per slot
   std::vector<std::unique_ptr<Member>> waiting_, draining_;
-  Phase phase_ = IDLE;
-  int zc_ = 0;                  // slots covered by the launches of this cycle
-  int nlive_ = 0;               // live slots at the last host check (timer accounting)
-  int j_wait_ = 0, j_enq_ = 0;
+  int64_t t_enq_ = 0, t_done_ = 0;  // ticks enqueued / read back
+  int64_t snap_tick_ = -1;          // the last tick read back
+  int snap_jmax_ = 0;               // largest step of a live slot in it
   bool graphs_ = true;
-  std::vector<hipGraphExec_t>* gcache_ = nullptr;
 };
 
 // Arnoldi-step graphs are keyed by everything their kernel arguments hold:

@@ -125,24 +125,26 @@ __global__ __launch_bounds__(KT) void dots_kernel(Slots sl, const double* __rest
 }
 
 // First Gram-Schmidt correction and the second pass's dots in one read of
-// V: w1 = w - sum_i h_i V_i (written back), then part[blk][i] = V_i . w1
+// V, for the slot's step j (nv = j + 1 basis vectors, w = V[j + 1]):
+// w1 = w - sum_i h_i V_i (written back), then part[blk][i] = V_i . w1
 // (i < nv) and part[blk][nv] = w1 . w1.  With HOLD the element's column of V
 // stays in registers between the two uses; without it (the widest budget,
 // which would not fit) the column is loaded again, from cache.
 template <int NV, bool HOLD>
 __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __restrict__ V, int64_t ldv,
-                                                    int nv, const double* __restrict__ h, double* __restrict__ w,
-                                                    int64_t n, double* __restrict__ part, int nblk) {
+                                                    const double* __restrict__ h, int64_t n,
+                                                    double* __restrict__ part, int nblk) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
+  const int nv = bs.jj + 1;
   V = at(V, bs.ws);
   h = at(h, bs.ws);
-  w = at(w, bs.ws);
   part = at(part, bs.ws);
+  double* __restrict__ w = const_cast<double*>(V) + int64_t(nv) * ldv;
   __shared__ double red[4 * NV];
   __shared__ double rww[KT / 64];
   __shared__ double hs[NV];
-  if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+  if (threadIdx.x < NV) hs[threadIdx.x] = int(threadIdx.x) < nv ? h[threadIdx.x] : 0.0;
   __syncthreads();
   int64_t beg, end;
   chunk_of(n, nblk, beg, end);
@@ -174,23 +176,26 @@ __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __re
   block_store<NV>(acc, nv, part, red);
 }
 
-// First pass of step j >= 1 of the lagged CGS2: complete the previous basis
-// vector in place, V[j] <- (V[j] - sum_{i<j} h_i V_i) * fsc[0], and in the
-// same read of V form part[blk][i] = V_i . w for i <= j (V_j completed).
-// The column of V_0 .. V_{j-1} is held (HOLD) or reloaded as in updots.
+// First pass of the slot's step j of the lagged CGS2: complete the current
+// basis vector in place, V[j] <- (V[j] - sum_{i<j} h_i V_i) * fsc[0] (for
+// j = 0 only the scaling: V[0] holds the residual and fsc[0] = 1/beta), and
+// in the same read of V form part[blk][i] = V_i . w for i <= j (V_j
+// completed) with w = V[j + 1], the operator's output of this step.  The
+// column of V_0 .. V_{j-1} is held (HOLD) or reloaded as in updots.
 template <int NV, bool HOLD>
-__global__ __launch_bounds__(KT) void finish_dots_kernel(Slots sl, double* __restrict__ V, int64_t ldv, int j,
+__global__ __launch_bounds__(KT) void finish_dots_kernel(Slots sl, double* __restrict__ V, int64_t ldv,
                                                          const double* __restrict__ h,
-                                                         const double* __restrict__ fsc,
-                                                         const double* __restrict__ w, int64_t n,
+                                                         const double* __restrict__ fsc, int64_t n,
                                                          double* __restrict__ part, int nblk) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
+  const int j = bs.jj;
+  const int jl = j > 0 ? j - 1 : 0;  // loads past j - 1 re-read this (valid) vector
   V = at(V, bs.ws);
   h = at(h, bs.ws);
   fsc = at(fsc, bs.ws);
-  w = at(w, bs.ws);
   part = at(part, bs.ws);
+  const double* __restrict__ w = V + int64_t(j + 1) * ldv;
   __shared__ double red[4 * NV];
   __shared__ double ru[KT / 64];
   __shared__ double hs[NV];
@@ -209,17 +214,18 @@ __global__ __launch_bounds__(KT) void finish_dots_kernel(Slots sl, double* __res
     double u = Vj[e];
     if constexpr (HOLD) {
       double v[NV];
-      load_column<NV>(V, ldv, j, e, v);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = V[int64_t(i < j ? i : jl) * ldv + e];
 #pragma unroll
       for (int i = 0; i < NV; ++i) u -= hs[i] * v[i];
 #pragma unroll
       for (int i = 0; i < NV; ++i) acc[i] += v[i] * we;
     } else {
 #pragma unroll
-      for (int i = 0; i < NV; ++i) u -= hs[i] * V[int64_t(i < j ? i : j - 1) * ldv + e];
+      for (int i = 0; i < NV; ++i) u -= hs[i] * V[int64_t(i < j ? i : jl) * ldv + e];
       __asm__ volatile("" ::: "memory");  // compiler fence: reload the column, do not keep it live
 #pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += V[int64_t(i < j ? i : j - 1) * ldv + e] * we;
+      for (int i = 0; i < NV; ++i) acc[i] += V[int64_t(i < j ? i : jl) * ldv + e] * we;
     }
     u *= sc;
     Vj[e] = u;
@@ -228,33 +234,6 @@ __global__ __launch_bounds__(KT) void finish_dots_kernel(Slots sl, double* __res
   const double su = block_sum(accu, ru);
   if (threadIdx.x == 0) part[int64_t(blockIdx.x) * HMAX + j] = su;
   block_store<NV>(acc, j, part, red);
-}
-
-// Second correction and normalisation: w = (w - sum_i h_i V_i) * f[0].
-template <int NV>
-__global__ __launch_bounds__(KT) void update_scale_kernel(Slots sl, const double* __restrict__ V, int64_t ldv,
-                                                          int nv, const double* __restrict__ h,
-                                                          double* __restrict__ w, int64_t n,
-                                                          const double* __restrict__ f) {
-  SlotBase bs;
-  if (!slot_open(sl, blockIdx.z, bs)) return;
-  V = at(V, bs.ws);
-  h = at(h, bs.ws);
-  w = at(w, bs.ws);
-  f = at(f, bs.ws);
-  __shared__ double hs[NV];
-  if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
-  __syncthreads();
-  const double a = f[0];
-  int64_t e = int64_t(blockIdx.x) * KT + threadIdx.x;
-  for (; e < n; e += int64_t(gridDim.x) * KT) {
-    double v[NV];
-    load_column<NV>(V, ldv, nv, e, v);
-    double x = w[e];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) x -= hs[i] * v[i];
-    w[e] = x * a;
-  }
 }
 
 // out[i] = sum_blk part[blk][i], one block per i, fixed order.
@@ -280,13 +259,14 @@ __global__ __launch_bounds__(KT) void reduce_kernel(Slots sl, const double* __re
 // 1/||w2||}.  h2[j + 1] holds ||w1||^2.  flags: 1 = non-finite value,
 // 2 = ||w2|| negligible (the Krylov space is invariant: the least-squares
 // solution is exact).
-__global__ void finish_kernel(Slots sl, const double* __restrict__ h1, const double* __restrict__ h2, int j,
-                              int k, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+__global__ void finish_kernel(Slots sl, const double* __restrict__ h1, const double* __restrict__ h2, int k,
+                              int jmax, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
                               double* __restrict__ g, const double* __restrict__ bnorm,
                               double* __restrict__ stat) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
+  const int j = bs.jj;
   h1 = at(h1, bs.ws);
   h2 = at(h2, bs.ws);
   H = at(H, bs.ws);
@@ -306,7 +286,7 @@ __global__ void finish_kernel(Slots sl, const double* __restrict__ h1, const dou
   const double hn = hn2 > 0 ? sqrt(hn2) : 0.0;
   col[j + 1] = hn;
   int flags = 0;
-  if (!isfinite(hn2) || !isfinite(cmax)) flags |= 1;
+  if (!isfinite(hn2) || !isfinite(cmax) || j > jmax) flags |= 1;
   if (hn <= 1e-14 * cmax) flags |= 2;
   for (int i = 0; i < j; ++i) {
     const double t = cs[i] * col[i] + sn[i] * col[i + 1];
@@ -337,16 +317,20 @@ __global__ void finish_kernel(Slots sl, const double* __restrict__ h1, const dou
     flags |= 1;
     stat[1] = double(flags);
   }
-  if (sl.tab) {
-    // the slot's own stopping test: a non-finite value discards the cycle
-    SlotDesc* d = sl.tab + blockIdx.z;
-    if (flags & 1) {
-      d->bad = 1;
-      d->jj = 0;
+  // the slot's own stopping test: a non-finite value discards the cycle; a
+  // stopped slot waits at the cycle boundary
+  SlotDesc* d = sl.tab + blockIdx.z;
+  d->steps += 1;
+  if (flags & 1) {
+    d->bad = 1;
+    d->jj = 0;
+    d->live = 0;
+    d->edge = 1;
+  } else {
+    d->jj = j + 1;
+    if ((flags & 2) || stat[0] <= d->rtol || j + 1 >= d->limit) {
       d->live = 0;
-    } else {
-      d->jj = j + 1;
-      if ((flags & 2) || stat[0] <= d->rtol || j + 1 >= d->limit) d->live = 0;
+      d->edge = 1;
     }
   }
 }
@@ -372,17 +356,75 @@ __global__ __launch_bounds__(KT) void start_cycle_kernel(Slots sl, const double*
   if (g) g[0] = beta;
   stat[3] = beta > 0 ? 1.0 / beta : 0.0;
   stat[4] = beta;
-  stat[5] = 1.0;  // v_0 = r / beta is complete: the first preconditioner input needs no scale
+  // V[0] holds r: the first preconditioner input is r / beta, and the
+  // first step's pass 1 scales V[0] in place
+  stat[5] = stat[3];
 }
 
-__global__ void scale_kernel(Slots sl, double* __restrict__ w, const double* __restrict__ f, int64_t n) {
+// The decision at a cycle boundary, per slot at the edge, in the order of
+// the single-solve driver: a non-finite right-hand side, a zero one, a
+// breakdown in the cycle, convergence of the true residual, the iteration
+// limit, and stagnation (three boundaries in a row that each cut the true
+// residual by less than 0.1 %); otherwise a new cycle of at most k steps.
+// stat[4] = beta = ||b - L x||, bn[0] = ||b||.
+__global__ void decide_kernel(Slots sl, const double* __restrict__ stat, const double* __restrict__ bn, int k) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  w = at(w, bs.ws);
-  f = at(f, bs.ws);
-  const double a = f[0];
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (; i < n; i += int64_t(gridDim.x) * blockDim.x) w[i] *= a;
+  stat = at(stat, bs.ws);
+  bn = at(bn, bs.ws);
+  SlotDesc* d = sl.tab + blockIdx.z;
+  const double beta = stat[4];
+  const int jj = d->jj;
+  d->iters += jj;
+  if (jj > 0) d->restarts += 1;
+  d->edge = 0;
+  d->live = 0;
+  d->jj = 0;
+  int done = 0, code = RTE_OK;
+  if (d->bnorm < 0) {
+    const double b = bn[0];
+    d->bnorm = b;
+    d->prev = INFINITY;
+    if (!isfinite(b)) {
+      done = 1;
+      code = RTE_EINVAL;
+    } else if (b == 0.0) {
+      d->rel = 0.0;
+      done = 2;
+    }
+  }
+  if (!done) {
+    d->rel = beta / d->bnorm;
+    if (d->bad || !isfinite(beta)) {
+      done = 1;
+      code = RTE_EBREAKDOWN;
+    } else if (d->rel <= d->rtol) {
+      done = 1;
+    } else if (d->iters >= d->max_iters) {
+      done = 1;
+      code = RTE_ENOCONV;
+    } else {
+      if (beta >= d->prev * (1.0 - 1e-3)) {
+        if (++d->stall >= 3) {
+          done = 1;
+          code = RTE_ENOCONV;
+        }
+      } else {
+        d->stall = 0;
+      }
+    }
+  }
+  d->bad = 0;
+  if (done) {
+    d->done = done;
+    d->code = code;
+    return;
+  }
+  d->prev = beta;
+  const int left = d->max_iters - d->iters;
+  d->limit = left < k ? left : k;
+  d->live = 1;
 }
 
 // Back substitution on the rotated (upper-triangular) Hessenberg matrix.
@@ -424,26 +466,6 @@ __global__ __launch_bounds__(KT) void xupdate_kernel(Slots sl, double* __restric
   }
 }
 
-// One report row per occupied slot, gathered for a single copy to the host.
-__global__ void report_kernel(Slots sl, const double* __restrict__ stat, const double* __restrict__ bn,
-                              double* __restrict__ rep) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  SlotBase bs;
-  if (!slot_open(sl, blockIdx.z, bs)) return;
-  stat = at(stat, bs.ws);
-  bn = at(bn, bs.ws);
-  double* r = rep + 8 * int64_t(blockIdx.z);
-  r[0] = stat[4];
-  r[1] = bn[0];
-  if (sl.tab) {
-    const SlotDesc* d = sl.tab + blockIdx.z;
-    r[2] = double(d->jj);
-    r[3] = double(d->bad);
-    r[4] = double(d->live);
-    r[5] = double(d->occupied);
-  }
-}
-
 unsigned ew_grid(int64_t n) {
   int64_t g = (n + KT - 1) / KT;
   if (g > 8192) g = 8192;
@@ -469,14 +491,9 @@ void dots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const 
   launch_k(dots_kernel<NV>, g, dim3(KT), 0, s, ps, sl, V, ldv, nv, w, n, part, nblk);
 }
 template <int NV>
-void updots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const double* V, int64_t ldv, int nv,
-               const double* h, double* w, int64_t n, double* part, int nblk) {
-  launch_k(updots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
-}
-template <int NV>
-void upscale_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const double* V, int64_t ldv,
-                int nv, const double* h, double* w, int64_t n, const double* f) {
-  launch_k(update_scale_kernel<NV>, g, dim3(KT), 0, s, ps, sl, V, ldv, nv, h, w, n, f);
+void updots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, const double* V, int64_t ldv,
+               const double* h, int64_t n, double* part, int nblk) {
+  launch_k(updots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, sl, V, ldv, h, n, part, nblk);
 }
 dim3 z3(unsigned x, const Slots& sl) { return dim3(x, 1, unsigned(sl.count)); }
 }  // namespace
@@ -502,62 +519,52 @@ void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double
 
 namespace {
 template <int NV>
-void fdots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, double* V, int64_t ldv, int j,
-              const double* h, const double* fsc, const double* w, int64_t n, double* part, int nblk) {
-  launch_k(finish_dots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
+void fdots_go(dim3 g, hipStream_t s, const ProfScope& ps, const Slots& sl, double* V, int64_t ldv,
+              const double* h, const double* fsc, int64_t n, double* part, int nblk) {
+  launch_k(finish_dots_kernel<NV, (NV <= 32)>, g, dim3(KT), 0, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
 }
 }  // namespace
 
-void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int j, const double* h, const double* fsc,
-                        const double* w, int64_t n, double* part, int nblk, hipStream_t s) {
-  RTE_REQUIRE(j >= 1 && j <= 64, RTE_EINVAL, "too many basis vectors");
+void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int jmax, const double* h, const double* fsc,
+                        int64_t n, double* part, int nblk, hipStream_t s) {
+  RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the Arnoldi step kernels run under a slot table");
+  RTE_REQUIRE(jmax >= 0 && jmax <= 63, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
-  ps.work = 8.0 * double(n) * (j + 3);  // V_0..V_{j-1}, V_j read and written, w
+  ps.work = 8.0 * double(n) * (jmax + 3);  // V_0..V_{j-1}, V_j read and written, w (j at its bound)
   const dim3 g = z3(unsigned(nblk), sl);
-  if (j <= 8) fdots_go<8>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
-  else if (j <= 16) fdots_go<16>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
-  else if (j <= 32) fdots_go<32>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
-  else fdots_go<64>(g, s, ps, sl, V, ldv, j, h, fsc, w, n, part, nblk);
+  if (jmax <= 8) fdots_go<8>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
+  else if (jmax <= 16) fdots_go<16>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
+  else if (jmax <= 32) fdots_go<32>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
+  else fdots_go<64>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_updots(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
+void launch_updots(const Slots& sl, const double* V, int64_t ldv, int jmax, const double* h, int64_t n,
                    double* part, int nblk, hipStream_t s) {
-  RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
+  RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the Arnoldi step kernels run under a slot table");
+  RTE_REQUIRE(jmax >= 0 && jmax <= 63, RTE_EINVAL, "too many basis vectors");
+  const int nv = jmax + 1;
   ProfScope ps(RTE_K_ORTH, s, true);
-  ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once
+  ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once (j at its bound)
   const dim3 g = z3(unsigned(nblk), sl);
-  if (nv <= 8) updots_go<8>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
-  else if (nv <= 16) updots_go<16>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
-  else if (nv <= 32) updots_go<32>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
-  else updots_go<64>(g, s, ps, sl, V, ldv, nv, h, w, n, part, nblk);
+  if (nv <= 8) updots_go<8>(g, s, ps, sl, V, ldv, h, n, part, nblk);
+  else if (nv <= 16) updots_go<16>(g, s, ps, sl, V, ldv, h, n, part, nblk);
+  else if (nv <= 32) updots_go<32>(g, s, ps, sl, V, ldv, h, n, part, nblk);
+  else updots_go<64>(g, s, ps, sl, V, ldv, h, n, part, nblk);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_update_scale(const Slots& sl, const double* V, int64_t ldv, int nv, const double* h, double* w,
-                         int64_t n, const double* f, hipStream_t s) {
-  RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
+void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int k, int jmax, double* H,
+                        double* cs, double* sn, double* g, const double* bnorm, double* stat, hipStream_t s) {
+  RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the Arnoldi step kernels run under a slot table");
   ProfScope ps(RTE_K_ORTH, s, true);
-  ps.work = 8.0 * double(n) * (nv + 2);
-  const dim3 g = z3(ew_grid(n), sl);
-  if (nv <= 8) upscale_go<8>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
-  else if (nv <= 16) upscale_go<16>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
-  else if (nv <= 32) upscale_go<32>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
-  else upscale_go<64>(g, s, ps, sl, V, ldv, nv, h, w, n, f);
+  launch_k(finish_kernel, z3(1, sl), dim3(64), 0, s, ps, sl, h1, h2, k, jmax, H, cs, sn, g, bnorm, stat);
   RTE_HIP(hipGetLastError());
 }
 
-void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int j, int k, double* H, double* cs,
-                        double* sn, double* g, const double* bnorm, double* stat, hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s, true);
-  launch_k(finish_kernel, z3(1, sl), dim3(64), 0, s, ps, sl, h1, h2, j, k, H, cs, sn, g, bnorm, stat);
-  RTE_HIP(hipGetLastError());
-}
-
-void launch_scale_by(const Slots& sl, double* w, const double* stat_inv, int64_t n, hipStream_t s) {
-  ProfScope ps(RTE_K_ORTH, s, true);
-  ps.work = 16.0 * double(n);
-  launch_k(scale_kernel, z3(ew_grid(n), sl), dim3(KT), 0, s, ps, sl, w, stat_inv, n);
+void launch_decide(const Slots& sl, const double* stat, const double* bn, int k, hipStream_t s) {
+  RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the boundary decision runs under a slot table");
+  hipLaunchKernelGGL(decide_kernel, z3(1, sl), dim3(64), 0, s, sl, stat, bn, k);
   RTE_HIP(hipGetLastError());
 }
 
@@ -575,11 +582,6 @@ void launch_lsq(const Slots& sl, const double* H, const double* g, int jj, int k
 void launch_xupdate(const Slots& sl, double* x, const float* Z, int64_t ldz, const double* y, int jj, int64_t n,
                     hipStream_t s) {
   hipLaunchKernelGGL(xupdate_kernel, z3(ew_grid(n), sl), dim3(KT), 0, s, sl, x, Z, ldz, y, jj, n);
-  RTE_HIP(hipGetLastError());
-}
-
-void launch_report(const Slots& sl, const double* stat, const double* bn, double* rep, hipStream_t s) {
-  hipLaunchKernelGGL(report_kernel, z3(1, sl), dim3(64), 0, s, sl, stat, bn, rep);
   RTE_HIP(hipGetLastError());
 }
 

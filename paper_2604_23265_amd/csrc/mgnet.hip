@@ -790,7 +790,7 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
                                                    int C0, int64_t P) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  v = at(v, bs.ws);
+  v = at(v, bs.ws + bs.dx);
   const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   f0 = at(f0, bs.ws);
   if (t0) {
@@ -848,10 +848,10 @@ __global__ __launch_bounds__(256) void proj_kernel(Slots sl, const double* __res
                                                    float sc, float* __restrict__ z, int N, int C0, int64_t P) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  v = at(v, bs.ws);
+  v = at(v, bs.ws + bs.dx);
   const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   u0 = at(u0, bs.ws);
-  z = at(z, bs.ws);
+  z = at(z, bs.ws + bs.dy);
   sT = at(sT, bs.op);
   sA = at(sA, bs.op);
   dc = at(dc, bs.op);
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* 
                                                         int64_t P) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  v = at(v, bs.ws);
+  v = at(v, bs.ws + bs.dx);
   const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   f0 = at(f0, bs.ws);
   if (t0) {
@@ -995,10 +995,10 @@ __global__ __launch_bounds__(256) void proj_slot_kernel(Slots sl, const double* 
                                                         float sc, float* __restrict__ z, int N, int64_t P) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  v = at(v, bs.ws);
+  v = at(v, bs.ws + bs.dx);
   const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
   u0 = at(u0, bs.ws);
-  z = at(z, bs.ws);
+  z = at(z, bs.ws + bs.dy);
   sT = at(sT, bs.op);
   sA = at(sA, bs.op);
   dc = at(dc, bs.op);
@@ -1077,8 +1077,8 @@ __global__ void cast_kernel(Slots sl, const double* __restrict__ a, const double
                             float* __restrict__ b, int64_t n) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
-  a = at(a, bs.ws);
-  b = at(b, bs.ws);
+  a = at(a, bs.ws + bs.dx);
+  b = at(b, bs.ws + bs.dy);
   const double sc = scale ? at(scale, bs.ws)[0] : 1.0;
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   for (; i < n; i += int64_t(gridDim.x) * blockDim.x) b[i] = float(a[i] * sc);

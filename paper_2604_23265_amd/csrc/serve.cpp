@@ -2,9 +2,9 @@
 // arrival order while fewer than max_slots solves are active and the
 // request's workspace fits in the caller's device arena.  Admitted requests
 // of one shape (grid, directions, model, restart length, preconditioner)
-// join one Batch: each launch of a batch covers all of its solves, and a
-// request that arrives while others run joins at the batch's next cycle
-// boundary.  Batches of different shapes run on streams of their own and
+// join one Batch: each launch of a batch covers all of its solves, each
+// solve runs its own restart cycles, and a request that arrives while
+// others run joins at the batch's next tick (Arnoldi step).  Batches of different shapes run on streams of their own and
 // overlap on the device.  A finished solve frees its arena range as soon as
 // its result has been copied to the caller's buffer.
 #include <atomic>

@@ -157,9 +157,7 @@ SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet) 
   return L;
 }
 
-size_t batch_table_bytes(int capacity) {
-  return align256(size_t(capacity) * sizeof(SlotDesc)) + align256(size_t(capacity) * 8 * sizeof(double));
-}
+size_t batch_table_bytes(int capacity) { return align256(size_t(capacity) * sizeof(SlotDesc)); }
 
 namespace {
 
@@ -198,7 +196,7 @@ std::map<GraphKey, std::unique_ptr<std::vector<hipGraphExec_t>>>& graph_map() {
   return *m;
 }
 
-std::atomic<int64_t> g_steps{0};  // Arnoldi steps enqueued by every batch (timer sampling)
+std::atomic<int64_t> g_steps{0};  // ticks enqueued by every batch (timer sampling)
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -210,7 +208,7 @@ std::vector<hipGraphExec_t>* step_graphs(const void* tab, const Model* m, int pr
                                          const std::vector<int64_t>& shape, int zc) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   auto& slot = graph_map()[GraphKey{tab, m, precond, k, zc, shape}];
-  if (!slot) slot.reset(new std::vector<hipGraphExec_t>(size_t(k), nullptr));
+  if (!slot) slot.reset(new std::vector<hipGraphExec_t>(4, nullptr));  // register budgets 8, 16, 32, 64
   return slot.get();
 }
 
@@ -255,7 +253,6 @@ Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capa
   lay_ = solve_layout(shape, m, k, mg_);
   rel_ = shape.relative();
   tab_ = reinterpret_cast<SlotDesc*>(tables);
-  rep_ = reinterpret_cast<double*>(tables + align256(size_t(capacity) * sizeof(SlotDesc)));
   if (mg_) const_cast<Model*>(m)->ensure_on_device();
   const char* env = std::getenv("RTE_GRAPHS");
   graphs_ = !(env && env[0] == '0');
@@ -264,13 +261,9 @@ Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capa
                         hipHostMallocDefault));
   RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsnap_), 2 * size_t(capacity) * sizeof(SlotDesc),
                         hipHostMallocDefault));
-  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hrep_), size_t(capacity) * 8 * sizeof(double),
-                        hipHostMallocDefault));
   std::memset(hdesc_, 0, size_t(capacity) * sizeof(SlotDesc));
   std::memset(hsnap_, 0, 2 * size_t(capacity) * sizeof(SlotDesc));
-  std::memset(hrep_, 0, size_t(capacity) * 8 * sizeof(double));
-  for (auto& e : ev_step_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  RTE_HIP(hipEventCreateWithFlags(&ev_rep_, hipEventDisableTiming));
+  for (auto& e : ev_tick_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   upload_all();
 }
 
@@ -281,12 +274,10 @@ Batch::~Batch() {
       if (mb && mb->copied) (void)hipEventDestroy(mb->copied);
   for (auto& mb : slot_)
     if (mb && mb->copied) (void)hipEventDestroy(mb->copied);
-  for (auto& e : ev_step_)
+  for (auto& e : ev_tick_)
     if (e) (void)hipEventDestroy(e);
-  if (ev_rep_) (void)hipEventDestroy(ev_rep_);
   if (hdesc_) (void)hipHostFree(hdesc_);
   if (hsnap_) (void)hipHostFree(hsnap_);
-  if (hrep_) (void)hipHostFree(hrep_);
 }
 
 bool Batch::compatible(const Operator& op, const Model* m, int k, int precond) const {
@@ -302,8 +293,14 @@ int Batch::members() const {
 
 bool Batch::full() const { return members() >= cap_; }
 
-bool Batch::idle() const { return phase_ == IDLE && members() == 0 && draining_.empty(); }
+bool Batch::idle() const {
+  return t_done_ == t_enq_ && members() == 0 && draining_.empty();
+}
 
+// Descriptor uploads come from the slot's own pinned entry, written only at
+// admission; a slot is admitted again only after the host has read its
+// previous solve's end from a later table copy, so the earlier upload has
+// long completed.
 void Batch::upload(int z) {
   RTE_HIP(hipMemcpyAsync(tab_ + z, hdesc_ + z, sizeof(SlotDesc), hipMemcpyHostToDevice, s_));
 }
@@ -326,55 +323,66 @@ void Batch::add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws
   mb->out = out;
   mb->t0 = t_start;
   waiting_.push_back(std::move(mb));
-  if (phase_ == IDLE) boundary();
 }
 
-// Cycle boundary: admit waiting solves into free slots, then for every
-// occupied slot combine the finished cycle's steps into x (x += Z y), form
-// the FP64 true residual r = b - L x as v_0, and report beta = ||r|| and
-// ||b|| to the host.
 namespace {
 struct Quiet {
   Quiet() { prof_quiet() = true; }
   ~Quiet() { prof_quiet() = false; }
 };
+int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+// register budget index of the dot kernels for steps j <= jmax: 8, 16, 32, 64
+int budget_index(int jmax) {
+  const int nv = jmax + 1;
+  return nv <= 8 ? 0 : nv <= 16 ? 1 : nv <= 32 ? 2 : 3;
+}
 }  // namespace
 
-void Batch::boundary() {
-  Quiet quiet;
+// A waiting solve takes slot z: x = x0 (or 0), the right-hand side is copied
+// into the workspace, and the descriptor marks the slot at a cycle edge
+// with no steps taken, so the next boundary launches form r = b - L x and
+// decide (normally: a first cycle).
+void Batch::admit(int z) {
+  std::unique_ptr<Member> mb = std::move(waiting_.front());
+  waiting_.erase(waiting_.begin());
   const int64_t n = lay_.n;
-  for (int z = 0; z < cap_ && !waiting_.empty(); ++z) {
-    if (slot_[z]) continue;
-    std::unique_ptr<Member> mb = std::move(waiting_.front());
-    waiting_.erase(waiting_.begin());
-    double* x = reinterpret_cast<double*>(mb->ws + lay_.off_x);
-    double* b = reinterpret_cast<double*>(mb->ws + lay_.off_b);
-    if (mb->o.x0)
-      RTE_HIP(hipMemcpyAsync(x, mb->o.x0, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
-    else
-      launch_fill_f64(Slots{}, x, 0.0, n, s_);
-    const double* bsrc = mb->o.b ? static_cast<const double*>(mb->o.b) : mb->op->a.b64;
-    RTE_HIP(hipMemcpyAsync(b, bsrc, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
-    SlotDesc d{};
-    d.ws = reinterpret_cast<uint64_t>(mb->ws);
-    d.op = reinterpret_cast<uint64_t>(mb->op->block);
-    d.occupied = 1;
-    d.rtol = mb->o.rtol;
-    hdesc_[z] = d;
-    upload(z);
-    mb->slot = z;
-    slot_[z] = std::move(mb);
-  }
-  zc_ = 0;
-  for (int z = 0; z < cap_; ++z)
-    if (slot_[z]) zc_ = z + 1;
-  if (zc_ == 0) {
-    phase_ = IDLE;
-    return;
-  }
-  const Slots so = slots(1);
+  double* x = reinterpret_cast<double*>(mb->ws + lay_.off_x);
+  double* b = reinterpret_cast<double*>(mb->ws + lay_.off_b);
+  if (mb->o.x0)
+    RTE_HIP(hipMemcpyAsync(x, mb->o.x0, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
+  else
+    launch_fill_f64(Slots{}, x, 0.0, n, s_);
+  const double* bsrc = mb->o.b ? static_cast<const double*>(mb->o.b) : mb->op->a.b64;
+  RTE_HIP(hipMemcpyAsync(b, bsrc, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
+  SlotDesc d{};
+  d.ws = reinterpret_cast<uint64_t>(mb->ws);
+  d.op = reinterpret_cast<uint64_t>(mb->op->block);
+  d.occupied = 1;
+  d.edge = 1;
+  d.rtol = mb->o.rtol;
+  d.max_iters = mb->o.max_iters;
+  d.bnorm = -1.0;
+  hdesc_[z] = d;
+  upload(z);
+  mb->slot = z;
+  mb->since = t_enq_;
+  mb->bnd_tick = t_enq_;
+  slot_[z] = std::move(mb);
+}
+
+// Cycle boundary of every slot at the edge: combine the ended cycle's steps
+// into x (x += Z y), form the FP64 true residual r = b - L x as V[0], its
+// norm and ||b||, and take the restart-or-finish decision on the device.
+void Batch::boundary_launches(int zc) {
+  Quiet quiet;
+  const Slots so{tab_, zc, GATE_EDGE};
   const Target T{&shape_, rel_, so};
   const Small q = small_of(lay_);
+  const int64_t n = lay_.n;
   const int nb = lay_.nblk, k = k_;
   double* x = off<double>(lay_.off_x);
   double* b = off<double>(lay_.off_b);
@@ -389,156 +397,68 @@ void Batch::boundary() {
   launch_apply(T, x, 1, V, 1, b, true, s_);
   launch_dots(so, V, n, 1, V, n, partn, nb, s_);
   launch_start_cycle(so, partn, nb, off<double>(q.g), k, stat, s_);
-  launch_report(so, stat, off<double>(q.bn), rep_, s_);
-  RTE_HIP(hipMemcpyAsync(hrep_, rep_, size_t(zc_) * 8 * sizeof(double), hipMemcpyDeviceToHost, s_));
-  RTE_HIP(hipEventRecord(ev_rep_, s_));
-  phase_ = RESTART;
+  launch_decide(so, stat, off<double>(q.bn), k, s_);
 }
 
-void Batch::finish_member(Member* mb, rte_status st) {
-  const int z = mb->slot;
-  mb->status = st;
-  mb->ms = now_ms() - mb->t0;
-  RTE_HIP(hipMemcpyAsync(mb->out, mb->ws + lay_.off_x, size_t(lay_.n) * 8, hipMemcpyDeviceToDevice, s_));
-  RTE_HIP(hipEventCreateWithFlags(&mb->copied, hipEventDisableTiming));
-  RTE_HIP(hipEventRecord(mb->copied, s_));
-  hdesc_[z] = SlotDesc{};
-  draining_.push_back(std::move(slot_[z]));
-}
-
-// The host's decision per slot after a boundary report, in the order of
-// the single-solve driver: a non-finite right-hand side, a zero one, a
-// breakdown in the last cycle, convergence of the true residual, the
-// iteration limit, and stagnation (three cycles that each reduce the true
-// residual by less than 0.1%).
-void Batch::decide() {
-  Quiet quiet;
-  int cont = 0;
-  for (int z = 0; z < zc_; ++z) {
-    Member* mb = slot_[z].get();
-    if (!mb) continue;
-    const double* r = hrep_ + 8 * z;
-    const double beta = r[0], bn = r[1];
-    const int jj = int(r[2]);
-    const bool bad = r[3] != 0.0;
-    mb->iters += jj;
-    if (jj > 0) ++mb->restarts;
-    if (mb->bnorm < 0) {
-      mb->bnorm = bn;
-      if (!std::isfinite(bn)) {
-        finish_member(mb, RTE_EINVAL);
-        continue;
-      }
-      if (bn == 0.0) {
-        launch_fill_f64(Slots{}, reinterpret_cast<double*>(mb->ws + lay_.off_x), 0.0, lay_.n, s_);
-        mb->rel = 0;
-        finish_member(mb, RTE_OK);
-        continue;
-      }
-      mb->prev = INFINITY;
-    }
-    mb->rel = beta / mb->bnorm;
-    if (bad || !std::isfinite(beta)) {
-      finish_member(mb, RTE_EBREAKDOWN);
-      continue;
-    }
-    if (mb->rel <= mb->o.rtol) {
-      finish_member(mb, RTE_OK);
-      continue;
-    }
-    if (mb->iters >= mb->o.max_iters) {
-      finish_member(mb, RTE_ENOCONV);
-      continue;
-    }
-    if (beta >= mb->prev * (1.0 - 1e-3)) {
-      if (++mb->stall >= 3) {
-        finish_member(mb, RTE_ENOCONV);
-        continue;
-      }
-    } else {
-      mb->stall = 0;
-    }
-    mb->prev = beta;
-    SlotDesc& d = hdesc_[z];
-    d.live = 1;
-    d.jj = 0;
-    d.bad = 0;
-    d.limit = std::min(k_, mb->o.max_iters - mb->iters);
-    ++cont;
-  }
-  upload_all();
-  nlive_ = cont;
-  if (cont == 0) {
-    boundary();
-    return;
-  }
-  const Small q = small_of(lay_);
-  launch_scale_by(slots(0), off<double>(lay_.off_V), off<double>(q.stat) + 3, lay_.n, s_);  // v_0 = r / beta
-  gcache_ = graphs_ ? step_graphs(tab_, m_, precond_, k_, key_, zc_) : nullptr;
-  j_wait_ = 0;
-  enqueue_step(0);
-  if (k_ > 1) enqueue_step(1);
-  phase_ = STEPS;
-}
-
-// Arnoldi step j for every live slot, with the second Gram-Schmidt
-// correction of each new basis vector lagged into the next step:
+// Arnoldi step j of every live slot, each at its own j, with the second
+// Gram-Schmidt correction of each new basis vector lagged into the next
+// step:
 //   the previous step left w1 = w - V h1 (once corrected, unnormalised) in
-//   V[j]; the preconditioner takes v^_j = w1 / ||w1|| (stat[5]), which is
-//   all flexible GMRES needs of its input (Z_j = M(v^_j) is what enters
-//   A Z = V H);
+//   V[j] (at j = 0: the residual r); the preconditioner takes
+//   v^_j = w1 / ||w1|| (r / beta; scale stat[5]), which is all flexible
+//   GMRES needs of its input (Z_j = M(v^_j) is what enters A Z = V H);
 //   pass 1 completes v_j = (w1 - V h2) / ||w1 - V h2|| (stat[3], h2 from the
-//   previous step) in place and forms h1 = V^T w in the same read of V;
+//   previous step; at j = 0, r / beta) in place and forms h1 = V^T w in the
+//   same read of V;
 //   pass 2 forms w1 = w - V h1 with h2 = V^T w1 and ||w1||^2 in one read;
 //   the finishing kernel sets column j of H (h1 + h2 over
 //   ||w1 - V h2|| = sqrt(||w1||^2 - ||h2||^2)) and the Givens rotation.
-// Two passes over V per step instead of three.
-void Batch::step_body(int j, int zc, hipStream_t s) {
-  const Slots sl{tab_, zc, 0};
-  const Target T{&shape_, rel_, sl};
+// Two passes over V per step instead of three.  The step-indexed operands
+// (V_j, Z_j, V_{j+1}) are passed at j = 0 and moved by each slot's jj.
+void Batch::step_body(int jmax, int zc, hipStream_t s) {
   const int64_t n = lay_.n;
   const int nb = lay_.nblk, k = k_;
   const Small q = small_of(lay_);
   double* V = off<double>(lay_.off_V);
-  const int64_t ldv = lay_.ldv;
-  double* Vj = V + size_t(j) * ldv;
-  double* Vn = V + size_t(j + 1) * ldv;
-  float* Zj = off<float>(lay_.off_Z) + size_t(j) * lay_.ldz;
+  float* Z = off<float>(lay_.off_Z);
+  const int64_t ldv = lay_.ldv, ldz = lay_.ldz;
+  const Slots sl{tab_, zc, GATE_LIVE};
+  const Slots vz{tab_, zc, GATE_LIVE, ldv * 8, ldz * 4};  // V_j in, Z_j out
+  const Slots zv{tab_, zc, GATE_LIVE, ldz * 4, ldv * 8};  // Z_j in, V_{j+1} out
+  const Target Tvz{&shape_, rel_, vz};
+  const Target Tzv{&shape_, rel_, zv};
   double* part1 = off<double>(lay_.off_part1);
   double* part2 = off<double>(lay_.off_part2);
   double* h1 = off<double>(q.h1);
   double* h2 = off<double>(q.h2);
   double* stat = off<double>(q.stat);
   if (mg_)
-    precond_apply(T, *m_, kind_, Vj, Zj, off<char>(lay_.off_mg), s, stat + 5);
+    precond_apply(Tvz, *m_, kind_, V, Z, off<char>(lay_.off_mg), s, stat + 5);
   else if (bj_)
-    launch_block_jacobi(T, Vj, stat + 5, Zj, s);
+    launch_block_jacobi(Tvz, V, stat + 5, Z, s);
   else
-    launch_cast_f64_f32(sl, Vj, stat + 5, Zj, n, s);
-  launch_apply(T, Zj, 0, Vn, 1, nullptr, false, s);
-  if (j == 0)
-    launch_dots(sl, V, ldv, 1, Vn, n, part1, nb, s);
-  else
-    launch_finish_dots(sl, V, ldv, j, h2, stat + 3, Vn, n, part1, nb, s);
-  launch_reduce(sl, part1, nb, j + 1, h1, s);
-  launch_updots(sl, V, ldv, j + 1, h1, Vn, n, part2, nb, s);
-  launch_reduce(sl, part2, nb, j + 2, h2, s);
-  launch_finish_step(sl, h1, h2, j, k, off<double>(q.H), off<double>(q.cs), off<double>(q.sn), off<double>(q.g),
-                     off<double>(q.bn), stat, s);
+    launch_cast_f64_f32(vz, V, stat + 5, Z, n, s);
+  launch_apply(Tzv, Z, 0, V + ldv, 1, nullptr, false, s);
+  launch_finish_dots(sl, V, ldv, jmax, h2, stat + 3, n, part1, nb, s);
+  launch_reduce(sl, part1, nb, jmax + 1, h1, s);
+  launch_updots(sl, V, ldv, jmax, h1, n, part2, nb, s);
+  launch_reduce(sl, part2, nb, jmax + 2, h2, s);
+  launch_finish_step(sl, h1, h2, k, jmax, off<double>(q.H), off<double>(q.cs), off<double>(q.sn),
+                     off<double>(q.g), off<double>(q.bn), stat, s);
 }
 
 namespace {
 
 // Capture the launches of one Arnoldi step on a private stream (nothing runs
 // during capture) and instantiate them as a graph.
-hipGraphExec_t capture_step(Batch& b, int j, int zc) {
+hipGraphExec_t capture_step(Batch& b, int jmax, int zc) {
   thread_local hipStream_t cap = nullptr;
   if (!cap) RTE_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   prof_capturing() = true;
   hipGraph_t g = nullptr;
   RTE_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   try {
-    b.step_body(j, zc, cap);
+    b.step_body(jmax, zc, cap);
   } catch (...) {
     (void)hipStreamEndCapture(cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -556,86 +476,155 @@ hipGraphExec_t capture_step(Batch& b, int j, int zc) {
 
 }  // namespace
 
-// Replays the step's graph (captured on first use); while the kernel-class
-// timer is on, one step in `every` runs eagerly with all of its launches of
-// the enabled classes timed.  The descriptors are copied back after every
-// step so the host can end a cycle early.
-void Batch::enqueue_step(int j) {
+// One tick: admissions into free slots, the boundary launches when a slot
+// waits at an edge, the step (a graph per register budget and slot count;
+// while the kernel-class timer is on, one tick in `every` runs the step
+// eagerly with its launches timed), and the copy of the table.
+void Batch::enqueue_tick() {
+  const int64_t t = t_enq_;
+  bool bnd = false;
+  for (int z = 0; z < cap_ && !waiting_.empty(); ++z)
+    if (!slot_[z]) {
+      Quiet quiet;
+      admit(z);
+      bnd = true;
+    }
+  int hi = 0;
+  for (int z = 0; z < cap_; ++z)
+    if (slot_[z]) {
+      hi = z + 1;
+      if (slot_[z]->edge_pending) bnd = true;
+    }
+  const int zc = std::min(cap_, pow2_at_least(std::max(hi, 1)));
+  if (bnd) {
+    boundary_launches(zc);
+    for (int z = 0; z < cap_; ++z)
+      if (slot_[z]) {
+        slot_[z]->bnd_tick = t;
+        slot_[z]->edge_pending = false;
+      }
+  }
+  // a slot live at the last table read had jj <= snap_jmax_ then and takes
+  // one step per tick since; a slot restarted since has taken fewer
+  const int lag = int(t - 1 - snap_tick_);
+  const int jtrue = std::min(k_ - 1, snap_jmax_ + lag);
+  const int bi = budget_index(jtrue);
+  const int jmax = (8 << bi) - 1;
   const int stride = prof_stride();
   const bool sample = stride > 0 && (g_steps.fetch_add(1) % stride) == 0;
-  if (!gcache_ || sample) {
+  if (!graphs_ || sample) {
+    std::shared_ptr<double> sc;
+    if (sample) {
+      sc = std::make_shared<double>(-1.0);
+      tick_scale_[t % 2] = sc;
+    }
     prof_force() = sample;
     prof_quiet() = !sample;
-    prof_scale() = double(nlive_);
+    prof_scale() = sc;
     try {
-      step_body(j, zc_, s_);
+      step_body(jmax, zc, s_);
     } catch (...) {
       prof_force() = false;
       prof_quiet() = false;
-      prof_scale() = 1.0;
+      prof_scale().reset();
       throw;
     }
     prof_force() = false;
     prof_quiet() = false;
-    prof_scale() = 1.0;
+    prof_scale().reset();
   } else {
-    hipGraphExec_t& ge = (*gcache_)[j];
-    if (!ge) ge = capture_step(*this, j, zc_);
+    std::vector<hipGraphExec_t>* gc = step_graphs(tab_, m_, precond_, k_, key_, zc);
+    hipGraphExec_t& ge = (*gc)[size_t(bi)];
+    if (!ge) ge = capture_step(*this, jmax, zc);
     RTE_HIP(hipGraphLaunch(ge, s_));
   }
-  RTE_HIP(hipMemcpyAsync(hsnap_ + size_t(j % 2) * cap_, tab_, size_t(zc_) * sizeof(SlotDesc),
+  RTE_HIP(hipMemcpyAsync(hsnap_ + size_t(t % 2) * cap_, tab_, size_t(zc) * sizeof(SlotDesc),
                          hipMemcpyDeviceToHost, s_));
-  RTE_HIP(hipEventRecord(ev_step_[j % 2], s_));
-  j_enq_ = j + 1;
+  RTE_HIP(hipEventRecord(ev_tick_[t % 2], s_));
+  tick_zc_[t % 2] = zc;
+  t_enq_ = t + 1;
 }
 
 bool Batch::ready() {
-  hipEvent_t e = nullptr;
-  if (phase_ == RESTART) e = ev_rep_;
-  else if (phase_ == STEPS) e = ev_step_[j_wait_ % 2];
-  else return true;
-  const hipError_t r = hipEventQuery(e);
+  if (t_done_ == t_enq_) return true;
+  const hipError_t r = hipEventQuery(ev_tick_[t_done_ % 2]);
   if (r == hipErrorNotReady) return false;
   RTE_HIP(r);
   return true;
 }
 
 void Batch::wait() {
-  if (phase_ == RESTART) {
-    RTE_HIP(hipEventSynchronize(ev_rep_));
-  } else if (phase_ == STEPS) {
-    RTE_HIP(hipEventSynchronize(ev_step_[j_wait_ % 2]));
+  if (t_done_ < t_enq_) {
+    RTE_HIP(hipEventSynchronize(ev_tick_[t_done_ % 2]));
   } else {
     for (auto& mb : draining_) RTE_HIP(hipEventSynchronize(mb->copied));
   }
 }
 
-void Batch::advance() {
-  switch (phase_) {
-    case IDLE:
-      if (!waiting_.empty()) boundary();
-      return;
-    case RESTART:
-      decide();
-      return;
-    case STEPS: {
-      const int j = j_wait_;
-      const SlotDesc* snap = hsnap_ + size_t(j % 2) * cap_;
-      int live = 0;
-      for (int z = 0; z < zc_; ++z)
-        if (slot_[z] && snap[z].live) ++live;
-      nlive_ = live;
-      if (live == 0 || j + 1 == k_) {
-        // every slot has stopped: a step j + 1 already queued finds no live
-        // slot and changes nothing
-        boundary();
-        return;
-      }
-      j_wait_ = j + 1;
-      if (j + 2 < k_ && j_enq_ == j + 2) enqueue_step(j + 2);
-      return;
+// A finished solve: its x (or zeros, for b = 0) goes to the caller's buffer
+// behind the ticks already queued, which leave the slot untouched.
+void Batch::finish_member(int z, const SlotDesc& d) {
+  std::unique_ptr<Member>& mb = slot_[z];
+  mb->iters = d.iters;
+  mb->restarts = d.restarts;
+  mb->rel = d.rel;
+  mb->status = rte_status(d.code);
+  mb->ms = now_ms() - mb->t0;
+  Quiet quiet;
+  if (d.done == 2)
+    launch_fill_f64(Slots{}, mb->out, 0.0, lay_.n, s_);
+  else
+    RTE_HIP(hipMemcpyAsync(mb->out, mb->ws + lay_.off_x, size_t(lay_.n) * 8, hipMemcpyDeviceToDevice, s_));
+  RTE_HIP(hipEventCreateWithFlags(&mb->copied, hipEventDisableTiming));
+  RTE_HIP(hipEventRecord(mb->copied, s_));
+  draining_.push_back(std::move(mb));
+}
+
+// Reads the table copy of tick t: finished solves, slots waiting at an edge,
+// the largest step of a live slot, and how many slots stepped (the work
+// multiplier of a timed tick).
+void Batch::process(int64_t t) {
+  const SlotDesc* snap = hsnap_ + size_t(t % 2) * cap_;
+  const int zc = tick_zc_[t % 2];
+  int jm = 0, stepped = 0;
+  for (int z = 0; z < zc; ++z) {
+    Member* mb = slot_[z].get();
+    if (!mb || mb->since > t) continue;
+    const SlotDesc& d = snap[z];
+    if (d.steps > mb->steps_seen) {
+      ++stepped;
+      mb->steps_seen = d.steps;
     }
+    if (d.done) {
+      finish_member(z, d);
+      continue;
+    }
+    if (d.live) jm = std::max(jm, int(d.jj));
+    // an edge already covered by a boundary queued after tick t is not new
+    if (d.edge && mb->bnd_tick <= t) mb->edge_pending = true;
   }
+  snap_tick_ = t;
+  snap_jmax_ = jm;
+  if (tick_scale_[t % 2]) {
+    *tick_scale_[t % 2] = double(stepped);
+    tick_scale_[t % 2].reset();
+  }
+  t_done_ = t + 1;
+}
+
+void Batch::fill() {
+  while (t_enq_ - t_done_ < 2) {
+    bool work = !waiting_.empty();
+    for (auto& mb : slot_)
+      if (mb) work = true;
+    if (!work) return;
+    enqueue_tick();
+  }
+}
+
+void Batch::advance() {
+  if (t_done_ < t_enq_) process(t_done_);
+  fill();
 }
 
 void Batch::collect(std::vector<Finished>& out) {
@@ -683,9 +672,20 @@ void Batch::abandon(rte_status st, std::vector<Finished>& out) {
   for (auto& mb : waiting_) give(mb, st);
   draining_.clear();
   waiting_.clear();
+  for (auto& sc : tick_scale_) {
+    if (sc) *sc = 0.0;
+    sc.reset();
+  }
+  t_done_ = t_enq_ = 0;
+  snap_tick_ = -1;
+  snap_jmax_ = 0;
+  // every slot off before the table is used again
   std::memset(hdesc_, 0, size_t(cap_) * sizeof(SlotDesc));
-  phase_ = IDLE;
-  zc_ = 0;
+  try {
+    upload_all();
+    RTE_HIP(hipStreamSynchronize(s_));
+  } catch (...) {
+  }
 }
 
 }  // namespace rte

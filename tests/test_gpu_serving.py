@@ -120,3 +120,40 @@ def test_errors_and_poisoned_request_isolation():
         assert done[t][0] == 0
         x, st = op.solve(**kw)
         assert bool((x == out).all())
+
+
+def test_staggered_joins_and_per_slot_restarts():
+    """Solves that join a running batch at different steps, restart at different
+    steps (short cycles) and reuse freed slots give the results, iteration and
+    restart counts they give alone; the iteration limit and a zero right-hand
+    side end a solve inside the mix."""
+    torch = torch_cuda()
+    from paper_2604_23265_amd import _lib as L
+    from paper_2604_23265_amd import api
+    say("case serving staggered joins, restart 5")
+    reqs = [configs.c3_request(r, ndir_choices=(16,), grid_choices=(32,)) for r in range(100, 107)]
+    models, ops = _build(reqs)
+    kw = [dict(restart=5, rtol=1e-8, precond="bf16") for _ in ops]
+    kw[3]["max_iters"] = 7
+    zero_b = torch.zeros(ops[5].n, dtype=torch.float64, device="cuda")
+    kw[5]["b"] = zero_b
+    alone = []
+    for op, k in zip(ops, kw):
+        x, st = op.solve(**k)
+        alone.append((x.clone(), st))
+    assert alone[3][1]["status"] == L.RTE_ENOCONV and alone[3][1]["iterations"] == 7
+    assert alone[5][1]["converged"] == 1 and alone[5][1]["iterations"] == 0
+    srv = api.Server(arena_bytes=512 << 20, max_slots=3)
+    outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+    tickets = []
+    for i, (op, out, k) in enumerate(zip(ops, outs, kw)):
+        tickets.append(srv.submit(op, out, model=op.model, **k))
+        time.sleep(0.002 * (i % 3))
+    done = _wait(srv, tickets)
+    srv.close()
+    for i, (t, (a, sa), out) in enumerate(zip(tickets, alone, outs)):
+        code, st = done[t]
+        assert code == sa["status"], i
+        assert (st["iterations"], st["restarts"]) == (sa["iterations"], sa["restarts"]), i
+        assert bool((out == a).all()), "result %d differs between alone and in the mix" % i
+    assert bool((outs[5] == 0).all())
