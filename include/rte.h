@@ -198,8 +198,9 @@ rte_status rte_workspace_bytes(const rte_operator* op, const mgnet_model* model,
  * the iterate lives in the workspace, so x0 may alias psi_out).
  * stats (host) is filled on RTE_OK, RTE_ENOCONV and RTE_EBREAKDOWN.
  * Blocks the calling thread until the solve ends.
- * Errors: RTE_EINVAL, RTE_ENOMEM (workspace smaller than required),
- * RTE_ENOCONV, RTE_EBREAKDOWN, RTE_EDEVICE. */
+ * Errors: RTE_EINVAL (also when psi_out, x0 or b is not device memory),
+ * RTE_ENOMEM (workspace smaller than required), RTE_ENOCONV, RTE_EBREAKDOWN,
+ * RTE_EDEVICE. */
 rte_status rte_solve(const rte_operator* op, const mgnet_model* model, const rte_solve_opts* opts,
                      void* workspace, size_t ws_bytes, double* psi_out, rte_solve_stats* stats,
                      void* stream);
@@ -235,7 +236,8 @@ rte_status rte_server_create(void* arena, size_t arena_bytes, int max_slots, rte
 rte_status rte_submit(rte_server* srv, const rte_operator* op, const mgnet_model* model,
                       const rte_solve_opts* opts, double* psi_out, uint64_t* ticket);
 /* RTE_EAGAIN while queued or running; once finished, fills *stats (host,
- * may be NULL), forgets the ticket and returns the solve's own status.
+ * may be NULL), forgets the ticket and returns the solve's own status
+ * (RTE_EINVAL when psi_out, x0 or b turned out not to be device memory).
  * Errors: RTE_ENOTFOUND for an unknown or already collected ticket. */
 rte_status rte_poll(rte_server* srv, uint64_t ticket, rte_solve_stats* stats);
 rte_status rte_server_query(rte_server* srv, rte_server_stats* out);

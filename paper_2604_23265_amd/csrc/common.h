@@ -98,6 +98,25 @@ struct SlotDesc {
 };
 static_assert(sizeof(SlotDesc) == 104, "slot descriptor layout");
 
+// Work the host stages per slot for one tick and hands over in a single
+// transfer and launch: admissions (the descriptor, x0 or null for x = 0, and
+// the right-hand side, as absolute device addresses) and finished results
+// (copy x to out, or zeros for b = 0).
+struct SlotInit {
+  SlotDesc d;
+  uint64_t x0, b;
+  int32_t admit, pad;
+};
+struct SlotEmit {
+  uint64_t out, x;
+  int32_t mode, pad;  // 0: nothing, 1: copy x, 2: zeros
+};
+// For every slot with init[z].admit: x = x0 (or 0) and b copied into the
+// workspace at init[z].d.ws + off_x / off_b, then tab[z] = init[z].d.
+void launch_admit(SlotDesc* tab, const SlotInit* init, int count, int64_t n, uint64_t off_x, uint64_t off_b,
+                  hipStream_t s);
+void launch_emit(const SlotEmit* em, int count, int64_t n, hipStream_t s);
+
 // Launch-wide slot selection.  gate picks the slots a launch runs for;
 // jx and jy are the bytes one Arnoldi step index adds to a launch's
 // step-indexed input and output operand (V_j, Z_j, V_{j+1}), applied with
@@ -437,6 +456,12 @@ class Batch {
   void step_body(int jmax, int zc, hipStream_t s);
 
  private:
+  struct Event {  // one completion event shared by the solves emitted together
+    hipEvent_t e = nullptr;
+    ~Event() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  };
   struct Member {
     void* tag = nullptr;
     const Operator* op = nullptr;
@@ -451,15 +476,14 @@ class Batch {
     int64_t bnd_tick = -1;   // last tick whose boundary launches cover the solve
     bool edge_pending = false;
     rte_status status = RTE_EAGAIN;
-    hipEvent_t copied = nullptr;
+    std::shared_ptr<Event> copied;
   };
   void enqueue_tick();
   void boundary_launches(int zc);
-  void admit(int z);
+  void admit(int z, SlotInit& in);
   void process(int64_t t);
   void fill();
-  void finish_member(int z, const SlotDesc& d);
-  void upload(int slot);
+  void finish_member(int z, const SlotDesc& d, SlotEmit& em);
   void upload_all();
 
   const Operator& shape_;
@@ -470,8 +494,12 @@ class Batch {
   SolveLayout lay_;
   OpArrays rel_;
   SlotDesc* tab_;               // device [cap]
+  SlotInit* dinit_;             // device [cap]: a tick's admissions
+  SlotEmit* demit_;             // device [cap]: a tick's finished results
   hipStream_t s_;
-  SlotDesc* hdesc_ = nullptr;   // pinned: admission descriptors (one per slot)
+  SlotDesc* hdesc_ = nullptr;   // pinned [cap]: all-off descriptors (reset)
+  SlotInit* hinit_ = nullptr;   // pinned [2][cap], by tick parity
+  SlotEmit* hemit_ = nullptr;   // pinned [2][cap], by the parity of the tick read
   SlotDesc* hsnap_ = nullptr;   // pinned [2][cap]: the table after each tick
   hipEvent_t ev_tick_[2] = {nullptr, nullptr};
   int tick_zc_[2] = {0, 0};
@@ -481,6 +509,7 @@ class Batch {
   int64_t t_enq_ = 0, t_done_ = 0;  // ticks enqueued / read back
   int64_t snap_tick_ = -1;          // the last tick read back
   int snap_jmax_ = 0;               // largest step of a live slot in it
+  int zc_ = 0;                      // slots the launches cover (grows while the batch is busy)
   bool graphs_ = true;
 };
 

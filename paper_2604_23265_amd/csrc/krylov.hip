@@ -466,6 +466,37 @@ __global__ __launch_bounds__(KT) void xupdate_kernel(Slots sl, double* __restric
   }
 }
 
+__global__ void admit_kernel(SlotDesc* __restrict__ tab, const SlotInit* __restrict__ init, int64_t n,
+                             uint64_t off_x, uint64_t off_b) {
+  const int z = blockIdx.z;
+  if (!init[z].admit) return;
+  const uint64_t ws = init[z].d.ws;
+  double* __restrict__ x = reinterpret_cast<double*>(ws + off_x);
+  double* __restrict__ b = reinterpret_cast<double*>(ws + off_b);
+  const double* __restrict__ x0 = reinterpret_cast<const double*>(init[z].x0);
+  const double* __restrict__ bs = reinterpret_cast<const double*>(init[z].b);
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    x[e] = x0 ? x0[e] : 0.0;
+    b[e] = bs[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) tab[z] = init[z].d;
+}
+
+__global__ void emit_kernel(const SlotEmit* __restrict__ em, int64_t n) {
+  const int z = blockIdx.z;
+  const int mode = em[z].mode;
+  if (!mode) return;
+  double* __restrict__ out = reinterpret_cast<double*>(em[z].out);
+  const double* __restrict__ x = reinterpret_cast<const double*>(em[z].x);
+  if (mode == 1) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+      out[e] = x[e];
+  } else {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+      out[e] = 0.0;
+  }
+}
+
 unsigned ew_grid(int64_t n) {
   int64_t g = (n + KT - 1) / KT;
   if (g > 8192) g = 8192;
@@ -565,6 +596,18 @@ void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int
 void launch_decide(const Slots& sl, const double* stat, const double* bn, int k, hipStream_t s) {
   RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the boundary decision runs under a slot table");
   hipLaunchKernelGGL(decide_kernel, z3(1, sl), dim3(64), 0, s, sl, stat, bn, k);
+  RTE_HIP(hipGetLastError());
+}
+
+void launch_admit(SlotDesc* tab, const SlotInit* init, int count, int64_t n, uint64_t off_x, uint64_t off_b,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(admit_kernel, dim3(ew_grid(n), 1, unsigned(count)), dim3(KT), 0, s, tab, init, n, off_x,
+                     off_b);
+  RTE_HIP(hipGetLastError());
+}
+
+void launch_emit(const SlotEmit* em, int count, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(emit_kernel, dim3(ew_grid(n), 1, unsigned(count)), dim3(KT), 0, s, em, n);
   RTE_HIP(hipGetLastError());
 }
 

@@ -157,7 +157,10 @@ SolveLayout solve_layout(const Operator& op, const Model* m, int k, bool mgnet) 
   return L;
 }
 
-size_t batch_table_bytes(int capacity) { return align256(size_t(capacity) * sizeof(SlotDesc)); }
+size_t batch_table_bytes(int capacity) {
+  return align256(size_t(capacity) * sizeof(SlotDesc)) + align256(size_t(capacity) * sizeof(SlotInit)) +
+         align256(size_t(capacity) * sizeof(SlotEmit));
+}
 
 namespace {
 
@@ -253,6 +256,8 @@ Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capa
   lay_ = solve_layout(shape, m, k, mg_);
   rel_ = shape.relative();
   tab_ = reinterpret_cast<SlotDesc*>(tables);
+  dinit_ = reinterpret_cast<SlotInit*>(tables + align256(size_t(capacity) * sizeof(SlotDesc)));
+  demit_ = reinterpret_cast<SlotEmit*>(reinterpret_cast<char*>(dinit_) + align256(size_t(capacity) * sizeof(SlotInit)));
   if (mg_) const_cast<Model*>(m)->ensure_on_device();
   const char* env = std::getenv("RTE_GRAPHS");
   graphs_ = !(env && env[0] == '0');
@@ -261,23 +266,29 @@ Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capa
                         hipHostMallocDefault));
   RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsnap_), 2 * size_t(capacity) * sizeof(SlotDesc),
                         hipHostMallocDefault));
+  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hinit_), 2 * size_t(capacity) * sizeof(SlotInit),
+                        hipHostMallocDefault));
+  RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&hemit_), 2 * size_t(capacity) * sizeof(SlotEmit),
+                        hipHostMallocDefault));
   std::memset(hdesc_, 0, size_t(capacity) * sizeof(SlotDesc));
   std::memset(hsnap_, 0, 2 * size_t(capacity) * sizeof(SlotDesc));
+  std::memset(hinit_, 0, 2 * size_t(capacity) * sizeof(SlotInit));
+  std::memset(hemit_, 0, 2 * size_t(capacity) * sizeof(SlotEmit));
   for (auto& e : ev_tick_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   upload_all();
 }
 
 Batch::~Batch() {
   (void)hipStreamSynchronize(s_);
-  for (auto* v : {&waiting_, &draining_})
-    for (auto& mb : *v)
-      if (mb && mb->copied) (void)hipEventDestroy(mb->copied);
-  for (auto& mb : slot_)
-    if (mb && mb->copied) (void)hipEventDestroy(mb->copied);
+  waiting_.clear();
+  draining_.clear();
+  slot_.clear();
   for (auto& e : ev_tick_)
     if (e) (void)hipEventDestroy(e);
   if (hdesc_) (void)hipHostFree(hdesc_);
   if (hsnap_) (void)hipHostFree(hsnap_);
+  if (hinit_) (void)hipHostFree(hinit_);
+  if (hemit_) (void)hipHostFree(hemit_);
 }
 
 bool Batch::compatible(const Operator& op, const Model* m, int k, int precond) const {
@@ -297,17 +308,22 @@ bool Batch::idle() const {
   return t_done_ == t_enq_ && members() == 0 && draining_.empty();
 }
 
-// Descriptor uploads come from the slot's own pinned entry, written only at
-// admission; a slot is admitted again only after the host has read its
-// previous solve's end from a later table copy, so the earlier upload has
-// long completed.
-void Batch::upload(int z) {
-  RTE_HIP(hipMemcpyAsync(tab_ + z, hdesc_ + z, sizeof(SlotDesc), hipMemcpyHostToDevice, s_));
-}
-
 void Batch::upload_all() {
   RTE_HIP(hipMemcpyAsync(tab_, hdesc_, size_t(cap_) * sizeof(SlotDesc), hipMemcpyHostToDevice, s_));
 }
+
+namespace {
+// The admission and result launches read x0 and b and write the output in
+// a kernel: each must be device memory (a host address would fault there).
+void require_device(const void* p, const char* what) {
+  hipPointerAttribute_t a{};
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) (void)hipGetLastError();  // clear the sticky query error
+  RTE_REQUIRE(e == hipSuccess && (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged ||
+                                  a.type == hipMemoryTypeUnified || a.isManaged),
+              RTE_EINVAL, std::string(what) + " must be device memory");
+}
+}  // namespace
 
 void Batch::add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws, double* out, double t_start) {
   RTE_REQUIRE(o.restart == k_ && o.precond == precond_ && op.shape_key() == key_ && (!mg_ || op.model == m_),
@@ -315,6 +331,9 @@ void Batch::add(void* tag, const Operator& op, const rte_solve_opts& o, char* ws
   RTE_REQUIRE(!full(), RTE_EINVAL, "batch is full");
   RTE_REQUIRE(ws && out && (reinterpret_cast<uintptr_t>(ws) & 255) == 0, RTE_EINVAL,
               "bad workspace or output");
+  require_device(out, "the output");
+  if (o.x0) require_device(o.x0, "x0");
+  if (o.b) require_device(o.b, "b");
   std::unique_ptr<Member> mb(new Member());
   mb->tag = tag;
   mb->op = &op;
@@ -342,22 +361,14 @@ int budget_index(int jmax) {
 }
 }  // namespace
 
-// A waiting solve takes slot z: x = x0 (or 0), the right-hand side is copied
-// into the workspace, and the descriptor marks the slot at a cycle edge
-// with no steps taken, so the next boundary launches form r = b - L x and
-// decide (normally: a first cycle).
-void Batch::admit(int z) {
+// A waiting solve takes slot z: staged for the tick's admission launch,
+// which sets x = x0 (or 0), copies the right-hand side into the workspace
+// and writes the descriptor: the slot waits at a cycle edge with no steps
+// taken, so the boundary launches that follow form r = b - L x and decide
+// (normally: a first cycle).
+void Batch::admit(int z, SlotInit& in) {
   std::unique_ptr<Member> mb = std::move(waiting_.front());
   waiting_.erase(waiting_.begin());
-  const int64_t n = lay_.n;
-  double* x = reinterpret_cast<double*>(mb->ws + lay_.off_x);
-  double* b = reinterpret_cast<double*>(mb->ws + lay_.off_b);
-  if (mb->o.x0)
-    RTE_HIP(hipMemcpyAsync(x, mb->o.x0, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
-  else
-    launch_fill_f64(Slots{}, x, 0.0, n, s_);
-  const double* bsrc = mb->o.b ? static_cast<const double*>(mb->o.b) : mb->op->a.b64;
-  RTE_HIP(hipMemcpyAsync(b, bsrc, size_t(n) * 8, hipMemcpyDeviceToDevice, s_));
   SlotDesc d{};
   d.ws = reinterpret_cast<uint64_t>(mb->ws);
   d.op = reinterpret_cast<uint64_t>(mb->op->block);
@@ -366,8 +377,10 @@ void Batch::admit(int z) {
   d.rtol = mb->o.rtol;
   d.max_iters = mb->o.max_iters;
   d.bnorm = -1.0;
-  hdesc_[z] = d;
-  upload(z);
+  in.d = d;
+  in.x0 = reinterpret_cast<uint64_t>(mb->o.x0);
+  in.b = reinterpret_cast<uint64_t>(mb->o.b ? static_cast<const double*>(mb->o.b) : mb->op->a.b64);
+  in.admit = 1;
   mb->slot = z;
   mb->since = t_enq_;
   mb->bnd_tick = t_enq_;
@@ -482,20 +495,30 @@ hipGraphExec_t capture_step(Batch& b, int jmax, int zc) {
 // eagerly with its launches timed), and the copy of the table.
 void Batch::enqueue_tick() {
   const int64_t t = t_enq_;
+  SlotInit* init = hinit_ + size_t(t % 2) * cap_;
   bool bnd = false;
   for (int z = 0; z < cap_ && !waiting_.empty(); ++z)
     if (!slot_[z]) {
-      Quiet quiet;
-      admit(z);
+      if (!bnd) std::memset(init, 0, size_t(cap_) * sizeof(SlotInit));
+      admit(z, init[z]);
       bnd = true;
     }
+  const bool admitted = bnd;
   int hi = 0;
   for (int z = 0; z < cap_; ++z)
     if (slot_[z]) {
       hi = z + 1;
       if (slot_[z]->edge_pending) bnd = true;
     }
-  const int zc = std::min(cap_, pow2_at_least(std::max(hi, 1)));
+  // the launches cover a power-of-two prefix of the slots that only grows
+  // while the batch is busy, so few step graphs exist per batch
+  zc_ = std::max(zc_, std::min(cap_, pow2_at_least(std::max(hi, 1))));
+  const int zc = zc_;
+  if (admitted) {
+    Quiet quiet;
+    RTE_HIP(hipMemcpyAsync(dinit_, init, size_t(zc) * sizeof(SlotInit), hipMemcpyHostToDevice, s_));
+    launch_admit(tab_, dinit_, zc, lay_.n, lay_.off_x, lay_.off_b, s_);
+  }
   if (bnd) {
     boundary_launches(zc);
     for (int z = 0; z < cap_; ++z)
@@ -557,35 +580,35 @@ void Batch::wait() {
   if (t_done_ < t_enq_) {
     RTE_HIP(hipEventSynchronize(ev_tick_[t_done_ % 2]));
   } else {
-    for (auto& mb : draining_) RTE_HIP(hipEventSynchronize(mb->copied));
+    for (auto& mb : draining_) RTE_HIP(hipEventSynchronize(mb->copied->e));
   }
 }
 
 // A finished solve: its x (or zeros, for b = 0) goes to the caller's buffer
-// behind the ticks already queued, which leave the slot untouched.
-void Batch::finish_member(int z, const SlotDesc& d) {
+// by the emit launch queued behind the ticks already in flight, which leave
+// the slot untouched.
+void Batch::finish_member(int z, const SlotDesc& d, SlotEmit& em) {
   std::unique_ptr<Member>& mb = slot_[z];
   mb->iters = d.iters;
   mb->restarts = d.restarts;
   mb->rel = d.rel;
   mb->status = rte_status(d.code);
   mb->ms = now_ms() - mb->t0;
-  Quiet quiet;
-  if (d.done == 2)
-    launch_fill_f64(Slots{}, mb->out, 0.0, lay_.n, s_);
-  else
-    RTE_HIP(hipMemcpyAsync(mb->out, mb->ws + lay_.off_x, size_t(lay_.n) * 8, hipMemcpyDeviceToDevice, s_));
-  RTE_HIP(hipEventCreateWithFlags(&mb->copied, hipEventDisableTiming));
-  RTE_HIP(hipEventRecord(mb->copied, s_));
+  em.out = reinterpret_cast<uint64_t>(mb->out);
+  em.x = reinterpret_cast<uint64_t>(mb->ws + lay_.off_x);
+  em.mode = d.done == 2 ? 2 : 1;
   draining_.push_back(std::move(mb));
 }
 
-// Reads the table copy of tick t: finished solves, slots waiting at an edge,
-// the largest step of a live slot, and how many slots stepped (the work
-// multiplier of a timed tick).
+// Reads the table copy of tick t: finished solves (emitted together, with
+// one completion event), slots waiting at an edge, the largest step of a
+// live slot, and how many slots stepped (the work multiplier of a timed
+// tick).
 void Batch::process(int64_t t) {
   const SlotDesc* snap = hsnap_ + size_t(t % 2) * cap_;
+  SlotEmit* em = hemit_ + size_t(t % 2) * cap_;
   const int zc = tick_zc_[t % 2];
+  const size_t first_out = draining_.size();
   int jm = 0, stepped = 0;
   for (int z = 0; z < zc; ++z) {
     Member* mb = slot_[z].get();
@@ -596,12 +619,22 @@ void Batch::process(int64_t t) {
       mb->steps_seen = d.steps;
     }
     if (d.done) {
-      finish_member(z, d);
+      if (draining_.size() == first_out) std::memset(em, 0, size_t(zc) * sizeof(SlotEmit));
+      finish_member(z, d, em[z]);
       continue;
     }
     if (d.live) jm = std::max(jm, int(d.jj));
     // an edge already covered by a boundary queued after tick t is not new
     if (d.edge && mb->bnd_tick <= t) mb->edge_pending = true;
+  }
+  if (draining_.size() > first_out) {
+    Quiet quiet;
+    RTE_HIP(hipMemcpyAsync(demit_, em, size_t(zc) * sizeof(SlotEmit), hipMemcpyHostToDevice, s_));
+    launch_emit(demit_, zc, lay_.n, s_);
+    std::shared_ptr<Event> ev(new Event());
+    RTE_HIP(hipEventCreateWithFlags(&ev->e, hipEventDisableTiming));
+    RTE_HIP(hipEventRecord(ev->e, s_));
+    for (size_t i = first_out; i < draining_.size(); ++i) draining_[i]->copied = ev;
   }
   snap_tick_ = t;
   snap_jmax_ = jm;
@@ -617,7 +650,10 @@ void Batch::fill() {
     bool work = !waiting_.empty();
     for (auto& mb : slot_)
       if (mb) work = true;
-    if (!work) return;
+    if (!work) {
+      if (t_enq_ == t_done_) zc_ = 0;  // nothing in flight or held: start small again
+      return;
+    }
     enqueue_tick();
   }
 }
@@ -630,7 +666,7 @@ void Batch::advance() {
 void Batch::collect(std::vector<Finished>& out) {
   for (size_t i = 0; i < draining_.size();) {
     Member* mb = draining_[i].get();
-    const hipError_t r = hipEventQuery(mb->copied);
+    const hipError_t r = hipEventQuery(mb->copied->e);
     if (r == hipErrorNotReady) {
       ++i;
       continue;
@@ -646,8 +682,6 @@ void Batch::collect(std::vector<Finished>& out) {
     f.stats.rel_residual = mb->rel;
     f.stats.ms_total = mb->ms;
     out.push_back(f);
-    (void)hipEventDestroy(mb->copied);
-    mb->copied = nullptr;
     draining_.erase(draining_.begin() + long(i));
   }
 }
@@ -664,7 +698,6 @@ void Batch::abandon(rte_status st, std::vector<Finished>& out) {
     f.stats.status = code;
     f.stats.rel_residual = mb->rel;
     out.push_back(f);
-    if (mb->copied) (void)hipEventDestroy(mb->copied);
     mb.reset();
   };
   for (auto& mb : draining_) give(mb, mb->status);
@@ -679,6 +712,7 @@ void Batch::abandon(rte_status st, std::vector<Finished>& out) {
   t_done_ = t_enq_ = 0;
   snap_tick_ = -1;
   snap_jmax_ = 0;
+  zc_ = 0;
   // every slot off before the table is used again
   std::memset(hdesc_, 0, size_t(cap_) * sizeof(SlotDesc));
   try {
