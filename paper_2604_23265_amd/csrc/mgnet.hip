@@ -508,19 +508,25 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(const ConvArgs A0) {
 }
 
 // Tiled 2D BF16 convolution: one block computes an 8x8 patch of the
-// virtual grid for 32 output channels.  Per 32-channel input chunk the
-// block stages the patch's input footprint (rounded to BF16) and the
-// chunk's weights for its 32 output channels in LDS, both with an 80-byte
-// row stride; while the chunk's MFMAs run, the next chunk's global loads
-// are already in flight in registers.  Wave w owns patch rows 2w and 2w + 1
-// (16 pixels) and both 16-channel column tiles.
+// virtual grid for 32 or 64 output channels.  Per 32-channel input chunk
+// the block stages the patch's input footprint (rounded to BF16) and the
+// chunk's weights for its output channels in LDS, both in swizzled 64-byte
+// rows; while the chunk's MFMAs run, the next chunk's global loads are
+// already in flight in registers.  Wave w owns patch rows 2w and 2w + 1
+// (16 pixels) and every 16-channel column tile.
 //
 // CK = 0: 3x3 stride 1; CK = 1: 3x3 stride 2 (restriction); CK = 2: the
 // 4x4 stride-2 transposed convolution, one parity class per grid-z index.
 // Every output element accumulates its chunks in order and, within a chunk,
 // its taps in order -- the same chain whatever the launch shape, so results
 // do not depend on how many solves share the launch.
-constexpr int TILE_ROW_WORDS = 20;  // 32 BF16 (16 words) + 4 words of padding
+// LDS rows of the tiled conv: 32 BF16 (64 bytes, four 16-byte chunks), no
+// padding; chunk q of row r sits at chunk q ^ ((r >> 1) & 3).  Measured on
+// gfx950 with the bank-conflict counter, this order makes the 16-byte
+// fragment reads of the weights and both staging stores conflict-free (an
+// 80-byte padded row spends half of its LDS cycles in conflicts).
+constexpr int TILE_ROW_WORDS = 16;
+__device__ inline int tile_word(int row, int chunk) { return row * TILE_ROW_WORDS + 4 * (chunk ^ ((row >> 1) & 3)); }
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 template <int CK, int NI>
@@ -634,7 +640,7 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
         const v4f v = rin[i];
         const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
         const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
-        *reinterpret_cast<uint2*>(xin + pix * TILE_ROW_WORDS + q4 * 2) = make_uint2(lo, hi);
+        *reinterpret_cast<uint2*>(xin + tile_word(pix, q4 >> 1) + 2 * (q4 & 1)) = make_uint2(lo, hi);
       }
     }
 #pragma unroll
@@ -643,7 +649,7 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
       constexpr int PER_TAP = G::NCO * 4;
       if (idx < G::NTAP * PER_TAP) {
         const int t = idx / PER_TAP, rem = idx - (idx / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
-        *reinterpret_cast<v4u*>(wsm + (t * G::NCO + co) * TILE_ROW_WORDS + q8 * 4) = rw[i];
+        *reinterpret_cast<v4u*>(wsm + tile_word(t * G::NCO + co, q8)) = rw[i];
       }
     }
   };
@@ -668,10 +674,10 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
       const int dy = CK == 2 ? py_par - (t >> 1) : t / 3 - 1;
       const int fx = G::S * (px0 + lx) + dx - ox0;
       const int fy = G::S * (py0 + ly) + dy - oy0;
-      const v8bf av = *reinterpret_cast<const v8bf*>(xin + (fy * G::FP + fx) * TILE_ROW_WORDS + grp * 4);
+      const v8bf av = *reinterpret_cast<const v8bf*>(xin + tile_word(fy * G::FP + fx, grp));
 #pragma unroll
       for (int ni = 0; ni < NI; ++ni) {
-        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + (t * G::NCO + ni * 16 + li) * TILE_ROW_WORDS + grp * 4);
+        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + tile_word(t * G::NCO + ni * 16 + li, grp));
         acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
       }
     }
