@@ -35,10 +35,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_tile_kernel_c2_traffic.md")
 
 
 def measured_traffic():
-    """HBM bytes per conv launch from the committed counter summary, or None.
+    """(HBM bytes per conv launch, algorithmic bytes per launch of the same
+    launches) from the committed counter summary, or (None, None).
 
     The summary records the SHA-256 of the convolution source it was taken
-    with; a changed kernel makes the figure stale, so it is not reported.
+    with; a changed kernel makes the figures stale, so they are not reported.
     """
     import hashlib
     try:
@@ -49,10 +50,10 @@ def measured_traffic():
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip()
         if fields.get("source-sha256") != src:
-            return None
-        return float(fields["hbm-bytes-per-launch"])
+            return None, None
+        return float(fields["hbm-bytes-per-launch"]), float(fields["algorithmic-bytes-per-launch"])
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
 
 
 def log(*a):
@@ -293,9 +294,11 @@ def main():
             # 2500/8 = 312: HBM is the bound; MFMA use is reported beside it
             gbs = nbytes / (ms * 1e-3) / 1e9
             tflops = work / (ms * 1e-3) / 1e12
+            traffic, traffic_alg = measured_traffic()
             out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                               "traffic_unit": "HBM bytes per launch (counters)",
+                               "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                               "traffic_unit": "HBM bytes per launch (counters, every launch of one batch)",
+                               "traffic_over_algorithmic": (traffic / traffic_alg) if traffic else None,
                                "kernel": "conv_tile_kernel (3x3 stride-1/stride-2 and transposed 4x4 "
                                          "convolutions of the V-cycle, BF16 MFMA, all solves of the batch per launch)",
                                "timed_launches": launches, "sampling": samp,
