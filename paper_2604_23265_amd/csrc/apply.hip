@@ -15,6 +15,8 @@
 namespace rte {
 namespace {
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // A block of 256 threads owns TL consecutive cells: thread t -> cell t % TL,
 // direction slot t / TL (256 / TL slots).  TL = 64 (one slot per wave) for
 // up to 64 directions, TL = 16 beyond.
@@ -133,13 +135,27 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   }
 }
 
+// Tile of block x when consecutive tiles should share an L2: the
+// dispatcher deals workgroups to the eight XCDs round-robin by linear id
+// (x % 8 when the grid's x extent is a multiple of 8), so tile
+// (x % 8) (T / 8) + x / 8 gives XCD k the contiguous tiles
+// [k T / 8, (k + 1) T / 8), and the upwind neighbour rows a tile reads from
+// the tiles beside it are mostly in its own L2 instead of another XCD's.
+__device__ inline int xcd_tile(int x, int T) { return (T & 7) ? x : (x & 7) * (T >> 3) + (x >> 3); }
+
 // FP32 apply with one direction slot per wave (up to 128 directions): a
-// block owns 64 consecutive cells, lane = cell, wave w = directions w,
-// w + 4, ... (at most DPT of them).  The scatter's matrix entries are then
-// the same for the whole wave and come from scalar loads of the slot-packed
-// S (one LDS read of x_n feeds DPT FMAs); upwind neighbours are requested
-// at clamped addresses before the scatter and zeroed outside the grid.
-template <class TO, int DPT, bool D3>
+// block takes TPB tiles of 64 consecutive cells in turn, lane = cell, wave
+// w = directions w, w + 4, ... (at most DPT of them).  The scatter's matrix
+// entries are then the same for the whole wave; with LS the block stages
+// the slot-packed S in LDS once, with one vector load per thread, and the
+// scatter reads it with broadcast LDS reads (scalar loads of S, one wait
+// per two directions, serialised the scatter), else they come from scalar
+// loads.  The per-
+// direction upwind signs and coefficients and the cell's sigma values are
+// requested before any address that uses them, so the upwind neighbours are
+// requested together; they are read at clamped addresses and zeroed outside
+// the grid.
+template <class TO, int DPT, bool D3, bool LS, int TPB>
 __global__ __launch_bounds__(256) void apply_slot_kernel(Slots sl, const float* __restrict__ x, TO* __restrict__ y,
                                                          const float* __restrict__ sT, const float* __restrict__ sA,
                                                          const float* __restrict__ Sp, const float* __restrict__ dc,
@@ -155,71 +171,107 @@ __global__ __launch_bounds__(256) void apply_slot_kernel(Slots sl, const float* 
   dc = at(dc, bs.op);
   sg = at(sg, bs.op);
   constexpr int NA = D3 ? 3 : 2;
-  extern __shared__ float xs[];  // [N][64]
+  extern __shared__ float xs[];  // [N][64] x tile; with LS then S as [4][N][DPT]
+  float* ss = xs + N * 64;
   const int lane = threadIdx.x & 63;
   const int slot = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  const int c0 = int(blockIdx.x) * 64;
-  const int c = c0 + lane;
-  const int cc = c < cells ? c : cells - 1;
-  // stage x[:, tile]: this thread's rows are its own directions, so the
-  // loads of all of them are issued together
-  float xown[DPT];
-#pragma unroll
-  for (int q = 0; q < DPT; ++q) {
-    const int m = slot + 4 * q;
-    const float v = x[int64_t(m < N ? m : N - 1) * cells + cc];
-    xown[q] = c < cells ? v : 0.f;
-  }
-  const int rr = cc / nx;
-  const int i = cc - rr * nx;
-  const int k = rr / ny;
-  const int j = rr - k * ny;
-  const int pos[3] = {i, j, k};
-  const int ext[3] = {nx, ny, nz};
-  const int stride[3] = {1, nx, nx * ny};
-  float xnb[DPT][NA];
+  int sgn[DPT][NA];
+  float dcv[DPT][NA];
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
     const int m = slot + 4 * q;
     const int mc = m < N ? m : N - 1;
-    const int64_t o = int64_t(mc) * cells + cc;
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
-      const int sgn = sg[4 * mc + a];
-      const int p = pos[a] - sgn;
-      const bool inb = p >= 0 && p < ext[a];
-      const float v = x[inb ? o - sgn * stride[a] : o];
-      xnb[q][a] = inb ? v : 0.f;
+      sgn[q][a] = sg[4 * mc + a];
+      dcv[q][a] = dc[4 * mc + a];
     }
   }
-#pragma unroll
-  for (int q = 0; q < DPT; ++q) {
-    const int m = slot + 4 * q;
-    if (m < N) xs[m * 64 + lane] = xown[q];
+  if constexpr (LS) {
+    const int ns = 4 * N * DPT;  // a multiple of 4
+    for (int i = 4 * int(threadIdx.x); i < ns; i += 4 * 256)
+      *reinterpret_cast<v4f*>(ss + i) = *reinterpret_cast<const v4f*>(Sp + i);
   }
-  __syncthreads();
-  float acc[DPT];
+  // the block's TPB tiles of 64 cells, one after another (S staged once)
+  const int ntile = (cells + 63) / 64;
+  const int tb = xcd_tile(int(blockIdx.x), int(gridDim.x)) * TPB;
+  for (int tt = 0; tt < TPB; ++tt) {
+    const int tile = tb + tt;
+    if (tile >= ntile) break;  // uniform over the block
+    if (tt > 0) __syncthreads();  // the previous tile's reads of xs are done
+    const int c = tile * 64 + lane;
+    const int cc = c < cells ? c : cells - 1;
+    const float st = sT[cc], sa = sA[cc];
+    // x[:, tile]: this thread's rows are its own directions
+    float xown[DPT];
 #pragma unroll
-  for (int q = 0; q < DPT; ++q) acc[q] = 0.f;
-  const float* __restrict__ sp = Sp + slot * N * DPT;
-#pragma unroll 2
-  for (int n = 0; n < N; ++n) {
-    const float xv = xs[n * 64 + lane];
+    for (int q = 0; q < DPT; ++q) {
+      const int m = slot + 4 * q;
+      const float v = x[int64_t(m < N ? m : N - 1) * cells + cc];
+      xown[q] = c < cells ? v : 0.f;
+    }
+    const int rr = cc / nx;
+    const int i = cc - rr * nx;
+    const int k = rr / ny;
+    const int j = rr - k * ny;
+    const int pos[3] = {i, j, k};
+    const int ext[3] = {nx, ny, nz};
+    const int stride[3] = {1, nx, nx * ny};
+    float xnb[DPT][NA];
 #pragma unroll
-    for (int q = 0; q < DPT; ++q) acc[q] += sp[n * DPT + q] * xv;
-  }
-  if (c >= cells) return;
-  const float st = sT[c], sa = sA[c];
+    for (int q = 0; q < DPT; ++q) {
+      const int m = slot + 4 * q;
+      const int mc = m < N ? m : N - 1;
+      const int64_t o = int64_t(mc) * cells + cc;
 #pragma unroll
-  for (int q = 0; q < DPT; ++q) {
-    const int m = slot + 4 * q;
-    if (m >= N) break;
-    const float xc = xown[q];
-    float str = 0.f;
+      for (int a = 0; a < NA; ++a) {
+        const int p = pos[a] - sgn[q][a];
+        const bool inb = p >= 0 && p < ext[a];
+        const float v = x[inb ? o - sgn[q][a] * stride[a] : o];
+        xnb[q][a] = inb ? v : 0.f;
+      }
+    }
 #pragma unroll
-    for (int a = 0; a < NA; ++a) str += dc[4 * m + a] * (xc - xnb[q][a]);
-    const float val = str + st * (xc - acc[q]) + sa * acc[q];
-    y[int64_t(m) * cells + c] = TO(val);
+    for (int q = 0; q < DPT; ++q) {
+      const int m = slot + 4 * q;
+      if (m < N) xs[m * 64 + lane] = xown[q];
+    }
+    __syncthreads();
+    float acc[DPT];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) acc[q] = 0.f;
+    if constexpr (LS) {
+      const float* sp = ss + slot * N * DPT;
+#pragma unroll 4
+      for (int n = 0; n < N; ++n) {
+        const float xv = xs[n * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) acc[q] += sp[n * DPT + q] * xv;
+      }
+    } else {
+      // DPT scalar registers per direction n; four directions per wait up to
+      // DPT = 16 (64 SGPRs), two beyond
+      const float* __restrict__ sp = Sp + slot * N * DPT;
+#pragma unroll(DPT <= 16 ? 4 : 2)
+      for (int n = 0; n < N; ++n) {
+        const float xv = xs[n * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) acc[q] += sp[n * DPT + q] * xv;
+      }
+    }
+    if (c < cells) {
+#pragma unroll
+      for (int q = 0; q < DPT; ++q) {
+        const int m = slot + 4 * q;
+        if (m >= N) break;
+        const float xc = xown[q];
+        float str = 0.f;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) str += dcv[q][a] * (xc - xnb[q][a]);
+        const float val = str + st * (xc - acc[q]) + sa * acc[q];
+        y[int64_t(m) * cells + c] = TO(val);
+      }
+    }
   }
 }
 
@@ -227,21 +279,39 @@ template <class TO, bool D3>
 void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const ProfScope& ps) {
   const Operator& op = *Tg.op;
   const OpArrays& A = Tg.arr;
-  const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(Tg.sl.count));
-  const size_t lds = size_t(op.ndir) * 64 * sizeof(float);
+  const int dpt = slot_budget(op.ndir);
+  const size_t lds_x = size_t(op.ndir) * 64 * sizeof(float);
+  const size_t lds_s = size_t(4) * op.ndir * dpt * sizeof(float);  // slot-packed S
+  // S in LDS where its staging (4 N DPT floats per block) is at most half of
+  // the block's x tile: up to 32 directions.  With more directions the
+  // staging and the LDS it holds cost more than the scalar loads it saves
+  // (measured at 64 directions, with one and with four tiles per block).
+  const bool ls = dpt <= 8 && lds_x + lds_s <= 64 * 1024;
+  const size_t lds = ls ? lds_x + lds_s : lds_x;
+  constexpr int TPB_LS = 1;
+  const int64_t ntile = (op.cells + 63) / 64;
+  const dim3 grid(unsigned(ls ? (ntile + TPB_LS - 1) / TPB_LS : ntile), 1, unsigned(Tg.sl.count));
   auto launch = [&](auto kern) {
     launch_k(kern, grid, dim3(256), uint32_t(lds), s, ps, Tg.sl, static_cast<const float*>(x), static_cast<TO*>(y),
              A.sT32, A.sA32, A.Sp32, A.dc32, static_cast<const int*>(A.dsgn), op.ndir, op.nx, op.ny, op.nz,
              int(op.cells));
   };
-  switch (slot_budget(op.ndir)) {
-    case 1: launch(apply_slot_kernel<TO, 1, D3>); break;
-    case 2: launch(apply_slot_kernel<TO, 2, D3>); break;
-    case 4: launch(apply_slot_kernel<TO, 4, D3>); break;
-    case 8: launch(apply_slot_kernel<TO, 8, D3>); break;
-    case 16: launch(apply_slot_kernel<TO, 16, D3>); break;
-    default: launch(apply_slot_kernel<TO, 32, D3>); break;
-  }
+  auto pick = [&](auto ls_tag) {
+    constexpr bool LS = decltype(ls_tag)::value;
+    constexpr int TPB = LS ? TPB_LS : 1;
+    switch (dpt) {
+      case 1: launch(apply_slot_kernel<TO, 1, D3, LS, TPB>); break;
+      case 2: launch(apply_slot_kernel<TO, 2, D3, LS, TPB>); break;
+      case 4: launch(apply_slot_kernel<TO, 4, D3, LS, TPB>); break;
+      case 8: launch(apply_slot_kernel<TO, 8, D3, LS, TPB>); break;
+      case 16: launch(apply_slot_kernel<TO, 16, D3, LS, TPB>); break;
+      default: launch(apply_slot_kernel<TO, 32, D3, LS, TPB>); break;
+    }
+  };
+  if (ls)
+    pick(std::true_type{});
+  else
+    pick(std::false_type{});
   RTE_HIP(hipGetLastError());
 }
 
