@@ -235,6 +235,16 @@ rte_status rte_server_create(void* arena, size_t arena_bytes, int max_slots, rte
  * (the request can never fit the arena), RTE_EAGAIN (queue of 4096 full). */
 rte_status rte_submit(rte_server* srv, const rte_operator* op, const mgnet_model* model,
                       const rte_solve_opts* opts, double* psi_out, uint64_t* ticket);
+/* Queue `count` solves at once, all or none: they become visible to the
+ * worker together, so a burst of requests is admitted in the same tick
+ * instead of trickling in one call at a time.  ops[i], models[i] (models may
+ * be NULL, or an entry NULL, for no model), opts[i] (host array of count
+ * option structs), psi_out[i] as for rte_submit; tickets (host uint64 [count])
+ * receives the tickets in order.  Errors: as rte_submit, for the first
+ * request that fails validation; then no request is queued. */
+rte_status rte_submit_many(rte_server* srv, int count, const rte_operator* const* ops,
+                           const mgnet_model* const* models, const rte_solve_opts* opts, double* const* psi_out,
+                           uint64_t* tickets);
 /* RTE_EAGAIN while queued or running; once finished, fills *stats (host,
  * may be NULL), forgets the ticket and returns the solve's own status
  * (RTE_EINVAL when psi_out, x0 or b turned out not to be device memory).

@@ -77,6 +77,8 @@ _SIGS = {
     "rte_solve": [_P, _P, C.POINTER(SolveOpts), _P, C.c_size_t, _P, C.POINTER(SolveStats), _P],
     "rte_server_create": [_P, C.c_size_t, C.c_int, C.POINTER(_P)],
     "rte_submit": [_P, _P, _P, C.POINTER(SolveOpts), _P, C.POINTER(C.c_uint64)],
+    "rte_submit_many": [_P, C.c_int, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolveOpts), C.POINTER(_P),
+                        C.POINTER(C.c_uint64)],
     "rte_poll": [_P, C.c_uint64, C.POINTER(SolveStats)],
     "rte_server_query": [_P, C.POINTER(ServerStats)],
     "rte_server_destroy": [_P],

@@ -231,6 +231,22 @@ class Server:
         self._keep[t.value] = (op, model, psi, kw.get("x0"), kw.get("b"))
         return t.value
 
+    def submit_many(self, requests):
+        """Queue several solves at once (rte_submit_many): `requests` is a list of
+        (op, psi, model, kwargs) tuples; returns their tickets in order."""
+        n = len(requests)
+        if n == 0:
+            return []
+        ops = (C.c_void_p * n)(*[op.handle for op, _, _, _ in requests])
+        models = (C.c_void_p * n)(*[(m.handle if m else None) for _, _, m, _ in requests])
+        opts = (L.SolveOpts * n)(*[op.opts(**kw) for op, _, _, kw in requests])
+        outs = (C.c_void_p * n)(*[_dptr(psi) for _, psi, _, _ in requests])
+        tickets = (C.c_uint64 * n)()
+        check(lib().rte_submit_many(self._h, n, ops, models, opts, outs, tickets))
+        for (op, psi, m, kw), t in zip(requests, tickets):
+            self._keep[t] = (op, m, psi, kw.get("x0"), kw.get("b"))
+        return list(tickets)
+
     def poll(self, ticket):
         """None while running; (status, stats dict) once finished."""
         st = L.SolveStats()

@@ -257,32 +257,65 @@ rte_status rte_server_create(void* arena, size_t arena_bytes, int max_slots, rte
   });
 }
 
-rte_status rte_submit(rte_server* h, const rte_operator* op, const mgnet_model* model,
-                      const rte_solve_opts* opts, double* psi_out, uint64_t* ticket) {
-  return guarded2([&] {
-    RTE_REQUIRE(h && op && opts && psi_out && ticket, RTE_EINVAL, "rte_submit: null argument");
-    Server& s = *h->s;
-    const Model* m = model ? model->m.get() : nullptr;
-    validate_opts(*op->op, m, opts);
-    RTE_REQUIRE(opts->x0 == nullptr || opts->x0 != psi_out, RTE_EINVAL, "x0 must not alias psi_out");
-    std::unique_ptr<Request> r(new Request());
-    r->op = op->op.get();
-    r->m = m;
-    r->o = *opts;
-    r->x = psi_out;
-    const bool mg = opts->precond == RTE_PC_MGNET_BF16 || opts->precond == RTE_PC_MGNET_FP32;
-    r->need = Server::align(solve_layout(*r->op, m, opts->restart, mg).total);
-    RTE_REQUIRE(r->need + Server::align(batch_table_bytes(s.max_slots)) <= s.bytes, RTE_ENOMEM,
-                "request workspace exceeds the arena");
-    r->t_submit = now_ms();
-    std::lock_guard<std::mutex> lk(s.mu);
-    RTE_REQUIRE(!s.stopping, RTE_EINVAL, "server is shutting down");
-    RTE_REQUIRE(s.queue.size() < 4096, RTE_EAGAIN, "server queue is full");
+namespace {
+// A validated request, not yet queued.
+std::unique_ptr<Request> make_request(const Server& s, const rte_operator* op, const mgnet_model* model,
+                                      const rte_solve_opts* opts, double* psi_out) {
+  RTE_REQUIRE(op && opts && psi_out, RTE_EINVAL, "rte_submit: null argument");
+  const Model* m = model ? model->m.get() : nullptr;
+  validate_opts(*op->op, m, opts);
+  RTE_REQUIRE(opts->x0 == nullptr || opts->x0 != psi_out, RTE_EINVAL, "x0 must not alias psi_out");
+  std::unique_ptr<Request> r(new Request());
+  r->op = op->op.get();
+  r->m = m;
+  r->o = *opts;
+  r->x = psi_out;
+  const bool mg = opts->precond == RTE_PC_MGNET_BF16 || opts->precond == RTE_PC_MGNET_FP32;
+  r->need = Server::align(solve_layout(*r->op, m, opts->restart, mg).total);
+  RTE_REQUIRE(r->need + Server::align(batch_table_bytes(s.max_slots)) <= s.bytes, RTE_ENOMEM,
+              "request workspace exceeds the arena");
+  return r;
+}
+
+// Queues the requests under one lock, so the worker admits them together.
+void enqueue(Server& s, std::vector<std::unique_ptr<Request>>& rs, uint64_t* tickets) {
+  const double t = now_ms();
+  std::lock_guard<std::mutex> lk(s.mu);
+  RTE_REQUIRE(!s.stopping, RTE_EINVAL, "server is shutting down");
+  RTE_REQUIRE(s.queue.size() + rs.size() <= 4096, RTE_EAGAIN, "server queue is full");
+  for (size_t i = 0; i < rs.size(); ++i) {
+    std::unique_ptr<Request>& r = rs[i];
+    r->t_submit = t;
     r->ticket = s.next_ticket++;
-    *ticket = r->ticket;
+    tickets[i] = r->ticket;
     s.queue.push_back(r.get());
     s.tickets[r->ticket] = std::move(r);
     ++s.submitted;
+  }
+}
+}  // namespace
+
+rte_status rte_submit(rte_server* h, const rte_operator* op, const mgnet_model* model,
+                      const rte_solve_opts* opts, double* psi_out, uint64_t* ticket) {
+  return guarded2([&] {
+    RTE_REQUIRE(h && ticket, RTE_EINVAL, "rte_submit: null argument");
+    std::vector<std::unique_ptr<Request>> rs;
+    rs.push_back(make_request(*h->s, op, model, opts, psi_out));
+    enqueue(*h->s, rs, ticket);
+  });
+}
+
+rte_status rte_submit_many(rte_server* h, int count, const rte_operator* const* ops,
+                           const mgnet_model* const* models, const rte_solve_opts* opts, double* const* psi_out,
+                           uint64_t* tickets) {
+  return guarded2([&] {
+    RTE_REQUIRE(h && count >= 0 && (count == 0 || (ops && opts && psi_out && tickets)), RTE_EINVAL,
+                "rte_submit_many: null argument");
+    std::vector<std::unique_ptr<Request>> rs;
+    rs.reserve(size_t(count));
+    for (int i = 0; i < count; ++i)
+      rs.push_back(make_request(*h->s, ops[i], models ? models[i] : nullptr, opts + i, psi_out[i]));
+    enqueue(*h->s, rs, tickets);
   });
 }
 

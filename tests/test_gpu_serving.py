@@ -157,3 +157,29 @@ def test_staggered_joins_and_per_slot_restarts():
         assert (st["iterations"], st["restarts"]) == (sa["iterations"], sa["restarts"]), i
         assert bool((out == a).all()), "result %d differs between alone and in the mix" % i
     assert bool((outs[5] == 0).all())
+
+
+def test_submit_many_burst():
+    """A burst queued with one call is admitted together; results equal the
+    solves alone, and a burst with an invalid request queues nothing."""
+    torch = torch_cuda()
+    from paper_2604_23265_amd import _lib as L
+    from paper_2604_23265_amd import api
+    say("case serving submit_many")
+    reqs = [configs.c3_request(r, ndir_choices=(16,), grid_choices=(32,)) for r in range(200, 206)]
+    models, ops = _build(reqs)
+    kw = dict(restart=30, rtol=1e-8, precond="bf16")
+    alone = [op.solve(**kw)[0].clone() for op in ops]
+    srv = api.Server(arena_bytes=512 << 20, max_slots=8)
+    outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+    bad = [(ops[0], outs[0], ops[0].model, dict(kw, restart=0))] + [
+        (op, out, op.model, kw) for op, out in zip(ops[1:], outs[1:])]
+    with pytest.raises(L.RteError) as e:
+        srv.submit_many(bad)
+    assert e.value.code == L.RTE_EINVAL and srv.query()["submitted"] == 0
+    tickets = srv.submit_many([(op, out, op.model, kw) for op, out in zip(ops, outs)])
+    done = _wait(srv, tickets)
+    srv.close()
+    for t, a, out in zip(tickets, alone, outs):
+        assert done[t][0] == 0
+        assert bool((out == a).all())
