@@ -174,9 +174,9 @@ def main():
                     help="skip the Block-Jacobi and unpreconditioned batches")
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
     ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
-    ap.add_argument("--serving-requests", type=int, default=64, help="requests of the C3 stream (0 = skip)")
-    ap.add_argument("--serving-slots", type=int, default=8)
-    ap.add_argument("--serving-arena-gb", type=int, default=16)
+    ap.add_argument("--serving-requests", type=int, default=512, help="requests of the C3 stream (0 = skip)")
+    ap.add_argument("--serving-slots", type=int, default=16)
+    ap.add_argument("--serving-arena-gb", type=int, default=32)
     ap.add_argument("--serving-max-iters", type=int, default=3000)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device copy run before the solves (reference for counter scaling)")
