@@ -157,6 +157,70 @@ def serving_leg(args, api, torch, configs, weights):
                       "g ~ U[0,0.8], lognormal GRF sigma_T; BF16 MgNet FGMRES(30) to 1e-6"}
 
 
+def large_leg(args, api, L, torch, configs, weights):
+    """Kernel rates of the large single solves (the 512^2 x 64-direction and the 64^3 x
+    96-direction cases) with seeded weights: the FP32 operator apply, the BF16 V-cycle and
+    its convolutions, and the time per FGMRES iteration of a bounded solve."""
+    def ev_time(fn, reps):
+        for _ in range(3):
+            fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+
+    out = {}
+    cases = (("512x512_64dir", configs.c4, 30,
+              "2D 512x512, 64 directions, HG g=0.9, eps=1e-3, 8x8 checkerboard sigma_T {1,100}; "
+              "5-level MgNet, 64 channels"),
+             ("64x64x64_96dir", configs.c5, 20,
+              "3D 64^3, 96 sphere directions, HG g=0.8, eps=1e-2, lognormal GRF sigma_T; "
+              "4-level 3D MgNet, 48 channels"))
+    for name, make, k, desc in cases:
+        log("large: %s" % name)
+        prob = make()
+        hdr, t = configs.problem_weights(prob)
+        model = api.Model(weights.pack_mgn1(hdr, t))
+        op = api.Operator(prob, model=model)
+        torch.cuda.synchronize()
+        x = torch.randn(op.n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        dt_apply = ev_time(lambda: op.apply(x, y), 20)
+        apply_gbs = (8 * op.n + 8 * op.cells) / dt_apply / 1e9
+        v = torch.randn(op.n, dtype=torch.float64, device="cuda")
+        ws = torch.empty(op.precond_workspace(model), dtype=torch.uint8, device="cuda")
+        z = op.precond(model, v, mode="bf16", workspace=ws)
+        dt_mg = ev_time(lambda: op.precond(model, v, mode="bf16", z=z, workspace=ws), 5)
+        api.prof_reset()
+        api.prof_enable(L.K_CONV, 1)
+        for _ in range(3):
+            op.precond(model, v, mode="bf16", z=z, workspace=ws)
+        torch.cuda.synchronize()
+        api.prof_enable(L.K_CONV, 0)
+        ms, n, work, nb = api.prof_query(L.K_CONV)
+        api.prof_reset()
+        xs, st = op.solve(model=model, precond="bf16", rtol=1e-12, restart=k, max_iters=40)
+        out[name] = {
+            "workload": desc, "unknowns": int(op.n), "weights": "seeded (seed of the workload)",
+            "apply_fp32_us": dt_apply * 1e6, "apply_fp32_GBs": apply_gbs, "apply_frac_hbm": apply_gbs / HBM_PEAK_GBS,
+            "apply_bytes": "4 B in + 4 B out per unknown + 8 B per cell",
+            "vcycle_bf16_ms": dt_mg * 1e3,
+            "conv_launches_per_vcycle": n / 3, "conv_TFLOPs": work / (ms * 1e-3) / 1e12,
+            "conv_mfma_frac": work / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"],
+            "conv_GBs": nb / (ms * 1e-3) / 1e9, "conv_frac_hbm": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fgmres_restart": k, "fgmres_ms_per_iteration": st["ms_total"] / max(st["iterations"], 1),
+            "rel_residual_after_40": st["rel_residual"],
+        }
+        del op, model, x, y, v, ws, z, xs
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +238,7 @@ def main():
                     help="skip the Block-Jacobi and unpreconditioned batches")
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
     ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
+    ap.add_argument("--no-large", action="store_true", help="skip the large single-solve kernel rates")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests of the C3 stream (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=16)
     ap.add_argument("--serving-arena-gb", type=int, default=32)
@@ -373,6 +438,8 @@ def main():
     prob, blob = probs[0], blob
     if args.serving_requests:
         out["serving"] = serving_leg(args, api, torch, configs, weights)
+    if not args.no_large:
+        out["large_single_solves"] = large_leg(args, api, L, torch, configs, weights)
     if not args.no_cpu_baseline:
         log("cpu_baseline: oracle sample (~%.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(prob, blob, float(np.mean(its)), args.cpu_budget)
