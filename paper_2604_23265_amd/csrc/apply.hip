@@ -1,6 +1,10 @@
 // Discrete-ordinates operator apply (eq. (DORTE_2d), step-upwind finite
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
+// Two kernels: apply_slot_kernel (below) for the FP32 apply inside the
+// solve, one direction slot per wave; apply_kernel for the FP64 apply and
+// the FP64 residual, described here.
+//
 // Layout: x, y direction-major [N][cells].  A 256-thread block owns TL
 // consecutive cells (64, or 16 for more than 64 directions) and all N
 // directions.  The block stages x[:, tile] in LDS (rows of TL cells per
@@ -146,15 +150,15 @@ __device__ inline int xcd_tile(int x, int T) { return (T & 7) ? x : (x & 7) * (T
 // FP32 apply with one direction slot per wave (up to 128 directions): a
 // block takes TPB tiles of 64 consecutive cells in turn, lane = cell, wave
 // w = directions w, w + 4, ... (at most DPT of them).  The scatter's matrix
-// entries are then the same for the whole wave; with LS the block stages
-// the slot-packed S in LDS once, with one vector load per thread, and the
-// scatter reads it with broadcast LDS reads (scalar loads of S, one wait
-// per two directions, serialised the scatter), else they come from scalar
-// loads.  The per-
-// direction upwind signs and coefficients and the cell's sigma values are
-// requested before any address that uses them, so the upwind neighbours are
-// requested together; they are read at clamped addresses and zeroed outside
-// the grid.
+// entries are then the same for the whole wave.  With LS (up to 8
+// directions per wave) the block stages the slot-packed S in LDS once, one
+// vector load per thread, and the scatter reads it with broadcast LDS
+// reads: scalar loads of S had to be waited for every two directions and
+// serialised the scatter.  Beyond that S comes from scalar loads.  The
+// per-direction upwind signs and coefficients and the cell's sigma values
+// are requested before any address that uses them, so the upwind
+// neighbours are requested together; they are read at clamped addresses and
+// zeroed outside the grid.
 template <class TO, int DPT, bool D3, bool LS, int TPB>
 __global__ __launch_bounds__(256) void apply_slot_kernel(Slots sl, const float* __restrict__ x, TO* __restrict__ y,
                                                          const float* __restrict__ sT, const float* __restrict__ sA,
@@ -305,6 +309,7 @@ void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
       case 4: launch(apply_slot_kernel<TO, 4, D3, LS, TPB>); break;
       case 8: launch(apply_slot_kernel<TO, 8, D3, LS, TPB>); break;
       case 16: launch(apply_slot_kernel<TO, 16, D3, LS, TPB>); break;
+      case 24: launch(apply_slot_kernel<TO, 24, D3, LS, TPB>); break;
       default: launch(apply_slot_kernel<TO, 32, D3, LS, TPB>); break;
     }
   };

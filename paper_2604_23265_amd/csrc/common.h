@@ -207,7 +207,7 @@ constexpr int MAX_LEVELS = 8;
 // rounded up to a compile-time budget; 0 when N is beyond the largest.
 inline int slot_budget(int N) {
   const int need = (N + 3) / 4;
-  for (int b : {1, 2, 4, 8, 16, 32})
+  for (int b : {1, 2, 4, 8, 16, 24, 32})
     if (need <= b) return b;
   return 0;
 }

@@ -1343,6 +1343,7 @@ bool by_budget(int N, F&& f) {
     case 4: return f(std::integral_constant<int, 4>());
     case 8: return f(std::integral_constant<int, 8>());
     case 16: return f(std::integral_constant<int, 16>());
+    case 24: return f(std::integral_constant<int, 24>());
     case 32: return f(std::integral_constant<int, 32>());
     default: return false;
   }
