@@ -705,6 +705,235 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
     }
 }
 
+// Tiled 3D BF16 convolution: one block computes a 4x4x4 patch of the
+// virtual grid for 16 NI output channels; wave w owns z-layer w of the
+// patch (16 pixels, one MFMA row tile).  Per 32-channel input chunk the
+// block stages the patch's input footprint (6^3 pixels for the 3x3x3
+// convolution, 5^3 for one parity class of the 4x4x4 transposed one) and
+// the chunk's weights in the same swizzled 64-byte LDS rows as the 2D
+// kernel, the next chunk's loads in flight during the MFMAs.  Channel
+// counts only need to be multiples of 16: the channels of a partial last
+// chunk are staged as zeros in both operands.
+//
+// CK = 0: 3x3x3 stride 1; CK = 2: 4x4x4 stride-2 transposed, one parity
+// class per grid-z index (class = px + 2 py + 4 pz, tap = tx + 2 ty + 4 tz,
+// the order of the packed weights).  Accumulation runs chunk by chunk and
+// tap by tap, independent of the launch shape.
+template <int CK, int NI>
+struct Tile3Geom {
+  static constexpr int NTAP = CK == 2 ? 8 : 27;
+  static constexpr int FP = CK == 0 ? 6 : 5;
+  static constexpr int FPIX = FP * FP * FP;
+  static constexpr int NCLS = CK == 2 ? 8 : 1;
+  static constexpr int NCO = 16 * NI;
+  static constexpr int IN_PIECES = (FPIX * 8 + 255) / 256;
+  static constexpr int W_PIECES = (NTAP * NCO * 4 + 255) / 256;
+};
+
+template <int CK, int MODE, int NI>
+__global__ __launch_bounds__(256) void conv_tile3_kernel(const ConvArgs A0) {
+  using G = Tile3Geom<CK, NI>;
+  const int slot_z = int(blockIdx.z) / G::NCLS;
+  const int cls = int(blockIdx.z) - slot_z * G::NCLS;
+  SlotBase bs;
+  if (!slot_open(A0.sl, slot_z, bs)) return;
+  const float* __restrict__ in = at(A0.in, bs.ws);
+  float* __restrict__ out = at(A0.out, bs.ws);
+  float* __restrict__ out2 = at(A0.out2, bs.ws);
+  const float* __restrict__ fF = at(A0.f, bs.ws);
+  const float* __restrict__ fA = at(A0.a, bs.op);
+  const float* __restrict__ fI = at(A0.ainv, bs.op);
+  const uint16_t* __restrict__ W = static_cast<const uint16_t*>(A0.w);
+
+  __shared__ uint32_t xin[G::FPIX * TILE_ROW_WORDS];
+  __shared__ uint32_t wsm[G::NTAP * G::NCO * TILE_ROW_WORDS];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int grp = lane >> 4, li = lane & 15;
+  const int npx = A0.g_dim[0] >> 2, npy = A0.g_dim[1] >> 2;
+  const int patch = blockIdx.x;
+  const int pxi = patch % npx, pr_ = patch / npx;
+  const int px0 = 4 * pxi, py0 = 4 * (pr_ % npy), pz0 = 4 * (pr_ / npy);
+  const int co0 = blockIdx.y * G::NCO;
+  const int W0 = A0.in_dim[0], W1 = A0.in_dim[1], W2 = A0.in_dim[2];
+  const int cin = A0.cin, cout = A0.cout;
+  const int nchunk = (cin + 31) >> 5;
+  const int px_par = cls & 1, py_par = (cls >> 1) & 1, pz_par = (cls >> 2) & 1;
+  // input coordinates of footprint entry (0, 0, 0)
+  const int ox0 = CK == 2 ? px0 - 1 + px_par : px0 - 1;
+  const int oy0 = CK == 2 ? py0 - 1 + py_par : py0 - 1;
+  const int oz0 = CK == 2 ? pz0 - 1 + pz_par : pz0 - 1;
+
+  // ---- epilogue operands (independent of the reduction): request them now
+  const int ox_dim = A0.out_dim[0], oy_dim = A0.out_dim[1];
+  size_t oidx[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pr = 4 * grp + j;  // D row -> pixel (pr % 4, pr / 4) of z-layer `wave`
+    const int vx = px0 + (pr & 3), vy = py0 + (pr >> 2), vz = pz0 + wave;
+    const int ox = CK == 2 ? 2 * vx + px_par : vx;
+    const int oy = CK == 2 ? 2 * vy + py_par : vy;
+    const int oz = CK == 2 ? 2 * vz + pz_par : vz;
+    oidx[j] = (size_t(oz * oy_dim + oy) * ox_dim + ox) * cout + co0 + li;
+  }
+  constexpr bool NEED_F = MODE == CONV_RESID_R || MODE == CONV_RESID_T;
+  constexpr bool NEED_I = MODE == CONV_RESID_T || MODE == CONV_STORE_T;
+  constexpr bool NEED_U = MODE == CONV_ACCUM || NEED_F;
+  float ef[4 * NI], ea[4 * NI], ei[4 * NI], eu[4 * NI];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const int q = j * NI + ni;
+      const size_t o = oidx[j] + ni * 16;
+      if (NEED_F) {
+        ef[q] = fF[o];
+        ea[q] = fA[o];
+      }
+      if (NEED_I) ei[q] = fI[o];
+      if (NEED_U) eu[q] = MODE == CONV_ACCUM ? out[o] : in[o];
+    }
+
+  // ---- staging: chunk c's footprint and weights, loaded into registers;
+  // channels at or beyond cin are read at a valid address and zeroed
+  v4f rin[G::IN_PIECES];
+  v4u rw[G::W_PIECES];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < G::IN_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      const int pix = idx >> 3, q4 = idx & 7;
+      const int fx = pix % G::FP, fyz = pix / G::FP;
+      const int fy = fyz % G::FP, fz = fyz / G::FP;
+      const int ix = ox0 + fx, iy = oy0 + fy, iz = oz0 + fz;
+      const int ch = c * 32 + q4 * 4;
+      const bool ok = idx < G::FPIX * 8 && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1) &&
+                      unsigned(iz) < unsigned(W2) && ch < cin;
+      const int ixc = clampi(ix, 0, W0 - 1), iyc = clampi(iy, 0, W1 - 1), izc = clampi(iz, 0, W2 - 1);
+      const int chc = ch < cin ? ch : cin - 4;
+      const v4f v = *reinterpret_cast<const v4f*>(in + (size_t(izc * W1 + iyc) * W0 + ixc) * cin + chc);
+      rin[i] = ok ? v : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i = 0; i < G::W_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      constexpr int PER_TAP = G::NCO * 4;
+      const int idc = idx < G::NTAP * PER_TAP ? idx : G::NTAP * PER_TAP - 1;
+      const int t = idc / PER_TAP, rem = idc - (idc / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
+      const int ch = c * 32 + q8 * 8;
+      const v4u v = *reinterpret_cast<const v4u*>(W + (size_t((cls * G::NTAP + t) * cout + co0 + co)) * cin +
+                                                  (ch < cin ? ch : cin - 8));
+      rw[i] = ch < cin ? v : v4u{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < G::IN_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      if (idx < G::FPIX * 8) {
+        const int pix = idx >> 3, q4 = idx & 7;
+        const v4f v = rin[i];
+        const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
+        const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
+        *reinterpret_cast<uint2*>(xin + tile_word(pix, q4 >> 1) + 2 * (q4 & 1)) = make_uint2(lo, hi);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < G::W_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      constexpr int PER_TAP = G::NCO * 4;
+      if (idx < G::NTAP * PER_TAP) {
+        const int t = idx / PER_TAP, rem = idx - (idx / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
+        *reinterpret_cast<v4u*>(wsm + tile_word(t * G::NCO + co, q8)) = rw[i];
+      }
+    }
+  };
+
+  // this lane's A pixel: (li % 4, li / 4) of z-layer `wave`
+  const int lx = li & 3, ly = li >> 2, lz = wave;
+  v4f acc[NI];
+#pragma unroll
+  for (int ni = 0; ni < NI; ++ni) acc[ni] = v4f{0.f, 0.f, 0.f, 0.f};
+  load_chunk(0);
+  for (int c = 0; c < nchunk; ++c) {
+    if (c > 0) __syncthreads();  // the previous chunk's reads are done
+    store_chunk();
+    __syncthreads();
+    if (c + 1 < nchunk) load_chunk(c + 1);  // in flight during this chunk's MFMAs
+#pragma unroll
+    for (int t = 0; t < G::NTAP; ++t) {
+      // a 3x3x3 tap t reads (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1); transposed
+      // tap t of class (px, py, pz) reads (px - t % 2, py - t / 2 % 2, pz - t / 4)
+      const int dx = CK == 2 ? px_par - (t & 1) : t % 3 - 1;
+      const int dy = CK == 2 ? py_par - ((t >> 1) & 1) : (t / 3) % 3 - 1;
+      const int dz = CK == 2 ? pz_par - (t >> 2) : t / 9 - 1;
+      const int fx = px0 + lx + dx - ox0;
+      const int fy = py0 + ly + dy - oy0;
+      const int fz = pz0 + lz + dz - oz0;
+      const v8bf av = *reinterpret_cast<const v8bf*>(xin + tile_word((fz * G::FP + fy) * G::FP + fx, grp));
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni) {
+        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + tile_word(t * G::NCO + ni * 16 + li, grp));
+        acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) {
+      const int q = j * NI + ni;
+      const size_t o = oidx[j] + ni * 16;
+      const float v = acc[ni][j];
+      if constexpr (MODE == CONV_STORE) {
+        out[o] = v;
+      } else if constexpr (MODE == CONV_ACCUM) {
+        out[o] = eu[q] + v;
+      } else if constexpr (MODE == CONV_STORE_T) {
+        out[o] = v;
+        out2[o] = ei[q] * v;
+      } else if constexpr (MODE == CONV_RESID_R) {
+        out[o] = ef[q] - v - ea[q] * eu[q];
+      } else {
+        out[o] = ei[q] * (ef[q] - v - ea[q] * eu[q]);
+      }
+    }
+}
+
+template <int CK, int NI>
+void tile3_dispatch2(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, const ProfScope& ps) {
+  switch (mode) {
+    case CONV_STORE: launch_k(conv_tile3_kernel<CK, CONV_STORE, NI>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_ACCUM: launch_k(conv_tile3_kernel<CK, CONV_ACCUM, NI>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_STORE_T: launch_k(conv_tile3_kernel<CK, CONV_STORE_T, NI>, grid, dim3(256), 0, s, ps, a); break;
+    case CONV_RESID_R: launch_k(conv_tile3_kernel<CK, CONV_RESID_R, NI>, grid, dim3(256), 0, s, ps, a); break;
+    default: launch_k(conv_tile3_kernel<CK, CONV_RESID_T, NI>, grid, dim3(256), 0, s, ps, a); break;
+  }
+}
+
+// The 3x3x3 kernel stages 27 taps of weights per chunk, so it takes 16
+// output channels per block (41 KB of LDS); the transposed one stages 8 and
+// takes up to 64.
+template <int CK>
+void tile3_dispatch(const ConvArgs& a, int nz, int mode, hipStream_t s, const ProfScope& ps) {
+  const unsigned patches = unsigned((a.g_dim[0] / 4) * (a.g_dim[1] / 4) * (a.g_dim[2] / 4));
+  if constexpr (CK == 0) {
+    tile3_dispatch2<CK, 1>(a, dim3(patches, unsigned(a.cout / 16), unsigned(nz)), mode, s, ps);
+    return;
+  }
+  if (a.cout % 64 == 0) {
+    tile3_dispatch2<CK, 4>(a, dim3(patches, unsigned(a.cout / 64), unsigned(nz)), mode, s, ps);
+  } else if (a.cout % 48 == 0) {
+    tile3_dispatch2<CK, 3>(a, dim3(patches, unsigned(a.cout / 48), unsigned(nz)), mode, s, ps);
+  } else if (a.cout % 32 == 0) {
+    tile3_dispatch2<CK, 2>(a, dim3(patches, unsigned(a.cout / 32), unsigned(nz)), mode, s, ps);
+  } else {
+    tile3_dispatch2<CK, 1>(a, dim3(patches, unsigned(a.cout / 16), unsigned(nz)), mode, s, ps);
+  }
+}
+
 template <int CK, int NI>
 void tile_dispatch2(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, const ProfScope& ps) {
   switch (mode) {
@@ -1263,7 +1492,20 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
     else if (c.ostride == 1 && c.cstride == 2 && c.ntap == 9) ck = 1;
     else if (c.ostride == 2 && c.nclass == 4 && c.ntap == 4) ck = 2;
   }
-  if (ck >= 0) {
+  // The 3D tiled kernel: 3x3x3 stride-1 and 4x4x4 transposed BF16
+  // convolutions, channel counts multiples of 16 (launch_conv requires
+  // that), virtual grid a multiple of 4 per axis.
+  int ck3 = -1;
+  if (kind == MFMA_BF16 && c.dim == 3 && gxv % 4 == 0 && gyv % 4 == 0 && c.g_dim[2] % 4 == 0) {
+    if (c.ostride == 1 && c.cstride == 1 && c.ntap == 27) ck3 = 0;
+    else if (c.ostride == 2 && c.nclass == 8 && c.ntap == 8) ck3 = 2;
+  }
+  if (ck3 >= 0) {
+    a.w = c.w->d16;
+    const int nz = c.nclass * c.sl.count;
+    if (ck3 == 0) tile3_dispatch<0>(a, nz, c.mode, s, ps);
+    else tile3_dispatch<2>(a, nz, c.mode, s, ps);
+  } else if (ck >= 0) {
     a.w = c.w->d16;
     const int nz = c.nclass * c.sl.count;
     if (ck == 0) tile_dispatch<0>(a, gxv, gyv, nz, c.mode, s, ps);
