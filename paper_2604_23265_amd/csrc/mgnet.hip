@@ -707,13 +707,19 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
 
 // Tiled 3D BF16 convolution: one block computes a 4x4x4 patch of the
 // virtual grid for 16 NI output channels; wave w owns z-layer w of the
-// patch (16 pixels, one MFMA row tile).  Per 32-channel input chunk the
-// block stages the patch's input footprint (6^3 pixels for the 3x3x3
-// convolution, 5^3 for one parity class of the 4x4x4 transposed one) and
-// the chunk's weights in the same swizzled 64-byte LDS rows as the 2D
-// kernel, the next chunk's loads in flight during the MFMAs.  Channel
-// counts only need to be multiples of 16: the channels of a partial last
-// chunk are staged as zeros in both operands.
+// patch (16 pixels, one MFMA row tile) and all NI column tiles, so each
+// input fragment read from LDS feeds NI MFMAs.  Per 32-channel input chunk
+// the block stages the patch's input footprint (6^3 pixels for the 3x3x3
+// convolution, 5^3 for one parity class of the 4x4x4 transposed one) in the
+// same swizzled 64-byte LDS rows as the 2D kernel; the weights are staged
+// in rounds of TR taps (one kz-slice of the 3x3x3 kernel when the block has
+// more than 16 output channels, else all 27 taps; all 8 taps of the
+// transposed one), the next round's loads in flight during the current
+// round's MFMAs.  The epilogue operands are read after the reduction: held
+// through it, their 4 NI registers per operand cost more occupancy than
+// their latency costs once per block.  Channel counts only need to be multiples of 16: a last
+// chunk with 16 channels runs the K = 16 MFMA on the first half of each
+// row (the other half is staged as zeros and never read).
 //
 // CK = 0: 3x3x3 stride 1; CK = 2: 4x4x4 stride-2 transposed, one parity
 // class per grid-z index (class = px + 2 py + 4 pz, tap = tx + 2 ty + 4 tz,
@@ -722,12 +728,14 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
 template <int CK, int NI>
 struct Tile3Geom {
   static constexpr int NTAP = CK == 2 ? 8 : 27;
+  static constexpr int TR = CK == 2 ? 8 : (NI == 1 ? 27 : 9);  // taps per weight round
+  static constexpr int NR = NTAP / TR;
   static constexpr int FP = CK == 0 ? 6 : 5;
   static constexpr int FPIX = FP * FP * FP;
   static constexpr int NCLS = CK == 2 ? 8 : 1;
   static constexpr int NCO = 16 * NI;
   static constexpr int IN_PIECES = (FPIX * 8 + 255) / 256;
-  static constexpr int W_PIECES = (NTAP * NCO * 4 + 255) / 256;
+  static constexpr int W_PIECES = (TR * NCO * 4 + 255) / 256;
 };
 
 template <int CK, int MODE, int NI>
@@ -746,7 +754,7 @@ __global__ __launch_bounds__(256) void conv_tile3_kernel(const ConvArgs A0) {
   const uint16_t* __restrict__ W = static_cast<const uint16_t*>(A0.w);
 
   __shared__ uint32_t xin[G::FPIX * TILE_ROW_WORDS];
-  __shared__ uint32_t wsm[G::NTAP * G::NCO * TILE_ROW_WORDS];
+  __shared__ uint32_t wsm[G::TR * G::NCO * TILE_ROW_WORDS];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -765,7 +773,7 @@ __global__ __launch_bounds__(256) void conv_tile3_kernel(const ConvArgs A0) {
   const int oy0 = CK == 2 ? py0 - 1 + py_par : py0 - 1;
   const int oz0 = CK == 2 ? pz0 - 1 + pz_par : pz0 - 1;
 
-  // ---- epilogue operands (independent of the reduction): request them now
+  // ---- output (and epilogue operand) offsets of this lane's D rows
   const int ox_dim = A0.out_dim[0], oy_dim = A0.out_dim[1];
   size_t oidx[4];
 #pragma unroll
@@ -777,6 +785,122 @@ __global__ __launch_bounds__(256) void conv_tile3_kernel(const ConvArgs A0) {
     const int oz = CK == 2 ? 2 * vz + pz_par : vz;
     oidx[j] = (size_t(oz * oy_dim + oy) * ox_dim + ox) * cout + co0 + li;
   }
+  // ---- staging into registers: chunk c's footprint, and round r's weights
+  // (taps r TR .. r TR + TR - 1) of chunk c; channels at or beyond cin are
+  // read at a valid address and zeroed
+  v4f rin[G::IN_PIECES];
+  v4u rw[G::W_PIECES];
+  auto load_in = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < G::IN_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      const int pix = idx >> 3, q4 = idx & 7;
+      const int fx = pix % G::FP, fyz = pix / G::FP;
+      const int fy = fyz % G::FP, fz = fyz / G::FP;
+      const int ix = ox0 + fx, iy = oy0 + fy, iz = oz0 + fz;
+      const int ch = c * 32 + q4 * 4;
+      const bool ok = idx < G::FPIX * 8 && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1) &&
+                      unsigned(iz) < unsigned(W2) && ch < cin;
+      const int ixc = clampi(ix, 0, W0 - 1), iyc = clampi(iy, 0, W1 - 1), izc = clampi(iz, 0, W2 - 1);
+      const int chc = ch < cin ? ch : cin - 4;
+      const v4f v = *reinterpret_cast<const v4f*>(in + (size_t(izc * W1 + iyc) * W0 + ixc) * cin + chc);
+      rin[i] = ok ? v : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto load_w = [&](int c, int r) {
+#pragma unroll
+    for (int i = 0; i < G::W_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      constexpr int PER_TAP = G::NCO * 4;
+      const int idc = idx < G::TR * PER_TAP ? idx : G::TR * PER_TAP - 1;
+      const int t = idc / PER_TAP, rem = idc - (idc / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
+      const int ch = c * 32 + q8 * 8;
+      const v4u v = *reinterpret_cast<const v4u*>(
+          W + (size_t((cls * G::NTAP + r * G::TR + t) * cout + co0 + co)) * cin + (ch < cin ? ch : cin - 8));
+      rw[i] = ch < cin ? v : v4u{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store_in = [&]() {
+#pragma unroll
+    for (int i = 0; i < G::IN_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      if (idx < G::FPIX * 8) {
+        const int pix = idx >> 3, q4 = idx & 7;
+        const v4f v = rin[i];
+        const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
+        const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
+        *reinterpret_cast<uint2*>(xin + tile_word(pix, q4 >> 1) + 2 * (q4 & 1)) = make_uint2(lo, hi);
+      }
+    }
+  };
+  auto store_w = [&]() {
+#pragma unroll
+    for (int i = 0; i < G::W_PIECES; ++i) {
+      const int idx = int(threadIdx.x) + 256 * i;
+      constexpr int PER_TAP = G::NCO * 4;
+      if (idx < G::TR * PER_TAP) {
+        const int t = idx / PER_TAP, rem = idx - (idx / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
+        *reinterpret_cast<v4u*>(wsm + tile_word(t * G::NCO + co, q8)) = rw[i];
+      }
+    }
+  };
+
+  // this lane's A pixel: (li % 4, li / 4) of z-layer `wave`
+  const int lx = li & 3, ly = li >> 2, lz = wave;
+  // weight rows t NCO + 16 ni + li: NCO and 16 are multiples of 8, so the
+  // swizzle depends on li only and the row offset is a constant per (t, ni)
+  const int bfull = tile_word(li, grp), bhalf = tile_word(li, grp >> 1) + 2 * (grp & 1);
+  v4f acc[NI];
+#pragma unroll
+  for (int ni = 0; ni < NI; ++ni) acc[ni] = v4f{0.f, 0.f, 0.f, 0.f};
+  load_in(0);
+  load_w(0, 0);
+  for (int c = 0; c < nchunk; ++c) {
+    const bool half = cin - 32 * c == 16;  // uniform: a 16-channel last chunk
+    for (int r = 0; r < G::NR; ++r) {
+      if (c > 0 || r > 0) __syncthreads();  // the previous round's reads are done
+      if (r == 0) store_in();
+      store_w();
+      __syncthreads();
+      // the next round's loads, in flight during this round's MFMAs
+      if (r + 1 < G::NR) {
+        load_w(c, r + 1);
+      } else if (c + 1 < nchunk) {
+        load_in(c + 1);
+        load_w(c + 1, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < G::TR; ++t) {
+        // a 3x3x3 tap u = r TR + t reads (u % 3 - 1, u / 3 % 3 - 1, u / 9 - 1);
+        // transposed tap t of class (px, py, pz) reads (px - t % 2, py - t / 2 % 2, pz - t / 4)
+        const int u = r * G::TR + t;
+        const int dx = CK == 2 ? px_par - (t & 1) : t % 3 - 1;
+        const int dy = CK == 2 ? py_par - ((t >> 1) & 1) : (u / 3) % 3 - 1;
+        const int dz = CK == 2 ? pz_par - (t >> 2) : u / 9 - 1;
+        const int fx = px0 + lx + dx - ox0;
+        const int fy = py0 + ly + dy - oy0;
+        const int fz = pz0 + lz + dz - oz0;
+        const int arow = (fz * G::FP + fy) * G::FP + fx;
+        if (half) {
+          // K = 16: k-group grp holds channels 4 grp .. 4 grp + 3 of the chunk
+          const v4s av = *reinterpret_cast<const v4s*>(xin + tile_word(arow, grp >> 1) + 2 * (grp & 1));
+#pragma unroll
+          for (int ni = 0; ni < NI; ++ni) {
+            const v4s bv = *reinterpret_cast<const v4s*>(wsm + bhalf + (t * G::NCO + ni * 16) * TILE_ROW_WORDS);
+            acc[ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[ni], 0, 0, 0);
+          }
+        } else {
+          const v8bf av = *reinterpret_cast<const v8bf*>(xin + tile_word(arow, grp));
+#pragma unroll
+          for (int ni = 0; ni < NI; ++ni) {
+            const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + bfull + (t * G::NCO + ni * 16) * TILE_ROW_WORDS);
+            acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+
   constexpr bool NEED_F = MODE == CONV_RESID_R || MODE == CONV_RESID_T;
   constexpr bool NEED_I = MODE == CONV_RESID_T || MODE == CONV_STORE_T;
   constexpr bool NEED_U = MODE == CONV_ACCUM || NEED_F;
@@ -794,91 +918,6 @@ __global__ __launch_bounds__(256) void conv_tile3_kernel(const ConvArgs A0) {
       if (NEED_I) ei[q] = fI[o];
       if (NEED_U) eu[q] = MODE == CONV_ACCUM ? out[o] : in[o];
     }
-
-  // ---- staging: chunk c's footprint and weights, loaded into registers;
-  // channels at or beyond cin are read at a valid address and zeroed
-  v4f rin[G::IN_PIECES];
-  v4u rw[G::W_PIECES];
-  auto load_chunk = [&](int c) {
-#pragma unroll
-    for (int i = 0; i < G::IN_PIECES; ++i) {
-      const int idx = int(threadIdx.x) + 256 * i;
-      const int pix = idx >> 3, q4 = idx & 7;
-      const int fx = pix % G::FP, fyz = pix / G::FP;
-      const int fy = fyz % G::FP, fz = fyz / G::FP;
-      const int ix = ox0 + fx, iy = oy0 + fy, iz = oz0 + fz;
-      const int ch = c * 32 + q4 * 4;
-      const bool ok = idx < G::FPIX * 8 && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1) &&
-                      unsigned(iz) < unsigned(W2) && ch < cin;
-      const int ixc = clampi(ix, 0, W0 - 1), iyc = clampi(iy, 0, W1 - 1), izc = clampi(iz, 0, W2 - 1);
-      const int chc = ch < cin ? ch : cin - 4;
-      const v4f v = *reinterpret_cast<const v4f*>(in + (size_t(izc * W1 + iyc) * W0 + ixc) * cin + chc);
-      rin[i] = ok ? v : v4f{0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int i = 0; i < G::W_PIECES; ++i) {
-      const int idx = int(threadIdx.x) + 256 * i;
-      constexpr int PER_TAP = G::NCO * 4;
-      const int idc = idx < G::NTAP * PER_TAP ? idx : G::NTAP * PER_TAP - 1;
-      const int t = idc / PER_TAP, rem = idc - (idc / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
-      const int ch = c * 32 + q8 * 8;
-      const v4u v = *reinterpret_cast<const v4u*>(W + (size_t((cls * G::NTAP + t) * cout + co0 + co)) * cin +
-                                                  (ch < cin ? ch : cin - 8));
-      rw[i] = ch < cin ? v : v4u{0u, 0u, 0u, 0u};
-    }
-  };
-  auto store_chunk = [&]() {
-#pragma unroll
-    for (int i = 0; i < G::IN_PIECES; ++i) {
-      const int idx = int(threadIdx.x) + 256 * i;
-      if (idx < G::FPIX * 8) {
-        const int pix = idx >> 3, q4 = idx & 7;
-        const v4f v = rin[i];
-        const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
-        const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
-        *reinterpret_cast<uint2*>(xin + tile_word(pix, q4 >> 1) + 2 * (q4 & 1)) = make_uint2(lo, hi);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < G::W_PIECES; ++i) {
-      const int idx = int(threadIdx.x) + 256 * i;
-      constexpr int PER_TAP = G::NCO * 4;
-      if (idx < G::NTAP * PER_TAP) {
-        const int t = idx / PER_TAP, rem = idx - (idx / PER_TAP) * PER_TAP, co = rem >> 2, q8 = rem & 3;
-        *reinterpret_cast<v4u*>(wsm + tile_word(t * G::NCO + co, q8)) = rw[i];
-      }
-    }
-  };
-
-  // this lane's A pixel: (li % 4, li / 4) of z-layer `wave`
-  const int lx = li & 3, ly = li >> 2, lz = wave;
-  v4f acc[NI];
-#pragma unroll
-  for (int ni = 0; ni < NI; ++ni) acc[ni] = v4f{0.f, 0.f, 0.f, 0.f};
-  load_chunk(0);
-  for (int c = 0; c < nchunk; ++c) {
-    if (c > 0) __syncthreads();  // the previous chunk's reads are done
-    store_chunk();
-    __syncthreads();
-    if (c + 1 < nchunk) load_chunk(c + 1);  // in flight during this chunk's MFMAs
-#pragma unroll
-    for (int t = 0; t < G::NTAP; ++t) {
-      // a 3x3x3 tap t reads (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1); transposed
-      // tap t of class (px, py, pz) reads (px - t % 2, py - t / 2 % 2, pz - t / 4)
-      const int dx = CK == 2 ? px_par - (t & 1) : t % 3 - 1;
-      const int dy = CK == 2 ? py_par - ((t >> 1) & 1) : (t / 3) % 3 - 1;
-      const int dz = CK == 2 ? pz_par - (t >> 2) : t / 9 - 1;
-      const int fx = px0 + lx + dx - ox0;
-      const int fy = py0 + ly + dy - oy0;
-      const int fz = pz0 + lz + dz - oz0;
-      const v8bf av = *reinterpret_cast<const v8bf*>(xin + tile_word((fz * G::FP + fy) * G::FP + fx, grp));
-#pragma unroll
-      for (int ni = 0; ni < NI; ++ni) {
-        const v8bf bv = *reinterpret_cast<const v8bf*>(wsm + tile_word(t * G::NCO + ni * 16 + li, grp));
-        acc[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ni], 0, 0, 0);
-      }
-    }
-  }
 
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -913,24 +952,23 @@ void tile3_dispatch2(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, cons
   }
 }
 
-// The 3x3x3 kernel stages 27 taps of weights per chunk, so it takes 16
-// output channels per block (41 KB of LDS); the transposed one stages 8 and
-// takes up to 64.
+// Output channels per block: the widest of 64 / 48 / 32 / 16 that divides
+// cout and still gives at least 1024 blocks (4 per CU), else 16.
 template <int CK>
 void tile3_dispatch(const ConvArgs& a, int nz, int mode, hipStream_t s, const ProfScope& ps) {
-  const unsigned patches = unsigned((a.g_dim[0] / 4) * (a.g_dim[1] / 4) * (a.g_dim[2] / 4));
-  if constexpr (CK == 0) {
-    tile3_dispatch2<CK, 1>(a, dim3(patches, unsigned(a.cout / 16), unsigned(nz)), mode, s, ps);
-    return;
-  }
-  if (a.cout % 64 == 0) {
-    tile3_dispatch2<CK, 4>(a, dim3(patches, unsigned(a.cout / 64), unsigned(nz)), mode, s, ps);
-  } else if (a.cout % 48 == 0) {
-    tile3_dispatch2<CK, 3>(a, dim3(patches, unsigned(a.cout / 48), unsigned(nz)), mode, s, ps);
-  } else if (a.cout % 32 == 0) {
-    tile3_dispatch2<CK, 2>(a, dim3(patches, unsigned(a.cout / 32), unsigned(nz)), mode, s, ps);
-  } else {
-    tile3_dispatch2<CK, 1>(a, dim3(patches, unsigned(a.cout / 16), unsigned(nz)), mode, s, ps);
+  const int64_t patches = int64_t(a.g_dim[0] / 4) * (a.g_dim[1] / 4) * (a.g_dim[2] / 4);
+  int ni = 1;
+  for (int cand : {4, 3, 2})
+    if (a.cout % (16 * cand) == 0 && patches * (a.cout / (16 * cand)) * nz >= 1024) {
+      ni = cand;
+      break;
+    }
+  const dim3 grid(unsigned(patches), unsigned(a.cout / (16 * ni)), unsigned(nz));
+  switch (ni) {
+    case 4: tile3_dispatch2<CK, 4>(a, grid, mode, s, ps); break;
+    case 3: tile3_dispatch2<CK, 3>(a, grid, mode, s, ps); break;
+    case 2: tile3_dispatch2<CK, 2>(a, grid, mode, s, ps); break;
+    default: tile3_dispatch2<CK, 1>(a, grid, mode, s, ps); break;
   }
 }
 
