@@ -14,6 +14,8 @@
 // come from global memory (the same or an adjacent row, cached) and are
 // requested before the scatter loop so their latency overlaps it.
 // Collision uses the cancellation-free form sT (x - Sx) + sA Sx.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rte {
@@ -320,6 +322,207 @@ void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   RTE_HIP(hipGetLastError());
 }
 
+// FP32 apply with the scatter on the matrix cores, for N a multiple of 16
+// and whole 64-cell tiles: the block has N / 16 waves and wave w owns
+// directions 16 w .. 16 w + 15 of each tile.  The scatter (S x)^T for them
+// is a [16 x N] x [N x 16] product per 16 cells, run with the 16x16x4
+// FP32 MFMA: the A operand, the wave's rows of S, stays in N / 4
+// registers per lane; the B operand is the tile of x in LDS.  The D layout
+// (direction 4 (l / 16) + r, cell l % 16) gives each group of 16 lanes 16
+// consecutive cells of one direction, so the streaming part reads and
+// writes coalesced rows.
+//
+// A block walks several tiles (the XCD running it takes a contiguous
+// range), requests the next tile's x into registers before the current
+// tile's MFMAs and stores, and loads S and the per-direction data once.
+// Measured at 512^2 x 64 directions: the HBM bytes (counters) equal the
+// algorithmic ones, yet the kernel reaches about a third of the HBM rate
+// and a quarter of the FP32 matrix rate; what bounds it is not settled.
+template <class TO, bool D3, int NN>
+__global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const float* __restrict__ x,
+                                                            TO* __restrict__ y, const float* __restrict__ sT,
+                                                            const float* __restrict__ sA,
+                                                            const float* __restrict__ S,
+                                                            const float* __restrict__ dc,
+                                                            const int* __restrict__ sg, int nx, int ny, int nz,
+                                                            int cells) {
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  x = at(x, bs.ws + bs.dx);
+  y = at(y, bs.ws + bs.dy);
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  S = at(S, bs.op);
+  dc = at(dc, bs.op);
+  sg = at(sg, bs.op);
+  constexpr int KS = NN / 4;        // k-steps of the MFMA
+  constexpr int NT = NN * 4;        // threads: NN / 16 waves
+  constexpr int XP = NN * 16 / NT;  // float4 pieces of a tile per thread (4)
+  constexpr int NA = D3 ? 3 : 2;
+  __shared__ float xs[NN * 64];  // [N][64] x tile
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int li = lane & 15, grp = lane >> 4;
+  // tiles of this block: with 8 | ntile and 8 | gridDim.x, block b runs on
+  // XCD b % 8, which takes tiles [k ntile / 8, (k + 1) ntile / 8)
+  const int ntile = cells / 64;
+  const int G = int(gridDim.x);
+  int t0, tstep, tend;
+  if ((ntile & 7) == 0 && (G & 7) == 0) {
+    const int k = int(blockIdx.x) & 7;
+    t0 = k * (ntile >> 3) + (int(blockIdx.x) >> 3);
+    tstep = G >> 3;
+    tend = (k + 1) * (ntile >> 3);
+  } else {
+    t0 = int(blockIdx.x);
+    tstep = G;
+    tend = ntile;
+  }
+  if (t0 >= tend) return;
+
+  // the wave's rows of S: lane l holds S[16 w + l % 16][4 s + l / 16]
+  float sa_reg[KS];
+  const float* __restrict__ srow = S + (16 * wave + li) * NN + grp;
+#pragma unroll
+  for (int k = 0; k < KS; ++k) sa_reg[k] = srow[4 * k];
+  // this lane's output directions m_r = 16 w + 4 (l / 16) + r
+  float dcv[4][NA];
+  int sgv[4][NA];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int m = 16 * wave + 4 * grp + r;
+      dcv[r][a] = dc[4 * m + a];
+      sgv[r][a] = sg[4 * m + a];
+    }
+  const int ext[3] = {nx, ny, nz};
+  const int stride[3] = {1, nx, nx * ny};
+  // per output direction: its row of x and y, and its neighbour offsets
+  int64_t rowb[4];
+  int offn[4][NA];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    rowb[r] = int64_t(16 * wave + 4 * grp + r) * cells;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) offn[r][a] = sgv[r][a] * stride[a];
+  }
+  const bool row_tiles = (nx & 63) == 0;
+
+  v4f rx[XP];
+  auto load_x = [&](int tile) {
+#pragma unroll
+    for (int i = 0; i < XP; ++i) {
+      const int idx = int(threadIdx.x) + NT * i;
+      const int m = idx >> 4, q = idx & 15;
+      rx[i] = *reinterpret_cast<const v4f*>(x + int64_t(m) * cells + tile * 64 + 4 * q);
+    }
+  };
+  load_x(t0);
+  for (int tile = t0; tile < tend; tile += tstep) {
+    const int c0 = tile * 64;
+    if (tile != t0) __syncthreads();  // the previous tile's reads of xs are done
+#pragma unroll
+    for (int i = 0; i < XP; ++i) {
+      const int idx = int(threadIdx.x) + NT * i;
+      *reinterpret_cast<v4f*>(xs + (idx >> 4) * 64 + 4 * (idx & 15)) = rx[i];
+    }
+    // cell data and upwind neighbours of the lane's 4 cells (one per
+    // 16-cell sub-tile) in its 4 directions; out-of-grid neighbours are
+    // zero.  When 64 divides nx the tile lies in one grid row, so its row
+    // and layer indices are uniform (no per-lane division).
+    float st[4], sav[4], xnb[4][4][NA];
+    int ti0 = 0, tj = 0, tk = 0;
+    if (row_tiles) {
+      const int rr = c0 / nx;
+      ti0 = c0 - rr * nx;
+      tj = rr % ny;
+      tk = rr / ny;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + 16 * u + li;
+      st[u] = sT[c];
+      sav[u] = sA[c];
+      int pos[3];
+      if (row_tiles) {
+        pos[0] = ti0 + 16 * u + li;
+        pos[1] = tj;
+        pos[2] = tk;
+      } else {
+        const int rr = c / nx;
+        pos[0] = c - rr * nx;
+        pos[1] = rr % ny;
+        pos[2] = rr / ny;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t o = rowb[r] + c;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const int p = pos[a] - sgv[r][a];
+          const bool inb = unsigned(p) < unsigned(ext[a]);
+          const float v = x[inb ? o - offn[r][a] : o];
+          xnb[u][r][a] = inb ? v : 0.f;
+        }
+      }
+    }
+    if (tile + tstep < tend) load_x(tile + tstep);  // in flight during this tile's work
+    __syncthreads();
+    // (S x)^T for the wave's 16 directions and the tile's 4 x 16 cells
+    v4f acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < KS; ++k)
+        acc[u] =
+            __builtin_amdgcn_mfma_f32_16x16x4f32(sa_reg[k], xs[(4 * k + grp) * 64 + 16 * u + li], acc[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + 16 * u + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 16 * wave + 4 * grp + r;
+        const float xc = xs[m * 64 + 16 * u + li];
+        float str = 0.f;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) str += dcv[r][a] * (xc - xnb[u][r][a]);
+        const float sx = acc[u][r];
+        y[rowb[r] + c] = TO(str + st[u] * (xc - sx) + sav[u] * sx);
+      }
+    }
+  }
+}
+
+template <class TO, bool D3>
+bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const ProfScope& ps) {
+  const Operator& op = *Tg.op;
+  const OpArrays& A = Tg.arr;
+  if (op.cells % 64 != 0) return false;
+  // about 2048 blocks over all solves of the launch, at least one tile each;
+  // a multiple of 8 when the tile count is (the XCD-contiguous order).
+  // Measured at 64 and 96 directions: 1024 blocks, or the next tile's
+  // loads issued before the upwind neighbours', were no faster.
+  const int64_t ntile = op.cells / 64;
+  int64_t g = std::max<int64_t>(1, 2048 / std::max(1, Tg.sl.count));
+  if (ntile % 8 == 0) g = std::max<int64_t>(8, g & ~int64_t(7));
+  g = std::min(g, ntile);
+  const dim3 grid(unsigned(g), 1, unsigned(Tg.sl.count));
+  auto launch = [&](auto kern, int nn) {
+    launch_k(kern, grid, dim3(unsigned(4 * nn)), 0u, s, ps, Tg.sl, static_cast<const float*>(x),
+             static_cast<TO*>(y), A.sT32, A.sA32, A.S32, A.dc32, static_cast<const int*>(A.dsgn), op.nx, op.ny,
+             op.nz, int(op.cells));
+  };
+  switch (op.ndir) {
+    case 32: launch(apply_mfma_kernel<TO, D3, 32>, 32); return true;
+    case 64: launch(apply_mfma_kernel<TO, D3, 64>, 64); return true;
+    case 96: launch(apply_mfma_kernel<TO, D3, 96>, 96); return true;
+    default: return false;
+  }
+}
+
 template <class T, class TI, class TO, bool RES, bool LDS_S, int TL>
 void go_dpt(const Target& Tg, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
             const T* dc, size_t lds, hipStream_t s, const ProfScope& ps) {
@@ -397,6 +600,11 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
   if (fp64) {
     RTE_REQUIRE(tin == 1 && tout == 1, RTE_EINVAL, "FP64 apply takes FP64 vectors");
     go<double, double, double, false>(Tg, x, y, nullptr, s, ps);
+  } else if (tin == 0 && (op.nz > 1 ? (tout == 0 ? go_mfma<float, true>(Tg, x, y, s, ps)
+                                                  : go_mfma<double, true>(Tg, x, y, s, ps))
+                                     : (tout == 0 ? go_mfma<float, false>(Tg, x, y, s, ps)
+                                                  : go_mfma<double, false>(Tg, x, y, s, ps)))) {
+    // the matrix-core scatter (N of 32, 64 or 96, whole 64-cell tiles)
   } else if (tin == 0 && Tg.arr.Sp32 && slot_budget(op.ndir) > 0) {
     const bool d3 = op.nz > 1;
     if (tout == 0)

@@ -202,6 +202,43 @@ def test_solve_matches_reference(name, mode):
     assert rel(host(x), ref) < tol
 
 
+# Direction counts of 32, 64 and 96 on whole 64-cell tiles take the
+# matrix-core scatter (2D and 3D); a 12 x 12 grid (144 cells, a ragged last
+# tile) with 32 directions takes the vector scatter.
+MC_CASES = {
+    "2d_n32": lambda: problems.make(n=8, ndir=32, g=0.7, eps=0.05, inflow="random", seed=11),
+    "2d_n64": lambda: problems.make(n=8, ndir=64, g=0.9, eps=0.1, inflow="random", seed=12),
+    "3d_n32": lambda: problems.make(dim=3, n=4, ndir=32, g=0.6, eps=0.3, kind="sphere", inflow="random", seed=13),
+    "3d_n96": lambda: problems.make(dim=3, n=4, ndir=96, g=0.8, eps=0.2, kind="sphere", inflow="random", seed=14),
+    "2d_n32_ragged": lambda: problems.make(n=12, ndir=32, g=0.5, eps=0.2, inflow="random", seed=15),
+}
+
+
+@pytest.mark.parametrize("name", list(MC_CASES))
+def test_apply_and_solve_at_scatter_shapes(name):
+    """FP32 apply against the oracle (1e-6), and a BF16-preconditioned solve (whose Arnoldi
+    steps apply L to FP32 vectors into FP64 ones) against dense LU (1e-5)."""
+    say("case", name)
+    torch_cuda()
+    from paper_2604_23265_amd import api
+    prob = MC_CASES[name]()
+    model, blob = model_for(prob)
+    op = api.Operator(prob, model=model)
+    P = osolve.Problem(prob, blob)
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(P.D.n).astype(np.float32)
+    y = host(op.apply(dev(x, "float32"))).astype(np.float64)
+    err = rel(y, P.apply(x.astype(np.float64)))
+    say("  apply fp32 rel err", err)
+    assert err < 1e-6
+    ref = reference_solution(P)
+    xs, st = op.solve(model=model, precond="bf16", rtol=1e-10, restart=30, max_iters=20000)
+    say("  stats", st)
+    assert st["converged"] == 1
+    assert osolve.relative_residual(P, host(xs)) <= 1.5e-10
+    assert rel(host(xs), ref) < 1e-5
+
+
 def test_solve_is_deterministic():
     say("case determinism c2_small bf16")
     prob, model, op, P = setup_case("c2_small")
