@@ -515,8 +515,9 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
              static_cast<TO*>(y), A.sT32, A.sA32, A.S32, A.dc32, static_cast<const int*>(A.dsgn), op.nx, op.ny,
              op.nz, int(op.cells));
   };
+  // 64 and 96 directions: at 32 the vector kernel is as fast per launch
+  // and faster in the serving stream's small batches (measured)
   switch (op.ndir) {
-    case 32: launch(apply_mfma_kernel<TO, D3, 32>, 32); return true;
     case 64: launch(apply_mfma_kernel<TO, D3, 64>, 64); return true;
     case 96: launch(apply_mfma_kernel<TO, D3, 96>, 96); return true;
     default: return false;
@@ -604,7 +605,7 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
                                                   : go_mfma<double, true>(Tg, x, y, s, ps))
                                      : (tout == 0 ? go_mfma<float, false>(Tg, x, y, s, ps)
                                                   : go_mfma<double, false>(Tg, x, y, s, ps)))) {
-    // the matrix-core scatter (N of 32, 64 or 96, whole 64-cell tiles)
+    // the matrix-core scatter (N of 64 or 96, whole 64-cell tiles)
   } else if (tin == 0 && Tg.arr.Sp32 && slot_budget(op.ndir) > 0) {
     const bool d3 = op.nz > 1;
     if (tout == 0)

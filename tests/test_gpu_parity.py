@@ -202,9 +202,9 @@ def test_solve_matches_reference(name, mode):
     assert rel(host(x), ref) < tol
 
 
-# Direction counts of 32, 64 and 96 on whole 64-cell tiles take the
-# matrix-core scatter (2D and 3D); a 12 x 12 grid (144 cells, a ragged last
-# tile) with 32 directions takes the vector scatter.
+# Direction counts of 64 and 96 on whole 64-cell tiles take the matrix-core
+# scatter (2D and 3D); 32 directions, and a 12 x 12 grid (144 cells, a
+# ragged last tile), take the vector scatter.
 MC_CASES = {
     "2d_n32": lambda: problems.make(n=8, ndir=32, g=0.7, eps=0.05, inflow="random", seed=11),
     "2d_n64": lambda: problems.make(n=8, ndir=64, g=0.9, eps=0.1, inflow="random", seed=12),
