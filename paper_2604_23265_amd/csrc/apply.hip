@@ -470,15 +470,17 @@ __global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const floa
     if (tile + tstep < tend) load_x(tile + tstep);  // in flight during this tile's work
     __syncthreads();
     // (S x)^T for the wave's 16 directions and the tile's 4 x 16 cells
+    // k outermost: the four sub-tiles' accumulators are independent, so
+    // consecutive MFMAs do not wait on each other's results
     v4f acc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int k = 0; k < KS; ++k)
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
         acc[u] =
             __builtin_amdgcn_mfma_f32_16x16x4f32(sa_reg[k], xs[(4 * k + grp) * 64 + 16 * u + li], acc[u], 0, 0, 0);
-    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = c0 + 16 * u + li;
