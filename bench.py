@@ -56,6 +56,29 @@ def measured_traffic():
         return None, None
 
 
+APPLY_SOURCE = os.path.join(ROOT, "paper_2604_23265_amd", "csrc", "apply.hip")
+APPLY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_mfma_kernel_c4_c5.md")
+
+
+def measured_apply_traffic():
+    """{case name: HBM bytes per FP32 apply launch} from the committed counter
+    summary of the large cases, or {} when the apply source has changed since."""
+    import hashlib
+    try:
+        src = hashlib.sha256(open(APPLY_SOURCE, "rb").read()).hexdigest()
+        fields = {}
+        for line in open(APPLY_TRAFFIC_FILE):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("source-sha256") != src:
+            return {}
+        pre = "hbm-bytes-per-launch-"
+        return {k[len(pre):]: float(v) for k, v in fields.items() if k.startswith(pre)}
+    except (OSError, ValueError):
+        return {}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -216,6 +239,13 @@ def large_leg(args, api, L, torch, configs, weights):
             "fgmres_restart": k, "fgmres_ms_per_iteration": st["ms_total"] / max(st["iterations"], 1),
             "rel_residual_after_40": st["rel_residual"],
         }
+        hbm = measured_apply_traffic().get(name)
+        if hbm is not None:
+            # the same launch's HBM bytes from the committed counter summary
+            alg = 8.0 * op.n + 8.0 * op.cells
+            out[name]["apply_hbm_bytes_counters"] = hbm
+            out[name]["apply_hbm_GBs_counters"] = hbm / dt_apply / 1e9
+            out[name]["apply_traffic_over_algorithmic"] = hbm / alg
         del op, model, x, y, v, ws, z, xs
         torch.cuda.empty_cache()
     return out
