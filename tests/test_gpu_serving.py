@@ -71,6 +71,50 @@ def test_results_alone_equal_results_in_the_mix():
     assert osolve.relative_residual(P, host(outs[0])) <= 1e-8 * 1.01
 
 
+def _shape_requests():
+    import problems
+    reqs = []
+    for s in range(3):  # 3D, 32 directions, 48-channel MgNet: the tiled 3D convolutions
+        reqs.append(problems.make(dim=3, n=8, ndir=32, g=0.6, eps=0.2, kind="sphere", inflow="random",
+                                  seed=40 + s, mg=dict(c0=48, levels=2, nu_pre=2, nu_post=2, nu_coarse=2,
+                                                       coef_ch=3, seed=7)))
+    for s in range(3):  # 2D, 64 directions: the matrix-core apply
+        reqs.append(problems.make(n=16, ndir=64, g=0.8, eps=0.1, inflow="random", seed=50 + s,
+                                  mg=dict(c0=32, levels=2, nu_pre=2, nu_post=2, nu_coarse=2, coef_ch=3, seed=8)))
+    for s in range(2):  # 3D, 96 directions: both
+        reqs.append(problems.make(dim=3, n=4, ndir=96, g=0.8, eps=0.3, kind="sphere", inflow="random",
+                                  seed=60 + s, mg=dict(c0=96, levels=2, nu_pre=2, nu_post=2, nu_coarse=2,
+                                                       coef_ch=3, seed=9)))
+    return reqs
+
+
+def test_results_alone_equal_results_in_the_mix_3d_and_wide_angle_shapes():
+    """Batches of 3D and 64/96-direction solves (every launch covering 2 or 3 solves) give
+    each solve the same bits as alone."""
+    torch = torch_cuda()
+    from paper_2604_23265_amd import api
+    say("case serving mix of 3D and wide-angle shapes")
+    reqs = _shape_requests()
+    models, ops = _build(reqs)
+    kw = dict(restart=30, rtol=1e-8, precond="bf16", max_iters=3000)
+    alone = []
+    for op in ops:
+        x, st = op.solve(**kw)
+        assert st["converged"] == 1, st
+        alone.append(x.clone())
+    srv = api.Server(arena_bytes=512 << 20, max_slots=4)
+    outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+    tickets = [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops, outs)]
+    done = _wait(srv, tickets)
+    srv.close()
+    for t, a, out in zip(tickets, alone, outs):
+        code, st = done[t]
+        assert code == 0 and st["converged"] == 1
+        assert bool((out == a).all()), "result differs between alone and in the mix"
+    for i in (0, 3, 6):
+        assert osolve.relative_residual(osolve.Problem(reqs[i]), host(outs[i])) <= 1e-8 * 1.01
+
+
 def test_admission_by_footprint():
     torch = torch_cuda()
     from paper_2604_23265_amd import api
