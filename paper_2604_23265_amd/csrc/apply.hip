@@ -1,9 +1,10 @@
 // Discrete-ordinates operator apply (eq. (DORTE_2d), step-upwind finite
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
-// Two kernels: apply_slot_kernel (below) for the FP32 apply inside the
-// solve, one direction slot per wave; apply_kernel for the FP64 apply and
-// the FP64 residual, described here.
+// Three kernels: apply_mfma_kernel (below) for the FP32 apply with 64 or
+// 96 directions, the scatter on the FP32 matrix cores; apply_slot_kernel
+// (below) for the other FP32 applies, one direction slot per wave; and
+// apply_kernel for the FP64 apply and the FP64 residual, described here.
 //
 // Layout: x, y direction-major [N][cells].  A 256-thread block owns TL
 // consecutive cells (64, or 16 for more than 64 directions) and all N

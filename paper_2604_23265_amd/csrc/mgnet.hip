@@ -4,7 +4,10 @@
 // Every convolution is an implicit GEMM: rows are the pixels of a "virtual
 // grid" (the output grid, or one parity class of it for the transposed
 // convolution), columns are output channels, and the reduction runs over
-// taps x input channels.  Each wave computes a 16-row x (16 NT)-column
+// taps x input channels.  The BF16 convolutions of the MgNet shapes run in
+// the LDS-tiled kernels further down (conv_tile_kernel in 2D,
+// conv_tile3_kernel in 3D); the generic kernel described here takes the
+// FP32 path and the remaining shapes.  Each wave computes a 16-row x (16 NT)-column
 // tile; a 256-thread block holds four such waves, either on four row groups
 // or, when the launch would otherwise leave the chip underfilled (coarse
 // levels), on one row group with the k-steps split four ways.  Operands are
