@@ -214,9 +214,34 @@ def coeffnet(net, D):
     return a, ainv
 
 
-def vcycle(net, fields, diag, v, D):
-    """z = M(v) for v of shape [N, cells]; `diag` is the diagonal of L, same shape."""
+def round_bf16(x):
+    """x rounded to the nearest bfloat16 value (ties to even), returned as float64.
+
+    bfloat16 keeps the float32 exponent and the top 7 fraction bits; the value
+    is first rounded to float32, then the low 16 bits of its encoding are
+    rounded away (finite values only).
+    """
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def vcycle(net, fields, diag, v, D, bf16=False):
+    """z = M(v) for v of shape [N, cells]; `diag` is the diagonal of L, same shape.
+
+    bf16=True rounds the input and the weights of every 3x3 / transposed
+    convolution of the V-cycle to bfloat16 (the precision the method runs the
+    network in, with wider accumulation), everything else staying FP64: the
+    reference for how far rounding alone moves a BF16 V-cycle from the FP64 one.
+    """
     a, ainv = fields
+    cv3, cvt4 = conv3, conv_transpose4
+    if bf16:
+        def cv3(x, W, stride=1):
+            return conv3(round_bf16(x), round_bf16(W), stride)
+
+        def cvt4(x, W):
+            return conv_transpose4(round_bf16(x), round_bf16(W))
     sh = spatial_shape(D)
     L = net.L
     vt = (np.asarray(v).reshape(D.N, D.cells) / diag).reshape((D.N,) + sh)
@@ -225,22 +250,22 @@ def vcycle(net, fields, diag, v, D):
     f[0] = conv1(vt, net.W_in)
 
     def residual(l):
-        return f[l] - conv3(u[l], net.A[l]) - a[l] * u[l]
+        return f[l] - cv3(u[l], net.A[l]) - a[l] * u[l]
 
     def smooth(l, B):
         r = residual(l)
-        u[l] = u[l] + conv3(ainv[l] * r, B)
+        u[l] = u[l] + cv3(ainv[l] * r, B)
 
     for l in range(L - 1):
         u[l] = np.zeros_like(f[l])
         for B in net.Bpre[l]:
             smooth(l, B)
-        f[l + 1] = conv3(residual(l), net.R[l], stride=2)
+        f[l + 1] = cv3(residual(l), net.R[l], stride=2)
     u[L - 1] = np.zeros_like(f[L - 1])
     for B in net.Bc:
         smooth(L - 1, B)
     for l in range(L - 2, -1, -1):
-        u[l] = u[l] + conv_transpose4(u[l + 1], net.Pr[l])
+        u[l] = u[l] + cvt4(u[l + 1], net.Pr[l])
         for B in net.Bpost[l]:
             smooth(l, B)
     z = net.s * vt + conv1(u[0], net.W_out)

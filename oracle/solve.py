@@ -22,6 +22,10 @@ class Problem:
     def precond(self, v):
         return network.vcycle(self.net, self.fields, self.diag, v, self.D).reshape(-1)
 
+    def precond_bf16(self, v):
+        """The V-cycle with its convolution inputs and weights rounded to bfloat16."""
+        return network.vcycle(self.net, self.fields, self.diag, v, self.D, bf16=True).reshape(-1)
+
     def block_jacobi(self, v):
         return comparators.block_jacobi(self.D, v).reshape(-1)
 

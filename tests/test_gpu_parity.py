@@ -6,8 +6,9 @@ full-size C2 workload (128^2 cells, 32 directions, 4-level MgNet) is checked
 on the complete apply and V-cycle and, for the solve, on the FP64 residual
 computed by the oracle, which must meet rtol at any size.
 Tolerances: FP64 kernels 1e-13 (relative to the largest value), FP32
-kernels 1e-6, BF16 V-cycle 4 * 2^-8 (normwise), solutions 1e-6 (FP32 path)
-and 1e-5 (BF16-preconditioned path) relative error.
+kernels 1e-6, FP32 V-cycle 1e-5; the BF16 V-cycle against the oracle's V-cycle with the
+same bfloat16 rounding of its convolution inputs and weights (see check_vcycle);
+solutions 1e-6 (FP32 path) and 1e-5 (BF16-preconditioned path) relative error.
 """
 import numpy as np
 import pytest
@@ -68,6 +69,31 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# The BF16 V-cycle runs its 3x3 and transposed convolutions on bfloat16 inputs and weights
+# with FP32 accumulation.  Its distance from the FP64 V-cycle is therefore set by the
+# network: the oracle's V-cycle with the same inputs and weights rounded to bfloat16 (FP64
+# otherwise) measures it.  The GPU result must sit within BF16_EMU_TOL of that rounded
+# V-cycle (what remains is FP32 against FP64 accumulation and the rare element that rounds
+# the other way), and within max(BF16_FLOOR, 2 x the rounding's own distance) of the FP64 one.
+BF16_FLOOR = 4 * 2.0 ** -8
+BF16_EMU_TOL = 2.0 ** -8
+
+
+def check_vcycle(z, P, v, mode, zref=None):
+    zref = P.precond(v) if zref is None else zref
+    err = rel(z, zref)
+    if mode == "fp32":
+        say("  vcycle fp32 rel err", err)
+        assert err < 1e-5
+        return err
+    emu = P.precond_bf16(v)
+    e_emu, d_emu = rel(emu, zref), rel(z, emu)
+    say("  vcycle bf16 rel err", err, "bf16-rounded oracle", e_emu, "gpu vs rounded oracle", d_emu)
+    assert d_emu < BF16_EMU_TOL
+    assert err < max(BF16_FLOOR, 2.0 * e_emu)
+    return err
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_setup_arrays_match(name):
     say("case", name)
@@ -122,20 +148,20 @@ def test_apply_fp32(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("mode,tol", [("fp32", 1e-5), ("bf16", 4 * 2.0 ** -8)])
-def test_vcycle(name, mode, tol):
+@pytest.mark.parametrize("mode", ["fp32", "bf16"])
+def test_vcycle(name, mode):
     say("case", name, mode)
     prob, model, op, P = setup_case(name)
     rng = np.random.default_rng(3)
     v = rng.standard_normal(P.D.n)
     z = host(op.precond(model, dev(v), mode=mode)).astype(np.float64)
     ref = P.precond(v)
-    err = rel(z, ref)
+    err = check_vcycle(z, P, v, mode, ref)
     # the network part alone (z minus the diagonal skip) must match as well
     skip = v / P.diag.reshape(-1) * P.net.s
     err_net = rel(z - skip, ref - skip)
-    say("  vcycle", mode, "rel err", err, "network part", err_net)
-    assert err < tol and err_net < 4 * tol
+    say("  network part", err_net)
+    assert err_net < 4 * max(err, 1e-5 if mode == "fp32" else BF16_FLOOR)
 
 
 @pytest.mark.parametrize("n", [16, 12])
@@ -155,10 +181,9 @@ def test_vcycle_3d_48_channels(n):
     rng = np.random.default_rng(8)
     v = rng.standard_normal(P.D.n)
     ref = P.precond(v)
-    for mode, tol in (("fp32", 1e-5), ("bf16", 4 * 2.0 ** -8)):
+    for mode in ("fp32", "bf16"):
         z = host(op.precond(model, dev(v), mode=mode)).astype(np.float64)
-        say("  vcycle", mode, rel(z, ref))
-        assert rel(z, ref) < tol
+        check_vcycle(z, P, v, mode, ref)
     za = host(op.precond(model, dev(v), mode="bf16"))
     zb = host(op.precond(model, dev(2.0 * v), mode="bf16"))
     assert bool((zb == 2 * za).all())
@@ -305,10 +330,9 @@ def test_c2_full_apply_and_vcycle(c2_full):
     y32 = host(op.apply(dev(x.astype(np.float32), "float32"))).astype(np.float64)
     assert rel(y32, P.apply(x.astype(np.float32).astype(np.float64))) < 1e-6
     zref = P.precond(x)
-    for mode, tol in (("fp32", 1e-5), ("bf16", 4 * 2.0 ** -8)):
+    for mode in ("fp32", "bf16"):
         z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
-        say("  vcycle", mode, rel(z, zref))
-        assert rel(z, zref) < tol
+        check_vcycle(z, P, x, mode, zref)
 
 
 @pytest.fixture(scope="module")
@@ -326,15 +350,13 @@ def c2_trained():
     return prob, model, op, P
 
 
-@pytest.mark.parametrize("mode,tol", [("fp32", 1e-5), ("bf16", 4 * 2.0 ** -8)])
-def test_c2_trained_vcycle(c2_trained, mode, tol):
+@pytest.mark.parametrize("mode", ["fp32", "bf16"])
+def test_c2_trained_vcycle(c2_trained, mode):
     prob, model, op, P = c2_trained
     say("case c2 trained vcycle", mode)
     x = np.random.default_rng(12).standard_normal(P.D.n)
     z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
-    err = rel(z, P.precond(x))
-    say("  rel err", err)
-    assert err < tol
+    check_vcycle(z, P, x, mode)
 
 
 @pytest.mark.parametrize("mode", ["bf16", "fp32"])
@@ -426,10 +448,9 @@ def test_full_size_apply_and_vcycle(name):
     y32 = host(op.apply(dev(x32, "float32"))).astype(np.float64)
     assert rel(y32, P.apply(x32.astype(np.float64))) < 1e-6
     zref = P.precond(x)
-    for mode, tol in (("fp32", 1e-5), ("bf16", 4 * 2.0 ** -8)):
+    for mode in ("fp32", "bf16"):
         z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
-        say("  vcycle", mode, rel(z, zref))
-        assert rel(z, zref) < tol
+        check_vcycle(z, P, x, mode, zref)
     # the V-cycle is linear in its input and scaling by 2 is exact in every
     # format it uses, so M(2x) is 2 M(x) bit for bit
     za = host(op.precond(model, dev(x), mode="bf16"))

@@ -345,7 +345,9 @@ def test_vcycle_is_linear(dim):
     assert np.linalg.norm(lhs - rhs_) <= 1e-12 * np.linalg.norm(lhs)
 
 
-def test_vcycle_identity_weights_give_twice_jacobi():
+def _identity_net_problem():
+    # one level, one smoothing step, A = 0, a = 0, a^{-1} = 1, B = centre-tap identity,
+    # W_in = W_out = I (c0 = N), s = 1: u = B * (a^{-1} f) = v / d and z = 2 v / d
     prob = problems.make(n=8, ndir=8, g=0.5, eps=0.1,
                          mg=dict(c0=8, levels=1, nu_pre=0, nu_post=0, nu_coarse=1, coef_ch=3, seed=1))
     hdr, t = configs.problem_weights(prob)
@@ -359,9 +361,42 @@ def test_vcycle_identity_weights_give_twice_jacobi():
     B[:] = 0
     for c in range(8):
         B[c, c, 1, 1] = 1.0
-    P = osolve.Problem(prob, weights.pack_mgn1(hdr, t))
+    return osolve.Problem(prob, weights.pack_mgn1(hdr, t))
+
+
+def test_vcycle_identity_weights_give_twice_jacobi():
+    P = _identity_net_problem()
     v = np.random.default_rng(1).standard_normal(P.D.n)
     assert np.allclose(P.precond(v), 2.0 * v / P.diag.reshape(-1), rtol=1e-14)
+
+
+def test_round_bf16_matches_torch_bfloat16():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(200000) * np.exp(rng.uniform(-30, 30, 200000))
+    # bfloat16 spacing near 1 is 2^-7: 1 + 2^-8 and 1 + 3 2^-8 are ties, rounded to even
+    x[:4] = [0.0, -2.5, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8]
+    r = network.round_bf16(x)
+    t = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(r, t)
+    assert r[2] == 1.0 and r[3] == 1.0 + 2.0 ** -6 and r[1] == -2.5
+
+
+def test_bf16_vcycle_identity_weights_and_homogeneity():
+    # with identity weights only the smoother's input is rounded: z = v/d + bf16(v/d)
+    P = _identity_net_problem()
+    v = np.random.default_rng(2).standard_normal(P.D.n)
+    vt = v / P.diag.reshape(-1)
+    assert np.allclose(P.precond_bf16(v), vt + network.round_bf16(vt), rtol=1e-15, atol=0)
+    # rounding commutes with scaling by 2, so the rounded V-cycle is exactly homogeneous
+    prob, blob = _net_problem(2)
+    Q = osolve.Problem(prob, blob)
+    w = np.random.default_rng(4).standard_normal(Q.D.n)
+    z = Q.precond_bf16(w)
+    assert np.array_equal(Q.precond_bf16(2.0 * w), 2.0 * z)
+    # and it moves the V-cycle by about the bfloat16 unit roundoff, not by zero or by O(1)
+    e = np.linalg.norm(z - Q.precond(w)) / np.linalg.norm(Q.precond(w))
+    assert 2.0 ** -12 < e < 2.0 ** -4
 
 
 def test_mgn1_reader_rejects_corrupt_blobs():
