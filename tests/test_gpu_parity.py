@@ -72,11 +72,14 @@ def rel(a, b):
 # The BF16 V-cycle runs its 3x3 and transposed convolutions on bfloat16 inputs and weights
 # with FP32 accumulation.  Its distance from the FP64 V-cycle is therefore set by the
 # network: the oracle's V-cycle with the same inputs and weights rounded to bfloat16 (FP64
-# otherwise) measures it.  The GPU result must sit within BF16_EMU_TOL of that rounded
-# V-cycle (what remains is FP32 against FP64 accumulation and the rare element that rounds
-# the other way), and within max(BF16_FLOOR, 2 x the rounding's own distance) of the FP64 one.
+# otherwise) measures it.  The GPU rounds the same values, except where FP32 and FP64
+# accumulation leave a value on different sides of a rounding boundary; those elements and
+# what the network makes of them keep the GPU result within a fraction of the rounding's own
+# effect of the rounded V-cycle (measured: at most 0.28 of it, for trained weights).  So the
+# GPU result must be closer to the rounded V-cycle than BF16_EMU_FRAC of the rounding's
+# distance from the FP64 one, and within max(BF16_FLOOR, 2 x that distance) of the FP64 one.
 BF16_FLOOR = 4 * 2.0 ** -8
-BF16_EMU_TOL = 2.0 ** -8
+BF16_EMU_FRAC = 0.5
 
 
 def check_vcycle(z, P, v, mode, zref=None):
@@ -89,7 +92,7 @@ def check_vcycle(z, P, v, mode, zref=None):
     emu = P.precond_bf16(v)
     e_emu, d_emu = rel(emu, zref), rel(z, emu)
     say("  vcycle bf16 rel err", err, "bf16-rounded oracle", e_emu, "gpu vs rounded oracle", d_emu)
-    assert d_emu < BF16_EMU_TOL
+    assert d_emu < max(2.0 ** -16, BF16_EMU_FRAC * e_emu)
     assert err < max(BF16_FLOOR, 2.0 * e_emu)
     return err
 
