@@ -183,6 +183,35 @@ def rhs_pool(count, N, ny, nx, rng):
     return out
 
 
+class BestKeeper:
+    """Guards a long run against late divergence: every `window` steps the mean loss of the
+    window is compared with the best so far and the parameters of the best window are kept;
+    at the end they are restored when the last window is worse by more than `slack` (or the
+    loss stopped being finite)."""
+
+    def __init__(self, window=200, slack=1.5):
+        self.window, self.slack = window, slack
+        self.best, self.params, self.step = math.inf, None, -1
+
+    def update(self, it, hist, params):
+        if (it + 1) % self.window:
+            return
+        w = float(np.mean(hist[-self.window:]))
+        if math.isfinite(w) and w < self.best:
+            self.best, self.step = w, it
+            self.params = [q.detach().clone() for q in params]
+
+    def finish(self, hist, params):
+        """Restores the best window's parameters if needed; returns (step kept, its loss)."""
+        last = float(np.mean(hist[-self.window:])) if hist else math.inf
+        if self.params is None or (math.isfinite(last) and last <= self.slack * self.best):
+            return len(hist) - 1, last
+        with _torch().no_grad():
+            for q, b in zip(params, self.params):
+                q.copy_(b)
+        return self.step, self.best
+
+
 def train(family, scatter, steps, batch, lr, seed, log, device="cuda", media_pool=64, rhs_count=256):
     """scatter(prob) -> S [N, N] of a problem (the library's matrix)."""
     torch = _torch()
@@ -206,6 +235,7 @@ def train(family, scatter, steps, batch, lr, seed, log, device="cuda", media_poo
         pools[n] = torch.as_tensor(rhs_pool(rhs_count, N, n, n, rng), device=device)
     log("%d media in %d groups" % (len(probs), len(groups)))
     hist = []
+    keeper = BestKeeper()
     t0 = time.time()
     for it in range(steps):
         lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
@@ -225,8 +255,17 @@ def train(family, scatter, steps, batch, lr, seed, log, device="cuda", media_poo
         torch.nn.utils.clip_grad_norm_(net.params(), 1.0)
         opt.step()
         hist.append(float(loss.detach()))
+        keeper.update(it, hist, net.params())
         if it % 50 == 0 or it == steps - 1:
             log("step %d loss %.4f lr %.2e (%.0f s)" % (it, hist[-1], lr_t, time.time() - t0))
+        if not math.isfinite(hist[-1]):
+            log("step %d: loss is not finite, stopping" % it)
+            break
+    kept, kept_loss = keeper.finish(hist, net.params())
+    if kept != len(hist) - 1:
+        log("final loss %.3g against %.3g at step %d: keeping the parameters of step %d"
+            % (float(np.mean(hist[-keeper.window:])), kept_loss, kept, kept))
+    net.kept_step, net.kept_loss = kept, kept_loss
     return net, hist
 
 
@@ -268,7 +307,8 @@ def main(argv=None):
         fh.write(blob)
     rec = {"family": args.family, "steps": args.steps, "batch": args.batch, "lr": args.lr, "seed": args.seed,
            "media": args.media,
-           "loss_first": hist[0], "loss_last": float(np.mean(hist[-50:])), "blob_bytes": len(blob)}
+           "loss_first": hist[0], "loss_last": float(np.mean(hist[-50:])), "blob_bytes": len(blob),
+           "kept_step": net.kept_step, "kept_window_loss": net.kept_loss}
     with open(args.out + ".json", "w") as fh:
         json.dump(rec, fh, indent=1)
     log(json.dumps(rec))

@@ -47,3 +47,25 @@ def test_training_network_is_the_vcycle():
     assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
     # the blob written back is the blob read
     assert net.blob() == weights.pack_mgn1(*configs.problem_weights(prob))
+
+
+def test_best_keeper_restores_the_best_window_after_divergence():
+    from paper_2604_23265_amd import train_mgnet as T
+    w = torch.zeros(3)
+    keeper = T.BestKeeper(window=4, slack=1.5)
+    hist = []
+    for it in range(16):
+        w += 1.0                                          # the parameters move every step
+        hist.append(1.0 / (it + 1) if it < 8 else 1e30)   # loss falls, then blows up
+        keeper.update(it, hist, [w])
+    step, loss = keeper.finish(hist, [w])
+    assert step == 7 and abs(loss - np.mean([1 / 5, 1 / 6, 1 / 7, 1 / 8])) < 1e-12
+    assert torch.equal(w, torch.full((3,), 8.0))        # the parameters of step 7
+    # a run that ends at its best keeps its final parameters
+    w2 = torch.zeros(2)
+    k2, h2 = T.BestKeeper(window=4), []
+    for it in range(8):
+        w2 += 1.0
+        h2.append(1.0 / (it + 1))
+        k2.update(it, h2, [w2])
+    assert k2.finish(h2, [w2])[0] == 7 and torch.equal(w2, torch.full((2,), 8.0))
