@@ -79,6 +79,18 @@ def measured_apply_traffic():
         return {}
 
 
+def trained_description():
+    """How the C2 weights were trained, from their record next to the blob."""
+    import json
+    try:
+        rec = json.load(open(TRAINED[:-len(".mgn1")] + ".json"))["record"]
+        return ("trained offline for the C2 family (residual loss ||b - L M b||, AdamW, %d steps at lr %g "
+                "over %d seeded media disjoint from these instances; weights/c2_mgnet.json)"
+                % (rec["steps"], rec["lr"], rec["media"]))
+    except (OSError, KeyError, ValueError):
+        return "trained offline for the C2 family (weights/c2_mgnet.json)"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -370,9 +382,7 @@ def main():
                     "continuous-batching server" % (args.batch, 2000 + args.batch - 1),
             "grid": [128, 128], "directions": 32, "unknowns": int(ops[0].n), "restart": 30, "rtol": 1e-6,
             "precond": "MgNet BF16 MFMA, FP32 accumulation",
-            "weights": ("trained offline for the C2 family (residual loss ||b - L M b||, AdamW, 8000 steps over "
-                        "256 seeded media disjoint from these instances; weights/c2_mgnet.json)"
-                        if args.weights == "trained" else "seeded initial weights (seed 2001)"),
+            "weights": trained_description() if args.weights == "trained" else "seeded initial weights (seed 2001)",
         },
         "iterations_per_solve": float(np.mean(its)),
         "rel_residual_max": float(max(s["rel_residual"] for s in sts)),
