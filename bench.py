@@ -81,7 +81,6 @@ def measured_apply_traffic():
 
 def trained_description():
     """How the C2 weights were trained, from their record next to the blob."""
-    import json
     try:
         rec = json.load(open(TRAINED[:-len(".mgn1")] + ".json"))["record"]
         return ("trained offline for the C2 family (residual loss ||b - L M b||, AdamW, %d steps at lr %g "
