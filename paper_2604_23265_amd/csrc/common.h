@@ -249,6 +249,10 @@ struct Operator {
   OpArrays relative() const;        // offsets from `block`
   // operators with equal shape keys share the block layout
   std::vector<int64_t> shape_key() const;
+  // The geometry of this operator (dimensions, directions, model levels and
+  // channels) with no device arrays: what launches need to size themselves,
+  // kept by a batch that outlives the operator it was created for.
+  std::unique_ptr<Operator> geometry() const;
 };
 
 // What a launch addresses: the operator's shape, its arrays (absolute, or
@@ -486,7 +490,7 @@ class Batch {
   void finish_member(int z, const SlotDesc& d, SlotEmit& em);
   void upload_all();
 
-  const Operator& shape_;
+  std::unique_ptr<Operator> shape_;  // geometry only: the first request's operator may be freed
   std::vector<int64_t> key_;
   const Model* m_;
   int k_, precond_, kind_, cap_;
@@ -520,6 +524,12 @@ class Batch {
 std::vector<hipGraphExec_t>* step_graphs(const void* tab, const Model* m, int precond, int k,
                                          const std::vector<int64_t>& shape, int zc);
 void drop_step_graphs(const Model* m);
+// A live batch marks its slot table in use: graphs of tables in use are
+// never evicted.  Graphs of other tables stay cached (a later solve on the
+// same workspace reuses them) up to a bounded number of keys, least
+// recently used first out.
+void step_graphs_hold(const void* tab);
+void step_graphs_release(const void* tab);
 
 }  // namespace rte
 

@@ -23,6 +23,25 @@ std::vector<int64_t> Operator::shape_key() const {
   return {dim, nx, ny, nz, ndir, levels, c0};
 }
 
+std::unique_ptr<Operator> Operator::geometry() const {
+  std::unique_ptr<Operator> o(new Operator());
+  o->dim = dim;
+  o->nx = nx;
+  o->ny = ny;
+  o->nz = nz;
+  o->ndir = ndir;
+  o->kernel = kernel;
+  o->cells = cells;
+  o->n = n;
+  o->h = h;
+  o->g = g;
+  o->device = device;
+  o->model = model;
+  o->levels = levels;
+  o->c0 = c0;
+  return o;
+}
+
 OpArrays Operator::relative() const {
   auto rel = [&](auto* p) { return p ? at(p, uint64_t(0) - reinterpret_cast<uint64_t>(block)) : p; };
   OpArrays r;

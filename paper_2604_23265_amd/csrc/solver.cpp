@@ -193,10 +193,41 @@ struct GraphKey {
   }
 };
 
+struct GraphEntry {
+  std::vector<hipGraphExec_t> g = std::vector<hipGraphExec_t>(4, nullptr);  // register budgets 8, 16, 32, 64
+  uint64_t used = 0;
+};
 std::mutex g_graph_mu;
-std::map<GraphKey, std::unique_ptr<std::vector<hipGraphExec_t>>>& graph_map() {
-  static auto* m = new std::map<GraphKey, std::unique_ptr<std::vector<hipGraphExec_t>>>();
+std::map<GraphKey, std::unique_ptr<GraphEntry>>& graph_map() {
+  static auto* m = new std::map<GraphKey, std::unique_ptr<GraphEntry>>();
   return *m;
+}
+std::map<const void*, int>& held_tables() {
+  static auto* m = new std::map<const void*, int>();
+  return *m;
+}
+uint64_t g_graph_clock = 0;
+// keys kept beyond the ones of tables in use
+constexpr size_t GRAPH_CACHE_KEYS = 32;
+
+void destroy_entry(GraphEntry& e) {
+  for (hipGraphExec_t x : e.g)
+    if (x) (void)hipGraphExecDestroy(x);
+}
+
+// with g_graph_mu held: evict least recently used keys of tables not in use
+void trim_graphs() {
+  auto& mp = graph_map();
+  auto& held = held_tables();
+  while (mp.size() > GRAPH_CACHE_KEYS) {
+    auto victim = mp.end();
+    for (auto it = mp.begin(); it != mp.end(); ++it)
+      if (!held.count(it->first.tab) && (victim == mp.end() || it->second->used < victim->second->used))
+        victim = it;
+    if (victim == mp.end()) return;
+    destroy_entry(*victim->second);
+    mp.erase(victim);
+  }
 }
 
 std::atomic<int64_t> g_steps{0};  // ticks enqueued by every batch (timer sampling)
@@ -211,8 +242,24 @@ std::vector<hipGraphExec_t>* step_graphs(const void* tab, const Model* m, int pr
                                          const std::vector<int64_t>& shape, int zc) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   auto& slot = graph_map()[GraphKey{tab, m, precond, k, zc, shape}];
-  if (!slot) slot.reset(new std::vector<hipGraphExec_t>(4, nullptr));  // register budgets 8, 16, 32, 64
-  return slot.get();
+  if (!slot) slot.reset(new GraphEntry());
+  slot->used = ++g_graph_clock;
+  std::vector<hipGraphExec_t>* r = &slot->g;
+  trim_graphs();  // the caller's table is held, so its entry stays
+  return r;
+}
+
+void step_graphs_hold(const void* tab) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  ++held_tables()[tab];
+}
+
+void step_graphs_release(const void* tab) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto& held = held_tables();
+  auto it = held.find(tab);
+  if (it != held.end() && --it->second == 0) held.erase(it);
+  trim_graphs();
 }
 
 void drop_step_graphs(const Model* m) {
@@ -220,8 +267,7 @@ void drop_step_graphs(const Model* m) {
   auto& mp = graph_map();
   for (auto it = mp.begin(); it != mp.end();) {
     if (it->first.m == m) {
-      for (hipGraphExec_t e : *it->second)
-        if (e) (void)hipGraphExecDestroy(e);
+      destroy_entry(*it->second);
       it = mp.erase(it);
     } else {
       ++it;
@@ -246,7 +292,7 @@ void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o) 
 
 Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capacity, char* tables,
              hipStream_t s)
-    : shape_(shape), key_(shape.shape_key()), m_(m), k_(k), precond_(precond), cap_(capacity), s_(s) {
+    : shape_(shape.geometry()), key_(shape.shape_key()), m_(m), k_(k), precond_(precond), cap_(capacity), s_(s) {
   RTE_REQUIRE(capacity >= 1 && capacity <= 64, RTE_EINVAL, "batch capacity must be in [1, 64]");
   RTE_REQUIRE(tables != nullptr && (reinterpret_cast<uintptr_t>(tables) & 255) == 0, RTE_EINVAL,
               "batch tables must be 256-byte aligned");
@@ -276,10 +322,12 @@ Batch::Batch(const Operator& shape, const Model* m, int k, int precond, int capa
   std::memset(hemit_, 0, 2 * size_t(capacity) * sizeof(SlotEmit));
   for (auto& e : ev_tick_) RTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   upload_all();
+  step_graphs_hold(tab_);
 }
 
 Batch::~Batch() {
   (void)hipStreamSynchronize(s_);
+  step_graphs_release(tab_);
   waiting_.clear();
   draining_.clear();
   slot_.clear();
@@ -393,7 +441,7 @@ void Batch::admit(int z, SlotInit& in) {
 void Batch::boundary_launches(int zc) {
   Quiet quiet;
   const Slots so{tab_, zc, GATE_EDGE};
-  const Target T{&shape_, rel_, so};
+  const Target T{shape_.get(), rel_, so};
   const Small q = small_of(lay_);
   const int64_t n = lay_.n;
   const int nb = lay_.nblk, k = k_;
@@ -438,8 +486,8 @@ void Batch::step_body(int jmax, int zc, hipStream_t s) {
   const Slots sl{tab_, zc, GATE_LIVE};
   const Slots vz{tab_, zc, GATE_LIVE, ldv * 8, ldz * 4};  // V_j in, Z_j out
   const Slots zv{tab_, zc, GATE_LIVE, ldz * 4, ldv * 8};  // Z_j in, V_{j+1} out
-  const Target Tvz{&shape_, rel_, vz};
-  const Target Tzv{&shape_, rel_, zv};
+  const Target Tvz{shape_.get(), rel_, vz};
+  const Target Tzv{shape_.get(), rel_, zv};
   double* part1 = off<double>(lay_.off_part1);
   double* part2 = off<double>(lay_.off_part2);
   double* h1 = off<double>(q.h1);

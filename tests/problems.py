@@ -43,3 +43,14 @@ def blob_for(prob):
     from rte_inputs import weights
     hdr, t = configs.problem_weights(prob)
     return weights.pack_mgn1(hdr, t)
+
+
+def net_problem(dim=2):
+    """A small problem with a 3-level (2D) or 2-level (3D) seeded MgNet, and its MGN1 blob."""
+    if dim == 2:
+        prob = make(n=16, ndir=8, g=0.5, eps=0.05, seed=3,
+                    mg=dict(c0=8, levels=3, nu_pre=2, nu_post=2, nu_coarse=2, coef_ch=3, seed=12))
+    else:
+        prob = make(dim=3, n=8, ndir=8, g=0.5, eps=0.05, seed=3, kind="sphere",
+                    mg=dict(c0=4, levels=2, nu_pre=1, nu_post=2, nu_coarse=1, coef_ch=3, seed=13))
+    return prob, blob_for(prob)

@@ -227,3 +227,32 @@ def test_submit_many_burst():
     for t, a, out in zip(tickets, alone, outs):
         assert done[t][0] == 0
         assert bool((out == a).all())
+
+
+def test_operator_freed_while_its_batch_serves_others():
+    """A batch is created from the first request's operator; that operator may be
+    freed once its ticket is polled, and the requests of the same shape still queued
+    behind it must solve exactly as they do alone."""
+    torch = torch_cuda()
+    from paper_2604_23265_amd import api
+    say("case serving: first operator freed after its poll")
+    reqs = [configs.c3_request(r, ndir_choices=(16,), grid_choices=(32,)) for r in range(300, 304)]
+    models, ops = _build(reqs)
+    kw = dict(restart=10, rtol=1e-8, precond="bf16")
+    alone = [op.solve(**kw)[0].clone() for op in ops]
+    srv = api.Server(arena_bytes=256 << 20, max_slots=1)   # one slot: the others wait in line
+    outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+    tickets = [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops, outs)]
+    first = _wait(srv, tickets[:1])
+    assert first[tickets[0]][0] == 0
+    ops[0].close()                       # the operator the batch was created from
+    ops[0] = None
+    torch.cuda.synchronize()
+    junk = torch.full((1 << 22,), float("nan"), dtype=torch.float64, device="cuda")  # reuse its memory
+    done = _wait(srv, tickets[1:])
+    srv.close()
+    del junk
+    for t, a, out in zip(tickets[1:], alone[1:], outs[1:]):
+        assert done[t][0] == 0
+        assert bool((out == a).all()), "a request served after the first operator was freed differs"
+    assert bool((outs[0] == alone[0]).all())

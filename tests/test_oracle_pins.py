@@ -255,32 +255,6 @@ def test_mirror_symmetry():
 
 # --------------------------------------------- network semantics (pin 9) ---
 
-torch = pytest.importorskip("torch")
-F = torch.nn.functional
-
-
-@pytest.mark.parametrize("dim,stride", [(2, 1), (2, 2), (3, 1), (3, 2)])
-def test_conv3_is_pytorch_cross_correlation(dim, stride):
-    rng = np.random.default_rng(1)
-    x = rng.standard_normal((5,) + (8,) * dim)
-    W = rng.standard_normal((7, 5) + (3,) * dim)
-    fn = F.conv2d if dim == 2 else F.conv3d
-    ref = fn(torch.from_numpy(x)[None], torch.from_numpy(W), stride=stride, padding=1)[0].numpy()
-    assert np.allclose(network.conv3(x, W, stride), ref, rtol=1e-13, atol=1e-13)
-
-
-@pytest.mark.parametrize("dim", [2, 3])
-def test_conv_transpose4_is_pytorch(dim):
-    rng = np.random.default_rng(2)
-    x = rng.standard_normal((6,) + (4,) * dim)
-    W = rng.standard_normal((6, 3) + (4,) * dim)
-    fn = F.conv_transpose2d if dim == 2 else F.conv_transpose3d
-    ref = fn(torch.from_numpy(x)[None], torch.from_numpy(W), stride=2, padding=1)[0].numpy()
-    out = network.conv_transpose4(x, W)
-    assert out.shape == ref.shape
-    assert np.allclose(out, ref, rtol=1e-13, atol=1e-13)
-
-
 def test_bilinear_prolongation_reproduces_linear_functions():
     C, n = 3, 8
     k = np.array([1, 3, 3, 1]) / 4.0
@@ -305,38 +279,9 @@ def test_full_weighting_restriction_keeps_constants():
     assert np.allclose(out[:, 1:, 1:], 3.0, atol=1e-15)
 
 
-def _net_problem(dim=2):
-    if dim == 2:
-        prob = problems.make(n=16, ndir=8, g=0.5, eps=0.05, seed=3,
-                             mg=dict(c0=8, levels=3, nu_pre=2, nu_post=2, nu_coarse=2, coef_ch=3, seed=12))
-    else:
-        prob = problems.make(dim=3, n=8, ndir=8, g=0.5, eps=0.05, seed=3, kind="sphere",
-                             mg=dict(c0=4, levels=2, nu_pre=1, nu_post=2, nu_coarse=1, coef_ch=3, seed=13))
-    return prob, problems.blob_for(prob)
-
-
-@pytest.mark.parametrize("dim", [2, 3])
-def test_coeffnet_is_the_pytorch_pyramid(dim):
-    prob, blob = _net_problem(dim)
-    D = dsc.Discretisation(prob)
-    net = network.Net(blob)
-    a, ainv = network.coeffnet(net, D)
-    conv = F.conv2d if dim == 2 else F.conv3d
-    sh = network.spatial_shape(D)
-    X = torch.from_numpy(np.stack([np.log(D.sT), D.sA / D.sT, np.log(D.eps)]).reshape((3,) + sh))[None]
-    T = lambda a: torch.from_numpy(np.ascontiguousarray(a))
-    Fm = X
-    for l in range(net.L):
-        Fm = torch.relu(conv(Fm, T(net.CW[l]), T(net.CB[l]), stride=1 if l == 0 else 2, padding=1))
-        wa = T(net.HAW[l]).reshape(net.HAW[l].shape + (1,) * dim)
-        wi = T(net.HIW[l]).reshape(net.HIW[l].shape + (1,) * dim)
-        assert np.allclose(a[l], conv(Fm, wa, T(net.HAB[l]))[0].numpy(), rtol=1e-12, atol=1e-12)
-        assert np.allclose(ainv[l], conv(Fm, wi, T(net.HIB[l]))[0].numpy(), rtol=1e-12, atol=1e-12)
-
-
 @pytest.mark.parametrize("dim", [2, 3])
 def test_vcycle_is_linear(dim):
-    prob, blob = _net_problem(dim)
+    prob, blob = problems.net_problem(dim)
     P = osolve.Problem(prob, blob)
     rng = np.random.default_rng(0)
     u, v = rng.standard_normal((2, P.D.n))
@@ -370,18 +315,6 @@ def test_vcycle_identity_weights_give_twice_jacobi():
     assert np.allclose(P.precond(v), 2.0 * v / P.diag.reshape(-1), rtol=1e-14)
 
 
-def test_round_bf16_matches_torch_bfloat16():
-    torch = pytest.importorskip("torch")
-    rng = np.random.default_rng(3)
-    x = rng.standard_normal(200000) * np.exp(rng.uniform(-30, 30, 200000))
-    # bfloat16 spacing near 1 is 2^-7: 1 + 2^-8 and 1 + 3 2^-8 are ties, rounded to even
-    x[:4] = [0.0, -2.5, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8]
-    r = network.round_bf16(x)
-    t = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
-    assert np.array_equal(r, t)
-    assert r[2] == 1.0 and r[3] == 1.0 + 2.0 ** -6 and r[1] == -2.5
-
-
 def test_bf16_vcycle_identity_weights_and_homogeneity():
     # with identity weights only the smoother's input is rounded: z = v/d + bf16(v/d)
     P = _identity_net_problem()
@@ -389,7 +322,7 @@ def test_bf16_vcycle_identity_weights_and_homogeneity():
     vt = v / P.diag.reshape(-1)
     assert np.allclose(P.precond_bf16(v), vt + network.round_bf16(vt), rtol=1e-15, atol=0)
     # rounding commutes with scaling by 2, so the rounded V-cycle is exactly homogeneous
-    prob, blob = _net_problem(2)
+    prob, blob = problems.net_problem(2)
     Q = osolve.Problem(prob, blob)
     w = np.random.default_rng(4).standard_normal(Q.D.n)
     z = Q.precond_bf16(w)
@@ -400,7 +333,7 @@ def test_bf16_vcycle_identity_weights_and_homogeneity():
 
 
 def test_mgn1_reader_rejects_corrupt_blobs():
-    prob, blob = _net_problem(2)
+    prob, blob = problems.net_problem(2)
     network.Net(blob)
     for bad in (blob[:100], b"XGN1" + blob[4:], blob + b"\0\0\0\0", blob[:-4]):
         with pytest.raises(network.FormatError):
@@ -415,7 +348,7 @@ def test_mgn1_reader_rejects_corrupt_blobs():
 # ------------------------------------------------- Arnoldi (pin 10) ---
 
 def test_arnoldi_identities_and_preconditioned_solution():
-    prob, blob = _net_problem(2)
+    prob, blob = problems.net_problem(2)
     P = osolve.Problem(prob, blob)
     rec = []
     x, info = P.solve(rtol=1e-12, restart=15, record=rec)
