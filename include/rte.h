@@ -163,6 +163,28 @@ rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, i
                              const double* v, float* z, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the MgNet
+ * V-cycle of rte_precond_apply (precond RTE_PC_MGNET_BF16 or
+ * RTE_PC_MGNET_FP32 only), with the level activations in a device array
+ * owned by the library instead of a caller workspace.  The array holds
+ * 64 MiB (RTE_NOALLOC_SCRATCH_BYTES) on each device the library runs on,
+ * kept until the process ends; a V-cycle whose rte_precond_workspace_bytes
+ * exceeds it is rejected with RTE_ENOMEM.  The call allocates no device
+ * memory: the model's weights must already be on the current device (they
+ * are once an operator has been built with the model on it).  Every call on
+ * one device uses that device's one array, so calls that overlap on one
+ * device (concurrent streams or threads) race and give undefined results;
+ * serialise them.  Nothing in the array needs to start at zero (each
+ * V-cycle writes every activation before reading it).  v: device double
+ * [n]; z: device float [n]; results equal rte_precond_apply's bit for bit.
+ * Errors: RTE_EINVAL (null argument, other preconditioner, operator not
+ * built with this model, weights not on the current device), RTE_ENOMEM,
+ * RTE_EDEVICE. */
+#define RTE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rte_status rte_precond_apply_noalloc(const rte_operator* op, const mgnet_model* model, int precond,
+                                     const double* v, float* z, void* stream);
+
 typedef struct {
   int restart;            /* Krylov cycle length k, 1..64 (paper: GMRES)          */
   double rtol;            /* stop when ||b - L x||_2 <= rtol ||b||_2, checked in FP64 */

@@ -73,6 +73,7 @@ _SIGS = {
     "rte_residual": [_P, _P, _P, _P],
     "rte_precond_workspace_bytes": [_P, _P, C.POINTER(C.c_size_t)],
     "rte_precond_apply": [_P, _P, C.c_int, _P, _P, _P, C.c_size_t, _P],
+    "rte_precond_apply_noalloc": [_P, _P, C.c_int, _P, _P, _P],
     "rte_workspace_bytes": [_P, _P, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)],
     "rte_solve": [_P, _P, C.POINTER(SolveOpts), _P, C.c_size_t, _P, C.POINTER(SolveStats), _P],
     "rte_server_create": [_P, C.c_size_t, C.c_int, C.POINTER(_P)],

@@ -175,6 +175,16 @@ class Operator:
                                       _dptr(workspace), workspace.numel(), _stream(stream)))
         return z
 
+    def precond_noalloc(self, model, v, mode="bf16", z=None, stream=None):
+        """z = M(v) with the V-cycle activations in the library's own device array
+        (rte_precond_apply_noalloc): no workspace, no device allocation in the call."""
+        torch = _torch()
+        if z is None:
+            z = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        check(lib().rte_precond_apply_noalloc(self._h, model.handle, PRECOND[mode], _dptr(v), _dptr(z),
+                                              _stream(stream)))
+        return z
+
     # ---- solve
     def opts(self, restart=30, rtol=1e-6, max_iters=20000, precond="bf16", x0=None, b=None):
         o = L.SolveOpts()
