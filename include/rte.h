@@ -185,6 +185,41 @@ rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, i
 rte_status rte_precond_apply_noalloc(const rte_operator* op, const mgnet_model* model, int precond,
                                      const double* v, float* z, void* stream);
 
+/* One convolution of the MgNet V-cycle (Sec. 3.3) with its fused pointwise
+ * epilogue, run over `nslots` independent inputs in one launch exactly as
+ * the V-cycle runs it: an inspection and test hook for the convolution
+ * kernels.
+ *   which, level, index select the weights: MGN_W_A (A_level), MGN_W_BPRE
+ *     (B_level^(index), before the restriction), MGN_W_BPOST (after the
+ *     prolongation), MGN_W_BCOARSE (coarsest level, B^(index)), MGN_W_R
+ *     (R_level: kernel 3, stride 2, channels C -> 2C), MGN_W_PR (Pr_level:
+ *     kernel 4, stride 2, transposed, 2C -> C, input on level + 1's grid);
+ *   precond: RTE_PC_MGNET_BF16 (input and weights rounded to bfloat16, nearest
+ *     even, products accumulated in FP32) or RTE_PC_MGNET_FP32;
+ *   in_dim: the input grid (cells along x, y, z; 1 for an unused z);
+ *   epilogue, with conv the convolution of `in` (zero padding outside the grid):
+ *     MGN_EPI_STORE    out = conv
+ *     MGN_EPI_ACCUM    out = out + conv
+ *     MGN_EPI_STORE_T  out = conv, out2 = ainv (.) conv
+ *     MGN_EPI_RESID_R  out = f - conv - a (.) in          (3x3 stride 1 only)
+ *     MGN_EPI_RESID_T  out = ainv (.) (f - conv - a (.) in) (3x3 stride 1 only)
+ *   Every array is device FP32, channels-last [pixels][channels] with pixels
+ *   x fastest; f, a, ainv and out2 have the output's shape (NULL where the
+ *   epilogue does not read them).  Slot s's arrays begin s * slot_stride
+ *   bytes after slot 0's (one stride for every array; slot_stride is ignored
+ *   when nslots is 1).
+ *   table: device memory of at least 128 * nslots bytes for the launch's slot
+ *   table, or NULL when nslots is 1.
+ * Synchronises `stream` before returning.  Errors: RTE_EINVAL (unknown
+ * weights or epilogue, grid not matching the level, null array). */
+enum { MGN_W_A = 0, MGN_W_BPRE = 1, MGN_W_BPOST = 2, MGN_W_BCOARSE = 3, MGN_W_R = 4, MGN_W_PR = 5 };
+enum { MGN_EPI_STORE = 0, MGN_EPI_ACCUM = 1, MGN_EPI_STORE_T = 2, MGN_EPI_RESID_R = 3,
+       MGN_EPI_RESID_T = 4 };
+rte_status mgnet_conv_apply(const mgnet_model* model, int precond, int which, int level, int index,
+                            int epilogue, const int* in_dim, int nslots, size_t slot_stride,
+                            const float* in, float* out, float* out2, const float* f, const float* a,
+                            const float* ainv, void* table, void* stream);
+
 typedef struct {
   int restart;            /* Krylov cycle length k, 1..64 (paper: GMRES)          */
   double rtol;            /* stop when ||b - L x||_2 <= rtol ||b||_2, checked in FP64 */

@@ -14,6 +14,8 @@ FP32, FP64 = 0, 1
 PC_NONE, PC_MGNET_BF16, PC_MGNET_FP32, PC_BLOCK_JACOBI = 0, 1, 2, 3
 ARR_RHS, ARR_SCATTER, ARR_SIGMA, ARR_FIELD_A, ARR_FIELD_AINV = 0, 1, 2, 3, 4
 K_APPLY, K_RESIDUAL, K_CONV, K_ORTH, K_PRECOND = 0, 1, 2, 3, 4
+W_A, W_BPRE, W_BPOST, W_BCOARSE, W_R, W_PR = 0, 1, 2, 3, 4, 5
+EPI_STORE, EPI_ACCUM, EPI_STORE_T, EPI_RESID_R, EPI_RESID_T = 0, 1, 2, 3, 4
 
 
 class RteError(RuntimeError):
@@ -74,6 +76,8 @@ _SIGS = {
     "rte_precond_workspace_bytes": [_P, _P, C.POINTER(C.c_size_t)],
     "rte_precond_apply": [_P, _P, C.c_int, _P, _P, _P, C.c_size_t, _P],
     "rte_precond_apply_noalloc": [_P, _P, C.c_int, _P, _P, _P],
+    "mgnet_conv_apply": [_P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int,
+                         C.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P],
     "rte_workspace_bytes": [_P, _P, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)],
     "rte_solve": [_P, _P, C.POINTER(SolveOpts), _P, C.c_size_t, _P, C.POINTER(SolveStats), _P],
     "rte_server_create": [_P, C.c_size_t, C.c_int, C.POINTER(_P)],

@@ -294,6 +294,77 @@ rte_status rte_precond_apply(const rte_operator* h, const mgnet_model* model, in
   });
 }
 
+static_assert(MGN_EPI_STORE == CONV_STORE && MGN_EPI_ACCUM == CONV_ACCUM && MGN_EPI_STORE_T == CONV_STORE_T &&
+                  MGN_EPI_RESID_R == CONV_RESID_R && MGN_EPI_RESID_T == CONV_RESID_T,
+              "the ABI's epilogue codes are the launcher's conv modes");
+static_assert(sizeof(SlotDesc) <= 128, "mgnet_conv_apply documents 128 bytes per slot");
+
+rte_status mgnet_conv_apply(const mgnet_model* model, int precond, int which, int level, int index,
+                            int epilogue, const int* in_dim, int nslots, size_t slot_stride, const float* in,
+                            float* out, float* out2, const float* f, const float* a, const float* ainv,
+                            void* table, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(model && in_dim && in && out, RTE_EINVAL, "mgnet_conv_apply: null argument");
+    RTE_REQUIRE(precond == RTE_PC_MGNET_BF16 || precond == RTE_PC_MGNET_FP32, RTE_EINVAL,
+                "mgnet_conv_apply: precond must be an MgNet precision");
+    RTE_REQUIRE(epilogue >= MGN_EPI_STORE && epilogue <= MGN_EPI_RESID_T, RTE_EINVAL,
+                "mgnet_conv_apply: unknown epilogue");
+    RTE_REQUIRE(nslots >= 1 && (nslots == 1 || table), RTE_EINVAL, "mgnet_conv_apply: bad slot count or table");
+    Model& m = *model->m;
+    const int L = m.levels;
+    RTE_REQUIRE(level >= 0 && level < L, RTE_EINVAL, "mgnet_conv_apply: level out of range");
+    const ConvW* w = nullptr;
+    auto pick = [&](const std::vector<ConvW>& v, int i) {
+      RTE_REQUIRE(i >= 0 && i < int(v.size()), RTE_EINVAL, "mgnet_conv_apply: index out of range");
+      return &v[size_t(i)];
+    };
+    const bool coarse = level == L - 1;
+    switch (which) {
+      case MGN_W_A: w = &m.A[size_t(level)]; break;
+      case MGN_W_BPRE: RTE_REQUIRE(!coarse, RTE_EINVAL, "no B_pre on the coarsest level"); w = pick(m.Bpre[size_t(level)], index); break;
+      case MGN_W_BPOST: RTE_REQUIRE(!coarse, RTE_EINVAL, "no B_post on the coarsest level"); w = pick(m.Bpost[size_t(level)], index); break;
+      case MGN_W_BCOARSE: RTE_REQUIRE(coarse, RTE_EINVAL, "B_coarse lives on the coarsest level"); w = pick(m.Bc, index); break;
+      case MGN_W_R: RTE_REQUIRE(!coarse, RTE_EINVAL, "no restriction from the coarsest level"); w = &m.R[size_t(level)]; break;
+      case MGN_W_PR: RTE_REQUIRE(!coarse, RTE_EINVAL, "no prolongation onto the coarsest level"); w = &m.Pr[size_t(level)]; break;
+      default: fail(RTE_EINVAL, "mgnet_conv_apply: unknown weights");
+    }
+    int d[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      d[ax] = in_dim[ax];
+      RTE_REQUIRE(d[ax] >= 1 && (ax < m.dim || d[ax] == 1), RTE_EINVAL, "mgnet_conv_apply: bad grid");
+      if (ax < m.dim && which == MGN_W_R) RTE_REQUIRE(d[ax] % 2 == 0, RTE_EINVAL, "restriction needs even extents");
+    }
+    ConvLaunch c{};
+    if (which == MGN_W_PR) convT4_setup(c, m.dim, d);
+    else conv3_setup(c, m.dim, d, which == MGN_W_R ? 2 : 1);
+    const bool needs_fa = epilogue == MGN_EPI_RESID_R || epilogue == MGN_EPI_RESID_T;
+    const bool needs_i = epilogue == MGN_EPI_RESID_T || epilogue == MGN_EPI_STORE_T;
+    RTE_REQUIRE(!needs_fa || (f && a), RTE_EINVAL, "mgnet_conv_apply: the residual epilogues need f and a");
+    RTE_REQUIRE(!needs_i || ainv, RTE_EINVAL, "mgnet_conv_apply: this epilogue needs ainv");
+    RTE_REQUIRE(epilogue != MGN_EPI_STORE_T || out2, RTE_EINVAL, "mgnet_conv_apply: STORE_T needs out2");
+    m.ensure_on_device();
+    hipStream_t s = S(stream);
+    std::vector<SlotDesc> tab;
+    if (table) {
+      tab.assign(size_t(nslots), SlotDesc{});
+      for (int z = 0; z < nslots; ++z) {
+        tab[size_t(z)].ws = uint64_t(z) * slot_stride;
+        tab[size_t(z)].op = uint64_t(z) * slot_stride;
+        tab[size_t(z)].live = 1;
+        tab[size_t(z)].occupied = 1;
+      }
+      RTE_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
+      c.sl.tab = static_cast<SlotDesc*>(table);
+      c.sl.count = nslots;
+      c.sl.gate = GATE_LIVE;
+    }
+    c.in = in; c.cin = w->cin; c.w = w; c.out = out; c.cout = w->cout; c.mode = epilogue;
+    c.f = f; c.a = a; c.ainv = ainv; c.out2 = out2;
+    launch_conv(c, precond == RTE_PC_MGNET_FP32 ? MFMA_F32 : MFMA_BF16, s);
+    RTE_HIP(hipStreamSynchronize(s));
+  });
+}
+
 rte_status rte_workspace_bytes(const rte_operator* h, const mgnet_model* model, const rte_solve_opts* opts,
                                size_t* bytes) {
   return guarded([&] {
