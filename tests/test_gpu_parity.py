@@ -6,9 +6,9 @@ full-size C2 workload (128^2 cells, 32 directions, 4-level MgNet) is checked
 on the complete apply and V-cycle and, for the solve, on the FP64 residual
 computed by the oracle, which must meet rtol at any size.
 Tolerances: FP64 kernels 1e-13 (relative to the largest value), FP32
-kernels 1e-6, FP32 V-cycle 1e-5; the BF16 V-cycle against the oracle's V-cycle with the
-same bfloat16 rounding of its convolution inputs and weights (see check_vcycle);
-solutions 1e-6 (FP32 path) and 1e-5 (BF16-preconditioned path) relative error.
+kernels 1e-6, FP32 V-cycle 1e-5; the BF16 V-cycle within a fixed bound per weight set
+(see check_vcycle); solutions 1e-6 (FP32 path) and 1e-5 (BF16-preconditioned path)
+relative error.  Each is checked on the 2-norm ratio and on the largest element.
 """
 import numpy as np
 import pytest
@@ -69,31 +69,47 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def rel_max(a, b):
+    """Largest element-wise difference over the largest element: an error confined to a few
+    elements (a tile edge, a boundary row) is not diluted as it is in the 2-norm ratio."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 # The BF16 V-cycle runs its 3x3 and transposed convolutions on bfloat16 inputs and weights
-# with FP32 accumulation.  Its distance from the FP64 V-cycle is therefore set by the
-# network: the oracle's V-cycle with the same inputs and weights rounded to bfloat16 (FP64
-# otherwise) measures it.  The GPU rounds the same values, except where FP32 and FP64
-# accumulation leave a value on different sides of a rounding boundary; those elements and
-# what the network makes of them keep the GPU result within a fraction of the rounding's own
-# effect of the rounded V-cycle (measured: at most 0.28 of it, for trained weights).  So the
-# GPU result must be closer to the rounded V-cycle than BF16_EMU_FRAC of the rounding's
-# distance from the FP64 one, and within max(BF16_FLOOR, 2 x that distance) of the FP64 one.
-BF16_FLOOR = 4 * 2.0 ** -8
-BF16_EMU_FRAC = 0.5
+# with FP32 accumulation; each launch is checked against the oracle element by element in
+# test_gpu_conv_parity.py.  How far the whole V-cycle then moves from the FP64 one is a
+# property of the network: how much its layers amplify the rounding of their inputs.  Each
+# weight set therefore has a fixed bound, on the 2-norm ratio and on the largest element
+# (measured values in brackets):
+#   seeded weights (every small case, C4, C5): 2e-3 from the FP64 V-cycle [<= 6.7e-4], and
+#     5e-4 from the oracle's V-cycle with the same bfloat16 rounding of the convolution
+#     inputs and weights (FP64 otherwise) [<= 2.0e-4];
+#   the trained C2 weights: 2.5e-2 from the FP64 V-cycle [9.0e-3 to 1.6e-2], and 1.5e-2
+#     from the rounded oracle [3.6e-3 to 8.0e-3].
+# The trained network's smoothers shrink the residual r = f - A*u - a(.)u well below its
+# terms, so FP32 and FP64 sums of those terms round r to different bfloat16 neighbours for
+# a few percent of its elements; the network amplifies those one-step differences as much
+# as the rounding itself (about 10x), which is why the GPU sits about half as far from the
+# rounded oracle as the rounded oracle sits from FP64.
+BF16_BOUNDS = {"seeded": (2e-3, 5e-4), "c2_trained": (2.5e-2, 1.5e-2)}
 
 
-def check_vcycle(z, P, v, mode, zref=None):
+def check_vcycle(z, P, v, mode, zref=None, weights="seeded"):
     zref = P.precond(v) if zref is None else zref
-    err = rel(z, zref)
+    err, err_max = rel(z, zref), rel_max(z, zref)
     if mode == "fp32":
-        say("  vcycle fp32 rel err", err)
+        say("  vcycle fp32 rel err %.3e  max-norm %.3e" % (err, err_max))
         assert err < 1e-5
+        assert err_max < 1e-5
         return err
     emu = P.precond_bf16(v)
     e_emu, d_emu = rel(emu, zref), rel(z, emu)
-    say("  vcycle bf16 rel err", err, "bf16-rounded oracle", e_emu, "gpu vs rounded oracle", d_emu)
-    assert d_emu < max(2.0 ** -16, BF16_EMU_FRAC * e_emu)
-    assert err < max(BF16_FLOOR, 2.0 * e_emu)
+    e_emu_max, d_emu_max = rel_max(emu, zref), rel_max(z, emu)
+    say("  vcycle bf16 rel err %.3e (max-norm %.3e); rounded oracle %.3e (%.3e); gpu vs rounded oracle "
+        "%.3e (%.3e)" % (err, err_max, e_emu, e_emu_max, d_emu, d_emu_max))
+    vs_fp64, vs_rounded = BF16_BOUNDS[weights]
+    assert err < vs_fp64 and err_max < vs_fp64
+    assert d_emu < vs_rounded and d_emu_max < vs_rounded
     return err
 
 
@@ -147,7 +163,9 @@ def test_apply_fp32(name):
     x = rng.standard_normal(P.D.n).astype(np.float32)
     y = host(op.apply(dev(x, "float32"))).astype(np.float64)
     ref = P.apply(x.astype(np.float64))
+    say("  apply fp32 rel err %.3e  max-norm %.3e" % (rel(y, ref), rel_max(y, ref)))
     assert rel(y, ref) < 1e-6
+    assert rel_max(y, ref) < 1e-6
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -164,7 +182,7 @@ def test_vcycle(name, mode):
     skip = v / P.diag.reshape(-1) * P.net.s
     err_net = rel(z - skip, ref - skip)
     say("  network part", err_net)
-    assert err_net < 4 * max(err, 1e-5 if mode == "fp32" else BF16_FLOOR)
+    assert err_net < (1e-5 if mode == "fp32" else 1e-2)
 
 
 @pytest.mark.parametrize("n", [16, 12])
@@ -227,7 +245,9 @@ def test_solve_matches_reference(name, mode):
     res = osolve.relative_residual(P, host(x))
     assert res <= 1.5e-10
     tol = 1e-5 if mode == "bf16" else 1e-6
+    say("  solution rel err %.3e  max-norm %.3e" % (rel(host(x), ref), rel_max(host(x), ref)))
     assert rel(host(x), ref) < tol
+    assert rel_max(host(x), ref) < tol
 
 
 # Direction counts of 64 and 96 on whole 64-cell tiles take the matrix-core
@@ -331,7 +351,9 @@ def test_c2_full_apply_and_vcycle(c2_full):
     ref = P.apply(x)
     assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
     y32 = host(op.apply(dev(x.astype(np.float32), "float32"))).astype(np.float64)
-    assert rel(y32, P.apply(x.astype(np.float32).astype(np.float64))) < 1e-6
+    ref32 = P.apply(x.astype(np.float32).astype(np.float64))
+    say("  apply fp32 rel err %.3e  max-norm %.3e" % (rel(y32, ref32), rel_max(y32, ref32)))
+    assert rel(y32, ref32) < 1e-6 and rel_max(y32, ref32) < 1e-6
     zref = P.precond(x)
     for mode in ("fp32", "bf16"):
         z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
@@ -359,7 +381,7 @@ def test_c2_trained_vcycle(c2_trained, mode):
     say("case c2 trained vcycle", mode)
     x = np.random.default_rng(12).standard_normal(P.D.n)
     z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
-    check_vcycle(z, P, x, mode)
+    check_vcycle(z, P, x, mode, weights="c2_trained")
 
 
 @pytest.mark.parametrize("mode", ["bf16", "fp32"])
@@ -371,6 +393,37 @@ def test_c2_trained_solve(c2_trained, mode):
     say("  stats", st)
     assert st["converged"] == 1 and st["iterations"] <= 40
     assert osolve.relative_residual(P, host(x)) <= 1e-8 * 1.01
+
+
+@pytest.fixture(scope="module")
+def c2_psi_star(c2_trained):
+    """psi* of the full C2 instance (GRF seed 2000): the oracle's FP64 flexible GMRES,
+    preconditioned by its own FP64 V-cycle with the trained weights, to rtol 1e-12."""
+    prob, model, op, P = c2_trained
+    say("oracle: C2 psi* to rtol 1e-12 (FP64 FGMRES with the FP64 V-cycle)")
+    x, st = P.solve(rtol=1e-12, restart=30, max_iters=400)
+    assert st["converged"], st
+    say("  oracle iterations", st.get("iterations"))
+    return x.reshape(-1)
+
+
+@pytest.mark.parametrize("mode,tol", [("bf16", 1e-5), ("fp32", 1e-6)])
+def test_c2_full_solution_error(c2_trained, c2_psi_star, mode, tol):
+    """Full-size C2 solution against the oracle's psi*: at rtol 1e-10 (error <= cond x rtol)
+    within 1e-5 (BF16 MgNet) and 1e-6 (FP32 MgNet), normwise and element-wise; the error of
+    the benchmark's rtol 1e-6 solve is reported."""
+    prob, model, op, P = c2_trained
+    ref = c2_psi_star
+    x, st = op.solve(model=model, precond=mode, rtol=1e-10, restart=30, max_iters=2000)
+    say("  %s rtol 1e-10: stats %s" % (mode, st))
+    assert st["converged"] == 1
+    e, em = rel(host(x), ref), rel_max(host(x), ref)
+    say("  %s rtol 1e-10: solution rel err %.3e  max-norm %.3e" % (mode, e, em))
+    assert e < tol and em < tol
+    x6, st6 = op.solve(model=model, precond=mode, rtol=1e-6, restart=30, max_iters=2000)
+    say("  %s rtol 1e-6: %d iterations, solution rel err %.3e  max-norm %.3e"
+        % (mode, st6["iterations"], rel(host(x6), ref), rel_max(host(x6), ref)))
+    assert st6["converged"] == 1
 
 
 def test_c2_full_block_jacobi(c2_full):
@@ -449,7 +502,9 @@ def test_full_size_apply_and_vcycle(name):
     assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
     x32 = x.astype(np.float32)
     y32 = host(op.apply(dev(x32, "float32"))).astype(np.float64)
-    assert rel(y32, P.apply(x32.astype(np.float64))) < 1e-6
+    ref32 = P.apply(x32.astype(np.float64))
+    say("  apply fp32 rel err %.3e  max-norm %.3e" % (rel(y32, ref32), rel_max(y32, ref32)))
+    assert rel(y32, ref32) < 1e-6 and rel_max(y32, ref32) < 1e-6
     zref = P.precond(x)
     for mode in ("fp32", "bf16"):
         z = host(op.precond(model, dev(x), mode=mode)).astype(np.float64)
