@@ -91,6 +91,11 @@ CASES = [
     (2, 16, 4, 2, "A", "RESID_T", (12, 12, 1), 3, "bf16"),
     (2, 32, 4, 0, "A", "RESID_T", (12, 12, 1), 3, "bf16"),
     (2, 32, 4, 1, "BPRE", "ACCUM", (20, 12, 1), 1, "bf16"),
+    # 16 x 8 patches (several along x and y) of the wide 3x3 kernel
+    (2, 32, 4, 0, "A", "RESID_T", (32, 8, 1), 3, "bf16"),
+    (2, 32, 4, 1, "BPOST", "ACCUM", (16, 24, 1), 32, "bf16"),
+    (2, 48, 4, 1, "A", "RESID_R", (32, 16, 1), 3, "bf16"),
+    (2, 32, 4, 0, "A", "STORE_T", (48, 16, 1), 1, "bf16"),
     # 2D restriction (stride 2) and transposed prolongation
     (2, 32, 4, 0, "R", "STORE_T", (16, 16, 1), 3, "bf16"),
     (2, 32, 4, 0, "R", "STORE", (16, 16, 1), 32, "bf16"),
