@@ -13,8 +13,11 @@ Modules
   solve           end-to-end build + FGMRES driver
   direct          independent solvers used only to pin the rest (dense LU,
                   transport sweeps, source iteration, the isotropic limit)
+  tfps            the tailored finite point scheme of Sec. 2.2 (2D): per-cell
+                  eigen-bases, midpoint continuity and inflow conditions, the
+                  assembled system and its sparse solve
 
 Functions whose result is not pinned by any test say "parity unpinned" in
 their docstring.
 """
-from . import direct, discretisation, krylov, network, solve  # noqa: F401
+from . import direct, discretisation, krylov, network, solve, tfps  # noqa: F401
