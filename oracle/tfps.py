@@ -39,8 +39,10 @@ from . import discretisation as dsc
 
 
 def _sorted_eigs(M):
-    """Eigenpairs of M (real spectrum) split by sign, each half ascending; vectors scaled to
-    max-norm 1 with their largest-magnitude entry positive."""
+    """Eigenpairs of M (real spectrum) in ascending order of the eigenvalue; each vector
+    scaled to max-norm 1 (the paper's normalisation), its sign fixed by making positive the
+    first entry whose magnitude is within 1e-8 of the largest (symmetric direction sets give
+    vectors whose largest entries tie in magnitude)."""
     w, V = np.linalg.eig(M)
     if np.max(np.abs(w.imag)) > 1e-9 * max(1.0, np.max(np.abs(w.real))):
         raise ValueError("complex eigenvalues: the cell's medium is outside the scheme's assumptions")
@@ -48,8 +50,9 @@ def _sorted_eigs(M):
     order = np.argsort(w)
     w, V = w[order], V[:, order]
     for k in range(V.shape[1]):
-        i = np.argmax(np.abs(V[:, k]))
-        V[:, k] /= V[i, k]
+        a = np.abs(V[:, k])
+        i = int(np.nonzero(a >= (1.0 - 1e-8) * a.max())[0][0])
+        V[:, k] *= np.sign(V[i, k]) / a.max()
     return w, V
 
 
