@@ -74,7 +74,9 @@ class TFPS:
         if np.sum(c > 0) * 2 != N or np.sum(s > 0) * 2 != N:
             raise ValueError("half of the directions must point each way along x and along y")
         self.c, self.s = c, s
-        sA = D.sT - D.sS
+        # sigma_T - sigma_s of the cell in the scaled equation, taken as eps sigma_a (the
+        # difference of the two scaled coefficients cancels when eps is small)
+        sA = D.sA
         if np.any(sA <= 0):
             raise ValueError("TFPS needs sigma_T - sigma_s > 0 in every cell")
         self.sA = sA
