@@ -98,6 +98,19 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else None
 
 
+def host_cpu():
+    """(logical CPUs, model name) of the host."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
 def cpu_baseline(prob, blob, gpu_iters, budget_s):
     """The FP64 oracle on the host: a bounded run of FGMRES iterations, scaled to solves/s."""
     from oracle import solve as osolve
@@ -106,6 +119,7 @@ def cpu_baseline(prob, blob, gpu_iters, budget_s):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = 1
+    ncpu, model = host_cpu()
     P = osolve.Problem(prob, blob)
     t0 = time.perf_counter()
     P.precond(P.b.reshape(-1))          # one V-cycle to size the sample
@@ -124,7 +138,53 @@ def cpu_baseline(prob, blob, gpu_iters, budget_s):
         "sample": "%d MgNet-preconditioned FGMRES(30) iterations of the same workload in FP64 NumPy "
                   "(%.1f s, %.3f s/iteration), scaled by the GPU's %.0f iterations per solve"
                   % (st["iterations"], dt, s_per_iter, gpu_iters),
+        "host_cpus": ncpu, "cpu_model": model, "blas_threads": int(threads),
+        "threads_note": "the convolutions' tensor contractions run on the BLAS threads; the stencil, the "
+                        "elementwise network arithmetic and the Krylov loop run single-threaded in NumPy",
     }
+
+
+def oracle_c1(api, torch, configs, weights):
+    """The small workload as a full solve: the oracle (FP64 GMRES(20) with the FP64 V-cycle of a
+    2-level seeded MgNet, rtol 1e-8) timed on the host, and the GPU's BF16 path beside it."""
+    from oracle import solve as osolve
+    prob = configs.c1()
+    hdr, t = configs.problem_weights(prob)
+    blob = weights.pack_mgn1(hdr, t)
+    P = osolve.Problem(prob, blob)
+    t0 = time.perf_counter()
+    x, st = P.solve(rtol=1e-8, restart=20, max_iters=5000)
+    dt = time.perf_counter() - t0
+    model = api.Model(blob)
+    op = api.Operator(prob, model=model)
+    op.solve(model=model, precond="bf16", rtol=1e-8, restart=20)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    xg, sg = op.solve(model=model, precond="bf16", rtol=1e-8, restart=20)
+    torch.cuda.synchronize()
+    dg = time.perf_counter() - t1
+    err = float(np.linalg.norm(xg.cpu().numpy() - x.reshape(-1)) / np.linalg.norm(x))
+    return {"workload": "2D 32x32, 16 directions, g=0, eps=1, sigma_T 1 with a 10 inclusion, sigma_a 0.1, q=1 on "
+                        "the inclusion; 2-level seeded MgNet (16 channels); GMRES(20) to 1e-8",
+            "oracle_s": dt, "oracle_iterations": int(st["iterations"]), "oracle_converged": bool(st["converged"]),
+            "gpu_bf16_ms": dg * 1e3, "gpu_iterations": int(sg["iterations"]),
+            "gpu_vs_oracle_rel_error": err}
+
+
+def solution_errors(prob, blob, xs):
+    """Relative error of GPU solutions of one instance against the oracle's psi* (FP64 FGMRES with
+    the FP64 V-cycle of the same weights, rtol 1e-12); xs: {label: host array}."""
+    from oracle import solve as osolve
+    P = osolve.Problem(prob, blob)
+    t0 = time.perf_counter()
+    ref, st = P.solve(rtol=1e-12, restart=30, max_iters=400)
+    ref = ref.reshape(-1)
+    out = {"reference": "oracle psi* of GRF seed 2000, FP64 FGMRES(30) + FP64 V-cycle to rtol 1e-12 "
+                        "(%d iterations, %.1f s)" % (st["iterations"], time.perf_counter() - t0)}
+    for k, x in xs.items():
+        out[k] = {"rel_l2": float(np.linalg.norm(x - ref) / np.linalg.norm(ref)),
+                  "rel_max": float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))}
+    return out
 
 
 def serving_leg(args, api, torch, configs, weights):
@@ -134,6 +194,7 @@ def serving_leg(args, api, torch, configs, weights):
     models = {}
     used = {}
     ops = []
+    builds = []
     for p in reqs:
         N = p["dirs"].shape[0]
         if N not in models:
@@ -145,7 +206,9 @@ def serving_leg(args, api, torch, configs, weights):
                 hdr, t = configs.problem_weights(p)
                 models[N] = api.Model(weights.pack_mgn1(hdr, t))
                 used[N] = "seeded"
+        tb = time.perf_counter()
         ops.append(api.Operator(p, model=models[N]))
+        builds.append((time.perf_counter() - tb) * 1e3)
     outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
     kw = dict(restart=30, rtol=1e-6, max_iters=args.serving_max_iters, precond="bf16")
     srv = api.Server(arena_bytes=args.serving_arena_gb << 30, max_slots=args.serving_slots)
@@ -178,12 +241,17 @@ def serving_leg(args, api, torch, configs, weights):
     log("serving: Poisson arrivals at %.2f req/s" % rate)
     wall2, done2 = run(arr)
     lat = [d[0] * 1e3 for d in done2.values()]
+    lat_b = [d[0] * 1e3 + builds[i] for i, d in done2.items()]
     its = [d[2]["iterations"] for d in done2.values()]
     ok = sum(1 for d in done2.values() if d[1] == 0)
     q = srv.query()
     srv.close()
     return {"requests": len(ops), "slots": args.serving_slots, "saturated_solves_per_s": sat,
             "arrival_rate": rate, "completed_ok": ok, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "latency_note": "p50/p99: arrival to completion of the solve, operators built beforehand; "
+                            "with_build: plus that request's operator build (host FP64 setup, upload, CoeffNet)",
+            "build_ms": {"p50": percentile(builds, 50), "p99": percentile(builds, 99)},
+            "with_build_ms": {"p50": percentile(lat_b, 50), "p99": percentile(lat_b, 99)},
             "iterations_mean": float(np.mean(its)), "iterations_max": int(np.max(its)),
             "arena_peak_gb": q["arena_peak"] / 2 ** 30, "max_iters": args.serving_max_iters,
             "weights": {str(k): v for k, v in sorted(used.items())},
@@ -310,7 +378,10 @@ def main():
     seeded_blob = weights.pack_mgn1(hdr, t)
     blob = open(TRAINED, "rb").read() if args.weights == "trained" else seeded_blob
     model = api.Model(blob)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
     ops = [api.Operator(p, model=model) for p in probs]
+    build_ms = (time.perf_counter() - tb) * 1e3 / len(probs)
     kw = dict(restart=30, rtol=1e-6, max_iters=20000)
     outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for op in ops]
     srv = api.Server(arena_bytes=int(args.arena_gb * 2 ** 30), max_slots=args.batch)
@@ -334,6 +405,8 @@ def main():
             raise RuntimeError("a solve did not converge: %r" % (sts,))
         return sts
 
+    step_ms = []
+
     def run(mode, steps, prof_cls=None):
         if prof_cls is not None:
             api.prof_reset()
@@ -341,8 +414,11 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sts = []
+        step_ms.clear()
         for _ in range(steps):
+            ts = time.perf_counter()
             sts += batch(mode)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = None
@@ -356,6 +432,9 @@ def main():
         batch("bf16")
     log("timed: %d batches of %d BF16-path solves (events on kernel class %s)" % (args.steps, args.batch, args.prof))
     dt, sts, prof = run("bf16", args.steps, pc)
+    bf16_step_ms = list(step_ms)
+    conv_keys = api.prof_query_keys(L.K_CONV) if args.prof == "conv" else {}
+    x_bf16 = outs[0].cpu().numpy()
     nsolves = args.steps * args.batch
     value = nsolves / dt
     lat = [s["ms_total"] for s in sts]
@@ -387,31 +466,50 @@ def main():
         "rel_residual_max": float(max(s["rel_residual"] for s in sts)),
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
                        "note": "submission to completion inside a batch"},
+        "step_ms": {"median": percentile(bf16_step_ms, 50), "p99": percentile(bf16_step_ms, 99),
+                    "min": min(bf16_step_ms), "max": max(bf16_step_ms)},
+        "operator_build_ms_per_solve": build_ms,
+        "operator_build_note": "host FP64 setup, upload and CoeffNet per instance, outside the timed region",
     }
     if prof is not None:
         ms, launches, work, nbytes = prof
         avg_ms = ms / max(launches, 1)
         samp = "one Arnoldi step in %d run without its graph, every launch of the class in it timed" % args.prof_every
         if args.prof == "conv":
-            # the V-cycle convolutions at these channel counts (32 .. 256) do
-            # about 70 flop per algorithmic byte, below the MFMA ridge of
-            # 2500/8 = 312: HBM is the bound; MFMA use is reported beside it
+            # The convolutions are bound by the matrix cores where their channel count
+            # is 64 or more (3 of the 4 levels here): the headline is MFMA use against
+            # the dense BF16 peak.  Per output-channel count (one V-cycle level each for
+            # the smoothers) the achieved rates and the algorithmic intensity against the
+            # ridge 2500 / 8 = 312 flop/B say which bound each level meets.
             gbs = nbytes / (ms * 1e-3) / 1e9
             tflops = work / (ms * 1e-3) / 1e12
             traffic, traffic_alg = measured_traffic()
-            out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+            ridge = MFMA_PEAK_TFLOPS["bf16"] * 1e12 / (HBM_PEAK_GBS * 1e9)
+            levels = {}
+            for key, (kms, kn, kwork, kb) in sorted(conv_keys.items()):
+                t_k, g_k = kwork / (kms * 1e-3) / 1e12, kb / (kms * 1e-3) / 1e9
+                levels["cout_%d" % (1 << key)] = {
+                    "launches": kn, "avg_us": kms / kn * 1e3, "share_of_conv_time": kms / ms,
+                    "TFLOPs": t_k, "mfma_frac": t_k / MFMA_PEAK_TFLOPS["bf16"],
+                    "GBs_algorithmic": g_k, "hbm_frac": g_k / HBM_PEAK_GBS,
+                    "intensity_flop_per_byte": kwork / kb,
+                    "bound": "mfma" if kwork / kb >= ridge else "hbm"}
+            out["roofline"] = {"bound": "mfma", "achieved": tflops, "peak": MFMA_PEAK_TFLOPS["bf16"],
+                               "unit": "TFLOP/s", "frac": tflops / MFMA_PEAK_TFLOPS["bf16"],
+                               "traffic": traffic,
                                "traffic_unit": "HBM bytes per launch (counters, every launch of one batch)",
                                "traffic_over_algorithmic": (traffic / traffic_alg) if traffic else None,
                                "kernel": "conv_tile_kernel (3x3 stride-1/stride-2 and transposed 4x4 "
                                          "convolutions of the V-cycle, BF16 MFMA, all solves of the batch per launch)",
                                "timed_launches": launches, "sampling": samp,
                                "avg_launch_us": avg_ms * 1e3,
-                               "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
                                "flop_per_launch": work / max(launches, 1),
+                               "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
                                "intensity_flop_per_byte": work / max(nbytes, 1.0),
-                               "mfma": {"achieved": tflops, "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
-                                        "frac": tflops / MFMA_PEAK_TFLOPS["bf16"]}}
+                               "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": gbs / HBM_PEAK_GBS,
+                                       "bytes": "input, BF16 weights, output and FP32 epilogue tensors once"},
+                               "by_output_channels": levels}
         else:
             achieved = work / (ms * 1e-3) / 1e9
             out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -422,6 +520,7 @@ def main():
     if not args.no_fp32:
         log("timed: %d batches of FP32-path solves" % args.steps)
         dt32, sts32, _ = run("fp32", args.steps)
+        x_fp32 = outs[0].cpu().numpy()
         out["fp32_path"] = {"value": nsolves / dt32, "unit": "solves/s", "ms_per_step": dt32 / args.steps * 1e3,
                             "iterations_per_solve": float(np.mean([s["iterations"] for s in sts32])),
                             "latency_ms": {"p50": percentile([s["ms_total"] for s in sts32], 50),
@@ -482,6 +581,15 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu_baseline: oracle sample (~%.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(prob, blob, float(np.mean(its)), args.cpu_budget)
+        log("oracle: psi* of instance 0 for the solution error")
+        xs = {"bf16_path": x_bf16}
+        if not args.no_fp32:
+            xs["fp32_path"] = x_fp32
+        out["solution_error_vs_oracle"] = solution_errors(prob, blob, xs)
+        out["solution_error_vs_oracle"]["note"] = ("instance 0's solutions of the timed runs (rtol 1e-6) "
+                                                   "against the oracle's psi*")
+        log("oracle: the small workload as a full solve")
+        out["c1_full_solve"] = oracle_c1(api, torch, configs, weights)
     print(json.dumps(out), flush=True)
 
 

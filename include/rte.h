@@ -69,6 +69,28 @@ typedef struct rte_operator rte_operator;
 typedef struct mgnet_model mgnet_model;
 typedef struct rte_server rte_server;
 
+/* Spatial scheme of an operator.
+ * UPWIND: cell-centred first-order upwind finite volumes (the equation at the
+ *   top of this file); unknowns psi, direction-major [ndir][cells].
+ * TFPS: the tailored finite point scheme of Sec. 2.2 (2D only): in every cell
+ *   the exact exponential solutions of the cell's constant-coefficient
+ *   discrete-ordinates equation, eq. (2D_eigenfunc), 2 N of them with
+ *   eigenvectors normalised to max-norm 1 (sign: the first entry within 1e-8
+ *   of the largest magnitude is positive) in the order x-type decaying from
+ *   the left edge, x-type decaying from the right edge, y-type from the bottom,
+ *   y-type from the top, eigenvalue ascending within each group, plus the
+ *   constant particular solution eps q / (eps sigma_a).  Unknowns: the
+ *   coefficients, cell-major [cells][2 N].  Equations, cell-major [cells][2][N]:
+ *   for cell (i, j), row [0][m] is continuity of psi_m at the midpoint of its
+ *   left face, eq. (2DTFPS_continuity_cond), written psi(cell i-1) -
+ *   psi(cell i) = particular-solution jump (i >= 1), or for i = 0 the inflow
+ *   condition, eq. (2DTFPS_boundary_cond), of the x = 0 face (u_x > 0) or of
+ *   the x = 1 face of cell (I-1, j) (u_x < 0); row [1][m] the same along y.
+ *   Needs sigma_a > 0 in every cell, every direction with nonzero x and y
+ *   components, half of them positive along each axis, and no MgNet model
+ *   (the preconditioners of rte_solve that apply: RTE_PC_NONE). */
+enum { RTE_SCHEME_UPWIND = 0, RTE_SCHEME_TFPS = 1 };
+
 /* Angular and spatial discretisation (Sec. 2.1; Sec. 2.2 first paragraph). */
 typedef struct {
   int dim;                /* 2 or 3; domain [0,1]^dim                            */
@@ -78,6 +100,7 @@ typedef struct {
   const double* weights;  /* host [ndir], positive, summing to 1 (+-1e-12)        */
   double g;               /* HG anisotropy, |g| < 1                              */
   int kernel;             /* RTE_HG_*                                            */
+  int scheme;             /* RTE_SCHEME_* (0: upwind)                             */
 } rte_geometry;
 
 /* Per-cell medium (eq. (RTE): sigma_T, sigma_a, q, eps; Sec. 2.2 cell values).
@@ -104,6 +127,7 @@ typedef struct {
   int64_t cells, n;       /* n = ndir * cells                                    */
   double h, g;
   int has_fields;         /* CoeffNet fields were built for a model              */
+  int scheme;             /* RTE_SCHEME_*; n = 2 ndir cells for TFPS              */
 } rte_operator_info;
 
 /* Build the operator: validate inputs, form S, the scaled coefficients and
@@ -149,6 +173,13 @@ rte_status rte_apply(const rte_operator* op, const void* x, void* y, int precisi
 
 /* r = b - L x in FP64 (double [n] each; may not overlap).  Errors: RTE_EINVAL. */
 rte_status rte_residual(const rte_operator* op, const double* x, double* r, void* stream);
+
+/* psi_m at every cell centre from a solution x of the operator's system:
+ * device double [ndir][cells] (direction-major).  UPWIND: a copy of x.  TFPS:
+ * eq. (2DTFPS_sol) evaluated at the centres, sum_k x_k chi^k + the particular
+ * solution.  x (device double [n]) and psi must not overlap.  Errors:
+ * RTE_EINVAL. */
+rte_status rte_cell_values(const rte_operator* op, const double* x, double* psi, void* stream);
 
 /* z = M(v): one MgNet V-cycle (Sec. 3.3) with the operator's CoeffNet
  * fields (precond RTE_PC_MGNET_BF16 or RTE_PC_MGNET_FP32), or the
@@ -330,6 +361,13 @@ enum { RTE_K_APPLY = 0, RTE_K_RESIDUAL = 1, RTE_K_CONV = 2, RTE_K_ORTH = 3,
 rte_status rte_prof_enable(int kernel_class, int every);
 rte_status rte_prof_query(int kernel_class, double* total_ms, int64_t* launches, double* work,
                           double* bytes);
+/* The same sums restricted to the launches of one key: for RTE_K_CONV the key
+ * is floor(log2(output channels)) of the convolution (so the levels of a
+ * V-cycle separate: C_l = C_0 2^l), for every other class 0.  Errors:
+ * RTE_EINVAL (class or key out of range). */
+#define RTE_PROF_KEYS 16
+rte_status rte_prof_query_key(int kernel_class, int key, double* total_ms, int64_t* launches, double* work,
+                              double* bytes);
 rte_status rte_prof_reset(void);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -10,6 +10,7 @@ RTE_EBREAKDOWN, RTE_EAGAIN, RTE_EFORMAT, RTE_ENOTFOUND = -5, -6, -7, -8
 STATUS_NAMES = {0: "RTE_OK", -1: "RTE_EINVAL", -2: "RTE_ENOMEM", -3: "RTE_EDEVICE", -4: "RTE_ENOCONV",
                 -5: "RTE_EBREAKDOWN", -6: "RTE_EAGAIN", -7: "RTE_EFORMAT", -8: "RTE_ENOTFOUND"}
 HG_AUTO, HG_FLATLAND, HG_SPHERE = 0, 1, 2
+SCHEME_UPWIND, SCHEME_TFPS = 0, 1
 FP32, FP64 = 0, 1
 PC_NONE, PC_MGNET_BF16, PC_MGNET_FP32, PC_BLOCK_JACOBI = 0, 1, 2, 3
 ARR_RHS, ARR_SCATTER, ARR_SIGMA, ARR_FIELD_A, ARR_FIELD_AINV = 0, 1, 2, 3, 4
@@ -27,7 +28,7 @@ class RteError(RuntimeError):
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("ndir", C.c_int),
                 ("dirs", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
-                ("g", C.c_double), ("kernel", C.c_int)]
+                ("g", C.c_double), ("kernel", C.c_int), ("scheme", C.c_int)]
 
 
 class Medium(C.Structure):
@@ -40,7 +41,7 @@ class Medium(C.Structure):
 class OperatorInfo(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("ndir", C.c_int), ("kernel", C.c_int), ("cells", C.c_int64), ("n", C.c_int64),
-                ("h", C.c_double), ("g", C.c_double), ("has_fields", C.c_int)]
+                ("h", C.c_double), ("g", C.c_double), ("has_fields", C.c_int), ("scheme", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -73,6 +74,7 @@ _SIGS = {
     "mgnet_describe": [_P, C.POINTER(C.c_int)],
     "rte_apply": [_P, _P, _P, C.c_int, _P],
     "rte_residual": [_P, _P, _P, _P],
+    "rte_cell_values": [_P, _P, _P, _P],
     "rte_precond_workspace_bytes": [_P, _P, C.POINTER(C.c_size_t)],
     "rte_precond_apply": [_P, _P, C.c_int, _P, _P, _P, C.c_size_t, _P],
     "rte_precond_apply_noalloc": [_P, _P, C.c_int, _P, _P, _P],
@@ -90,6 +92,8 @@ _SIGS = {
     "rte_prof_enable": [C.c_int, C.c_int],
     "rte_prof_query": [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                        C.POINTER(C.c_double)],
+    "rte_prof_query_key": [C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                           C.POINTER(C.c_double)],
     "rte_prof_reset": [],
 }
 

@@ -85,6 +85,7 @@ class Operator:
         g.weights = _ptr(w)
         g.g = float(prob["g"])
         g.kernel = _KERNEL[prob.get("kernel", "auto")]
+        g.scheme = {"upwind": L.SCHEME_UPWIND, "tfps": L.SCHEME_TFPS}[prob.get("scheme", "upwind")]
         m = L.Medium()
         m.sigma_t, m.sigma_a, m.q = _ptr(st), _ptr(sa), _ptr(q)
         m.eps = _ptr(eps_arr) if eps_arr is not None else None
@@ -146,6 +147,14 @@ class Operator:
             y = torch.empty_like(x)
         check(lib().rte_apply(self._h, _dptr(x), _dptr(y), prec, _stream(stream)))
         return y
+
+    def cell_values(self, x, psi=None, stream=None):
+        """psi at the cell centres, [ndir][cells] FP64 (rte_cell_values)."""
+        torch = _torch()
+        if psi is None:
+            psi = torch.empty(self.ndir * self.cells, dtype=torch.float64, device="cuda")
+        check(lib().rte_cell_values(self._h, _dptr(x), _dptr(psi), _stream(stream)))
+        return psi
 
     def residual(self, x, r=None, stream=None):
         torch = _torch()
@@ -298,6 +307,21 @@ def prof_query(cls):
     nbytes = C.c_double()
     check(lib().rte_prof_query(int(cls), C.byref(ms), C.byref(cnt), C.byref(work), C.byref(nbytes)))
     return ms.value, cnt.value, work.value, nbytes.value
+
+
+def prof_query_keys(cls):
+    """{key: (total ms, timed launches, work, bytes)} for every key with timed launches
+    (for convolutions the key is floor(log2(output channels)))."""
+    out = {}
+    for key in range(16):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        work = C.c_double()
+        nbytes = C.c_double()
+        check(lib().rte_prof_query_key(int(cls), key, C.byref(ms), C.byref(cnt), C.byref(work), C.byref(nbytes)))
+        if cnt.value:
+            out[key] = (ms.value, cnt.value, work.value, nbytes.value)
+    return out
 
 
 def prof_reset():

@@ -29,6 +29,7 @@ struct Prof {
     hipEvent_t e0, e1;
     double work, bytes;
     std::shared_ptr<double> scale;  // null: 1; negative: not known yet
+    int key;
   };
   std::vector<Rec> pending[RTE_K_COUNT];
   std::vector<hipEvent_t> pool;
@@ -36,6 +37,11 @@ struct Prof {
   double work[RTE_K_COUNT] = {};
   double bytes[RTE_K_COUNT] = {};
   int64_t count[RTE_K_COUNT] = {};
+  // the same sums split by the launch's key (RTE_PROF_KEYS of them per class)
+  double kms[RTE_K_COUNT][RTE_PROF_KEYS] = {};
+  double kwork[RTE_K_COUNT][RTE_PROF_KEYS] = {};
+  double kbytes[RTE_K_COUNT][RTE_PROF_KEYS] = {};
+  int64_t kcount[RTE_K_COUNT][RTE_PROF_KEYS] = {};
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -62,6 +68,11 @@ struct Prof {
       work[c] += pr.work * sc;
       bytes[c] += pr.bytes * sc;
       count[c] += 1;
+      const int k = pr.key;
+      kms[c][k] += t;
+      kwork[c][k] += pr.work * sc;
+      kbytes[c][k] += pr.bytes * sc;
+      kcount[c][k] += 1;
       pool.push_back(pr.e0);
       pool.push_back(pr.e1);
     }
@@ -119,7 +130,8 @@ ProfScope::~ProfScope() {
   std::lock_guard<std::mutex> lk(P.mu);
   try {
     if (!ext) (void)hipEventRecord(e1, s);
-    P.pending[cls].push_back({e0, e1, work, bytes < 0 ? work : bytes, prof_scale()});
+    const int k = key >= 0 && key < RTE_PROF_KEYS ? key : 0;
+    P.pending[cls].push_back({e0, e1, work, bytes < 0 ? work : bytes, prof_scale(), k});
     if (P.pending[cls].size() >= 65536) P.drain(cls);
   } catch (...) {
   }
@@ -208,6 +220,7 @@ rte_status rte_operator_get_info(const rte_operator* h, rte_operator_info* info)
     info->dim = o.dim; info->nx = o.nx; info->ny = o.ny; info->nz = o.nz; info->ndir = o.ndir;
     info->kernel = o.kernel; info->cells = o.cells; info->n = o.n; info->h = o.h; info->g = o.g;
     info->has_fields = o.model != nullptr;
+    info->scheme = o.scheme;
   });
 }
 
@@ -251,7 +264,7 @@ rte_status rte_apply(const rte_operator* h, const void* x, void* y, int precisio
     RTE_REQUIRE(x != y, RTE_EINVAL, "rte_apply: x and y must not alias");
     RTE_REQUIRE(precision == RTE_FP32 || precision == RTE_FP64, RTE_EINVAL, "rte_apply: bad precision");
     const int t = precision == RTE_FP64 ? 1 : 0;
-    launch_apply(Target::single(*h->op), x, t, y, t, nullptr, precision == RTE_FP64, S(stream));
+    launch_operator(Target::single(*h->op), x, t, y, t, nullptr, precision == RTE_FP64, S(stream));
   });
 }
 
@@ -260,7 +273,20 @@ rte_status rte_residual(const rte_operator* h, const double* x, double* r, void*
     RTE_REQUIRE(h && x && r, RTE_EINVAL, "rte_residual: null argument");
     RTE_REQUIRE(static_cast<const void*>(x) != static_cast<const void*>(r), RTE_EINVAL,
                 "rte_residual: x and r must not alias");
-    launch_apply(Target::single(*h->op), x, 1, r, 1, h->op->a.b64, true, S(stream));
+    launch_operator(Target::single(*h->op), x, 1, r, 1, h->op->a.b64, true, S(stream));
+  });
+}
+
+rte_status rte_cell_values(const rte_operator* h, const double* x, double* psi, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(h && x && psi, RTE_EINVAL, "rte_cell_values: null argument");
+    RTE_REQUIRE(static_cast<const void*>(x) != static_cast<const void*>(psi), RTE_EINVAL,
+                "rte_cell_values: x and psi must not alias");
+    const Operator& o = *h->op;
+    if (o.scheme == RTE_SCHEME_TFPS)
+      launch_tfps_centres(Target::single(o), x, psi, S(stream));
+    else
+      RTE_HIP(hipMemcpyAsync(psi, x, size_t(o.n) * 8, hipMemcpyDeviceToDevice, S(stream)));
   });
 }
 
@@ -276,6 +302,7 @@ rte_status rte_precond_apply(const rte_operator* h, const mgnet_model* model, in
   return guarded([&] {
     RTE_REQUIRE(h && v && z, RTE_EINVAL, "rte_precond_apply: null argument");
     const Operator& o = *h->op;
+    RTE_REQUIRE(o.scheme == RTE_SCHEME_UPWIND, RTE_EINVAL, "the preconditioners act on the upwind scheme");
     if (precond == RTE_PC_BLOCK_JACOBI) {
       RTE_REQUIRE(o.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
       launch_block_jacobi(Target::single(o), v, nullptr, z, S(stream));
@@ -438,6 +465,20 @@ rte_status rte_prof_query(int c, double* total_ms, int64_t* launches, double* wo
   });
 }
 
+rte_status rte_prof_query_key(int c, int key, double* total_ms, int64_t* launches, double* work, double* bytes) {
+  return guarded([&] {
+    RTE_REQUIRE(c >= 0 && c < RTE_K_COUNT, RTE_EINVAL, "unknown kernel class");
+    RTE_REQUIRE(key >= 0 && key < RTE_PROF_KEYS, RTE_EINVAL, "key out of range");
+    Prof& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.drain(c);
+    if (total_ms) *total_ms = P.kms[c][key];
+    if (launches) *launches = P.kcount[c][key];
+    if (work) *work = P.kwork[c][key];
+    if (bytes) *bytes = P.kbytes[c][key];
+  });
+}
+
 rte_status rte_prof_reset(void) {
   return guarded([&] {
     Prof& P = prof();
@@ -448,6 +489,12 @@ rte_status rte_prof_reset(void) {
       P.work[c] = 0;
       P.bytes[c] = 0;
       P.count[c] = 0;
+      for (int k = 0; k < RTE_PROF_KEYS; ++k) {
+        P.kms[c][k] = 0;
+        P.kwork[c][k] = 0;
+        P.kbytes[c][k] = 0;
+        P.kcount[c][k] = 0;
+      }
     }
   });
 }

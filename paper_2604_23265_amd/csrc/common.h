@@ -230,10 +230,19 @@ struct OpArrays {
   float* Sp32 = nullptr;      // S by direction slot: [4][N][slot_budget(N)], entry (s, n, q) = S_{s+4q, n}
   float* fa[MAX_LEVELS] = {};     // CoeffNet fields per level [cells_l][C_l]
   float* fainv[MAX_LEVELS] = {};
+  // TFPS (Sec. 2.2): per cell the index of its eigen-basis and its particular
+  // solution; tf_tab holds the device addresses of the basis tables (kept
+  // outside the block so that its layout depends on the shape only):
+  // tf_tab[0] -> L^T [nbasis][2N][N] FP64, tf_tab[1] -> xi [nbasis][2N] FP64
+  int* tf_bid = nullptr;
+  double* tf_chis = nullptr;
+  uint64_t* tf_tab = nullptr;
 };
 
 struct Operator {
   int dim = 2, nx = 0, ny = 0, nz = 1, ndir = 0, kernel = 0;
+  int scheme = RTE_SCHEME_UPWIND;
+  int nbasis = 0;                   // TFPS: distinct eigen-bases
   int64_t cells = 0, n = 0;
   double h = 0, g = 0;
   int device = 0;
@@ -307,6 +316,27 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s);
 void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride);
 void convT4_setup(ConvLaunch& c, int dim, const int in_dim[3]);
 
+// The operator of either scheme: launch_apply for the upwind one, the TFPS
+// apply for the other (same argument meaning).
+void launch_operator(const Target& T, const void* x, int tin, void* y, int tout, const double* b, bool fp64,
+                     hipStream_t s);
+// TFPS (Sec. 2.2): y = A x (b null) or y = b - A x, computed in FP64; x, y
+// FP32 (0) or FP64 (1); under a slot table x, y and b are workspace-relative.
+void launch_tfps_apply(const Target& T, const void* x, int tin, void* y, int tout, const double* b,
+                       hipStream_t s);
+// psi at the cell centres, [N][cells] FP64, from the coefficients x
+void launch_tfps_centres(const Target& T, const double* x, double* psi, hipStream_t s);
+// host: the TFPS bases, tables and right-hand side of an operator whose
+// scalar fields (grid, directions, S) are set
+struct TfpsHost {
+  std::vector<double> Lt, xi, chis, b;
+  std::vector<int> bid;
+  int nbasis = 0;
+};
+TfpsHost tfps_build_host(const Operator& op, const std::vector<double>& dirs, const std::vector<double>& w,
+                         const std::vector<double>& sT, const std::vector<double>& sA,
+                         const std::vector<double>& qh, const double* inflow, size_t fstride);
+
 // vscale (nullable, workspace-relative under a slot table): v is taken times
 // vscale[0]
 void launch_lift(const Target& T, const Model& m, const double* v, const double* vscale, float* f0,
@@ -374,6 +404,7 @@ struct ProfScope {
   hipStream_t s;
   double work = 0;   // algorithmic FLOPs (or bytes) of the enclosed launch
   double bytes = -1; // algorithmic bytes; < 0 means equal to work
+  int key = 0;       // sub-class of the launch (conv: log2 of the output channels)
   bool ext;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   ProfScope(int cls, hipStream_t s, bool ext = false);

@@ -1517,6 +1517,8 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
                       (ksplit ? true : (gxv >= 64 ? gxv % 64 == 0 : (64 % gxv == 0 && gyv % (64 / gxv) == 0)));
   ProfScope ps(RTE_K_CONV, s, true);
   ps.work = 2.0 * double(gm) * c.cout * double(c.cin) * c.ntap * c.nclass;
+  ps.key = 0;
+  while ((2 << ps.key) <= c.cout && ps.key + 1 < RTE_PROF_KEYS) ++ps.key;  // floor(log2(cout))
   {
     // algorithmic bytes: input tensor, weights, output and epilogue tensors once
     const double in_el = double(c.in_dim[0]) * c.in_dim[1] * c.in_dim[2] * c.cin;

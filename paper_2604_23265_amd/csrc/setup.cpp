@@ -20,7 +20,7 @@ int Operator::level_dim(int l, int axis) const {
 }
 
 std::vector<int64_t> Operator::shape_key() const {
-  return {dim, nx, ny, nz, ndir, levels, c0};
+  return {dim, nx, ny, nz, ndir, levels, c0, scheme};
 }
 
 std::unique_ptr<Operator> Operator::geometry() const {
@@ -39,6 +39,8 @@ std::unique_ptr<Operator> Operator::geometry() const {
   o->model = model;
   o->levels = levels;
   o->c0 = c0;
+  o->scheme = scheme;
+  o->nbasis = nbasis;
   return o;
 }
 
@@ -61,6 +63,9 @@ OpArrays Operator::relative() const {
     r.fa[l] = rel(a.fa[l]);
     r.fainv[l] = rel(a.fainv[l]);
   }
+  r.tf_bid = rel(a.tf_bid);
+  r.tf_chis = rel(a.tf_chis);
+  r.tf_tab = rel(a.tf_tab);
   return r;
 }
 
@@ -201,6 +206,13 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
     RTE_REQUIRE(st / e - e * sa >= 0, RTE_EINVAL,
                 "sigma_t/eps - eps*sigma_a < 0 at cell " + std::to_string(c) + " (negative scattering)");
   }
+  RTE_REQUIRE(g->scheme == RTE_SCHEME_UPWIND || g->scheme == RTE_SCHEME_TFPS, RTE_EINVAL, "unknown scheme");
+  const bool tfps = g->scheme == RTE_SCHEME_TFPS;
+  if (tfps) {
+    RTE_REQUIRE(dim == 2, RTE_EINVAL, "the TFPS operator is two-dimensional");
+    RTE_REQUIRE(model == nullptr, RTE_EINVAL, "MgNet preconditions the upwind scheme; build TFPS without a model");
+    RTE_REQUIRE(int64_t(2) * N * cells <= (int64_t(1) << 31) - 1, RTE_EINVAL, "problem too large (n >= 2^31)");
+  }
   if (model) {
     RTE_REQUIRE(model->dim == dim && model->ndir == N, RTE_EINVAL, "model does not match the geometry");
     int div = 1 << (model->levels - 1);
@@ -211,7 +223,8 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
   Operator* op = new Operator();
   try {
     op->dim = dim; op->nx = nx; op->ny = ny; op->nz = nz; op->ndir = N; op->kernel = kind;
-    op->cells = cells; op->n = int64_t(N) * cells; op->h = 1.0 / nx; op->g = g->g;
+    op->cells = cells; op->n = int64_t(tfps ? 2 : 1) * N * cells; op->h = 1.0 / nx; op->g = g->g;
+    op->scheme = g->scheme;
     RTE_HIP(hipGetDevice(&op->device));
     op->S = scattering_matrix(hg_values(dirs, N, g->g, kind), w, N);
 
@@ -234,14 +247,25 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
       dc[4 * m + 3] = sum;
     }
     // right-hand side: eps q plus the inflow flux through boundary faces
-    std::vector<double> b(size_t(op->n));
-    for (int m = 0; m < N; ++m)
-      for (int64_t c = 0; c < cells; ++c) b[size_t(m) * cells + c] = eps[c] * md->q[c];
-    if (md->inflow) {
-      size_t fstride = md->inflow_face_stride;
-      if (fstride == 0) fstride = size_t(std::max({int64_t(ny) * nz, int64_t(nx) * nz, dim == 3 ? int64_t(nx) * ny : 0}));
+    size_t fstride = md->inflow_face_stride;
+    if (fstride == 0) fstride = size_t(std::max({int64_t(ny) * nz, int64_t(nx) * nz, dim == 3 ? int64_t(nx) * ny : 0}));
+    if (md->inflow)
       RTE_REQUIRE(finite_all(md->inflow, int64_t(2 * dim) * N * int64_t(fstride)), RTE_EINVAL,
                   "non-finite inflow value");
+    TfpsHost TF;
+    std::vector<double> b;
+    if (tfps) {
+      std::vector<double> qh(cells);
+      for (int64_t c = 0; c < cells; ++c) qh[c] = eps[c] * md->q[c];
+      TF = tfps_build_host(*op, dirs, w, sT, sA, qh, md->inflow, fstride);
+      op->nbasis = TF.nbasis;
+      b.swap(TF.b);
+    } else {
+      b.assign(size_t(op->n), 0.0);
+      for (int m = 0; m < N; ++m)
+        for (int64_t c = 0; c < cells; ++c) b[size_t(m) * cells + c] = eps[c] * md->q[c];
+    }
+    if (md->inflow && !tfps) {
       for (int m = 0; m < N; ++m)
         for (int a = 0; a < dim; ++a) {
           int sgn = sg[4 * m + a];
@@ -300,6 +324,12 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
       o_fa[l] = take(bytes);
       o_fi[l] = take(bytes);
     }
+    size_t o_bid = 0, o_chis = 0, o_tab = 0;
+    if (tfps) {
+      o_bid = take(size_t(cells) * 4);
+      o_chis = take(size_t(cells) * 8);
+      o_tab = take(16);
+    }
     op->block_bytes = off;
     op->block = op->mem.alloc<char>(off);
     char* B = op->block;
@@ -322,6 +352,16 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
     for (int l = 0; l < op->levels; ++l) {
       op->a.fa[l] = reinterpret_cast<float*>(B + o_fa[l]);
       op->a.fainv[l] = reinterpret_cast<float*>(B + o_fi[l]);
+    }
+    if (tfps) {
+      // the basis tables live outside the block (their size depends on the medium);
+      // the block holds their addresses
+      const double* dL = op->mem.upload(TF.Lt);
+      const double* dxi = op->mem.upload(TF.xi);
+      const uint64_t tabs[2] = {reinterpret_cast<uint64_t>(dL), reinterpret_cast<uint64_t>(dxi)};
+      op->a.tf_bid = reinterpret_cast<int*>(put(o_bid, TF.bid.data(), TF.bid.size() * 4));
+      op->a.tf_chis = reinterpret_cast<double*>(put(o_chis, TF.chis.data(), TF.chis.size() * 8));
+      op->a.tf_tab = reinterpret_cast<uint64_t*>(put(o_tab, tabs, sizeof(tabs)));
     }
     if (model) {
       const_cast<Model*>(model)->ensure_on_device();

@@ -282,6 +282,9 @@ void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o) 
   RTE_REQUIRE(o->max_iters >= 1, RTE_EINVAL, "max_iters must be >= 1");
   RTE_REQUIRE(o->precond >= RTE_PC_NONE && o->precond <= RTE_PC_BLOCK_JACOBI, RTE_EINVAL,
               "unknown preconditioner");
+  if (op.scheme == RTE_SCHEME_TFPS)
+    RTE_REQUIRE(o->precond == RTE_PC_NONE, RTE_EINVAL,
+                "the TFPS operator is solved without a preconditioner (MgNet and Block-Jacobi act on the upwind scheme)");
   if (o->precond == RTE_PC_BLOCK_JACOBI)
     RTE_REQUIRE(op.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
   if (o->precond == RTE_PC_MGNET_BF16 || o->precond == RTE_PC_MGNET_FP32) {
@@ -455,7 +458,7 @@ void Batch::boundary_launches(int zc) {
   launch_dots(so, b, n, 1, b, n, partn, nb, s_);
   launch_start_cycle(so, partn, nb, nullptr, k, stat, s_);
   launch_copy_f64(so, stat + 4, off<double>(q.bn), 1, s_);
-  launch_apply(T, x, 1, V, 1, b, true, s_);
+  launch_operator(T, x, 1, V, 1, b, true, s_);
   launch_dots(so, V, n, 1, V, n, partn, nb, s_);
   launch_start_cycle(so, partn, nb, off<double>(q.g), k, stat, s_);
   launch_decide(so, stat, off<double>(q.bn), k, s_);
@@ -499,7 +502,7 @@ void Batch::step_body(int jmax, int zc, hipStream_t s) {
     launch_block_jacobi(Tvz, V, stat + 5, Z, s);
   else
     launch_cast_f64_f32(vz, V, stat + 5, Z, n, s);
-  launch_apply(Tzv, Z, 0, V + ldv, 1, nullptr, false, s);
+  launch_operator(Tzv, Z, 0, V + ldv, 1, nullptr, false, s);
   launch_finish_dots(sl, V, ldv, jmax, h2, stat + 3, n, part1, nb, s);
   launch_reduce(sl, part1, nb, jmax + 1, h1, s);
   launch_updots(sl, V, ldv, jmax, h1, n, part2, nb, s);
