@@ -434,6 +434,7 @@ def main():
     dt, sts, prof = run("bf16", args.steps, pc)
     bf16_step_ms = list(step_ms)
     conv_keys = api.prof_query_keys(L.K_CONV) if args.prof == "conv" else {}
+    orth_keys = api.prof_query_keys(L.K_ORTH) if args.prof == "orth" else {}
     x_bf16 = outs[0].cpu().numpy()
     nsolves = args.steps * args.batch
     value = nsolves / dt
@@ -517,6 +518,15 @@ def main():
                                "timed_launches": launches, "sampling": samp,
                                "avg_launch_us": avg_ms * 1e3,
                                "work_per_launch": work / max(launches, 1), "work_unit": "byte"}
+            if orth_keys:
+                names = {1: "dots", 2: "reduce", 3: "finish_dots (CGS2 pass 1)", 4: "updots (CGS2 pass 2)",
+                         5: "finish (Givens)"}
+                out["roofline"]["by_kernel"] = {
+                    names.get(k, str(k)): {"launches": kn, "avg_us": kms / kn * 1e3,
+                                           "algorithmic_bytes_per_launch": kb / kn,
+                                           "GBs_algorithmic": kb / (kms * 1e-3) / 1e9,
+                                           "hbm_frac": kb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                    for k, (kms, kn, kwork, kb) in sorted(orth_keys.items())}
     if not args.no_fp32:
         log("timed: %d batches of FP32-path solves" % args.steps)
         dt32, sts32, _ = run("fp32", args.steps)

@@ -363,8 +363,10 @@ rte_status rte_prof_query(int kernel_class, double* total_ms, int64_t* launches,
                           double* bytes);
 /* The same sums restricted to the launches of one key: for RTE_K_CONV the key
  * is floor(log2(output channels)) of the convolution (so the levels of a
- * V-cycle separate: C_l = C_0 2^l), for every other class 0.  Errors:
- * RTE_EINVAL (class or key out of range). */
+ * V-cycle separate: C_l = C_0 2^l); for RTE_K_ORTH 1 = boundary dot products,
+ * 2 = their second reduction stage, 3 = the lagged-CGS2 first pass (completes
+ * V_j, forms V^T w), 4 = the second pass (w -= V h, V^T w), 5 = the Givens step;
+ * for every other class 0.  Errors: RTE_EINVAL (class or key out of range). */
 #define RTE_PROF_KEYS 16
 rte_status rte_prof_query_key(int kernel_class, int key, double* total_ms, int64_t* launches, double* work,
                               double* bytes);

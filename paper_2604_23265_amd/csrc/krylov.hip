@@ -533,6 +533,7 @@ void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const do
                  int nblk, hipStream_t s) {
   RTE_REQUIRE(nv >= 1 && nv <= 64, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
+  ps.key = 1;
   ps.work = 8.0 * double(n) * (nv + 1);
   const dim3 g = z3(unsigned(nblk), sl);
   if (nv <= 8) dots_go<8>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
@@ -544,6 +545,7 @@ void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const do
 
 void launch_reduce(const Slots& sl, const double* part, int nblk, int nv, double* out, hipStream_t s) {
   ProfScope ps(RTE_K_ORTH, s, true);
+  ps.key = 2;
   launch_k(reduce_kernel, z3(unsigned(nv), sl), dim3(KT), 0, s, ps, sl, part, nblk, out);
   RTE_HIP(hipGetLastError());
 }
@@ -561,6 +563,7 @@ void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int jmax, const
   RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the Arnoldi step kernels run under a slot table");
   RTE_REQUIRE(jmax >= 0 && jmax <= 63, RTE_EINVAL, "too many basis vectors");
   ProfScope ps(RTE_K_ORTH, s, true);
+  ps.key = 3;
   ps.work = 8.0 * double(n) * (jmax + 3);  // V_0..V_{j-1}, V_j read and written, w (j at its bound)
   const dim3 g = z3(unsigned(nblk), sl);
   if (jmax <= 8) fdots_go<8>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
@@ -576,6 +579,7 @@ void launch_updots(const Slots& sl, const double* V, int64_t ldv, int jmax, cons
   RTE_REQUIRE(jmax >= 0 && jmax <= 63, RTE_EINVAL, "too many basis vectors");
   const int nv = jmax + 1;
   ProfScope ps(RTE_K_ORTH, s, true);
+  ps.key = 4;
   ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once (j at its bound)
   const dim3 g = z3(unsigned(nblk), sl);
   if (nv <= 8) updots_go<8>(g, s, ps, sl, V, ldv, h, n, part, nblk);
@@ -589,6 +593,7 @@ void launch_finish_step(const Slots& sl, const double* h1, const double* h2, int
                         double* cs, double* sn, double* g, const double* bnorm, double* stat, hipStream_t s) {
   RTE_REQUIRE(sl.tab != nullptr, RTE_EINVAL, "the Arnoldi step kernels run under a slot table");
   ProfScope ps(RTE_K_ORTH, s, true);
+  ps.key = 5;
   launch_k(finish_kernel, z3(1, sl), dim3(64), 0, s, ps, sl, h1, h2, k, jmax, H, cs, sn, g, bnorm, stat);
   RTE_HIP(hipGetLastError());
 }

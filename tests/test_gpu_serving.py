@@ -256,3 +256,42 @@ def test_operator_freed_while_its_batch_serves_others():
         assert done[t][0] == 0
         assert bool((out == a).all()), "a request served after the first operator was freed differs"
     assert bool((outs[0] == alone[0]).all())
+
+
+def test_stream_slice_alone_equals_mix_at_full_sizes():
+    """Twelve requests of the serving stream itself (grids 64^2..256^2, 16 and 32 directions,
+    log-uniform eps, trained weights per direction count) solved alone through rte_solve and
+    then through the server with staggered arrivals at 8 slots: every result, iteration and
+    restart count must be bitwise the same, and the FP64 residual the oracle computes for a
+    served result must meet the tolerance."""
+    import os
+    torch = torch_cuda()
+    from paper_2604_23265_amd import api
+    reqs = [configs.c3_request(r) for r in range(12)]
+    say("case stream slice:", [(p["n"][0], p["dirs"].shape[0]) for p in reqs])
+    wdir = os.path.join(os.path.dirname(api.__file__), "weights")
+    models = {N: api.Model(open(os.path.join(wdir, "c3_n%d.mgn1" % N), "rb").read()) for N in (16, 32)}
+    ops = [api.Operator(p, model=models[p["dirs"].shape[0]]) for p in reqs]
+    kw = dict(restart=30, rtol=1e-6, max_iters=3000, precond="bf16")
+    alone, stats = [], []
+    for op in ops:
+        x, st = op.solve(model=op.model, **kw)
+        alone.append(x.clone())
+        stats.append(st)
+    say("  alone iterations", [s["iterations"] for s in stats])
+    srv = api.Server(arena_bytes=4 << 30, max_slots=8)
+    outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+    tickets = [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops[:7], outs[:7])]
+    time.sleep(0.02)
+    tickets += [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops[7:], outs[7:])]
+    done = _wait(srv, tickets, timeout=300.0)
+    srv.close()
+    for i, t in enumerate(tickets):
+        code, st = done[t]
+        assert code == stats[i]["status"]
+        assert st["iterations"] == stats[i]["iterations"] and st["restarts"] == stats[i]["restarts"]
+        assert bool((outs[i] == alone[i]).all()), "request %d differs between alone and in the mix" % i
+    P = osolve.Problem(reqs[0])
+    res = osolve.relative_residual(P, host(outs[0]))
+    say("  oracle FP64 residual of request 0:", res)
+    assert stats[0]["converged"] == 1 and res <= 1e-6 * 1.001
