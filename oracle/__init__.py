@@ -13,6 +13,8 @@ Modules
   solve           end-to-end build + FGMRES driver
   direct          independent solvers used only to pin the rest (dense LU,
                   transport sweeps, source iteration, the isotropic limit)
+  atfps           the adaptive scheme of Sec. 2.3: selection, face bases,
+                  compressed system, layer reconstruction, the filtered loss
   tfps            the tailored finite point scheme of Sec. 2.2 (2D): per-cell
                   eigen-bases, midpoint continuity and inflow conditions, the
                   assembled system and its sparse solve
@@ -20,4 +22,4 @@ Modules
 Functions whose result is not pinned by any test say "parity unpinned" in
 their docstring.
 """
-from . import direct, discretisation, krylov, network, solve, tfps  # noqa: F401
+from . import atfps, direct, discretisation, krylov, network, solve, tfps  # noqa: F401
