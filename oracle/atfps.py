@@ -10,7 +10,9 @@ functions centred at the left, right, bottom and top face of the cell, N/2 each)
    functions.
 2. Interface bases: for each face, the functions centred on it (from the one or two cells
    that share it).  The kept ones' eigenvectors are orthonormalised by a QR factorisation;
-   the dropped ones' eigenvectors follow as they are; every vector is scaled to max-norm 1.
+   the dropped ones' eigenvectors follow as they are; every vector is scaled to max-norm 1
+   (reading: the orthonormalised ones with the sign rule of the eigenvectors, since the QR
+   factors are unique only up to column signs).
    On a boundary face only the incoming directions enter.  P^k is the coefficient of a
    vector on the k-th vector of that basis.
 3. Compressed system, eq. (2DAdaptiveTFPS_linear_sys): unknowns are the kept coefficients;
@@ -49,6 +51,17 @@ def _centred_on(k, N):
 def _maxnorm(V):
     big = np.max(np.abs(V), axis=0)
     return V / big[None, :]
+
+
+def _maxnorm_signed(V):
+    """Columns scaled to max-norm 1, each with its first entry within 1e-8 of the largest
+    magnitude positive (the QR factors are unique up to the signs of their columns)."""
+    out = np.array(V, float)
+    for k in range(out.shape[1]):
+        a = np.abs(out[:, k])
+        i = int(np.nonzero(a >= (1.0 - 1e-8) * a.max())[0][0])
+        out[:, k] *= np.sign(out[i, k]) / a.max()
+    return out
 
 
 class ATFPS:
@@ -100,7 +113,7 @@ class ATFPS:
         Ld = np.array([T.L[c][rows, k] for c, k in dropped]).T.reshape(len(rows), len(dropped))
         if len(kept):
             Q, _ = np.linalg.qr(Lk)
-            Q = _maxnorm(Q)
+            Q = _maxnorm_signed(Q)
         else:
             Q = np.zeros((len(rows), 0))
         H = np.concatenate([Q, _maxnorm(Ld) if len(dropped) else Ld], axis=1)
