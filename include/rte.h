@@ -68,6 +68,7 @@ enum { RTE_PC_NONE = 0, RTE_PC_MGNET_BF16 = 1, RTE_PC_MGNET_FP32 = 2, RTE_PC_BLO
 typedef struct rte_operator rte_operator;
 typedef struct mgnet_model mgnet_model;
 typedef struct rte_server rte_server;
+typedef struct rte_atfps rte_atfps;
 
 /* Spatial scheme of an operator.
  * UPWIND: cell-centred first-order upwind finite volumes (the equation at the
@@ -180,6 +181,52 @@ rte_status rte_residual(const rte_operator* op, const double* x, double* r, void
  * solution.  x (device double [n]) and psi must not overlap.  Errors:
  * RTE_EINVAL. */
 rte_status rte_cell_values(const rte_operator* op, const double* x, double* psi, void* stream);
+
+/* Adaptive tailored finite point scheme (Sec. 2.3) on a TFPS operator (scheme
+ * RTE_SCHEME_TFPS, 2D).  rte_atfps_build selects, per cell, the basis functions
+ * whose value at the cell centre exp(-|xi| sigma_T h / 2) exceeds delta (eq.
+ * (def_V_delta)), builds every face's interface basis (the kept functions
+ * centred on the face orthonormalised by a QR factorisation and scaled to
+ * max-norm 1, first near-largest entry positive; then the dropped functions'
+ * eigenvectors scaled to max-norm 1), and assembles in FP64 on the host:
+ *   - the compressed system A_d alpha = b_d of eq. (2DAdaptiveTFPS_linear_sys):
+ *     per face, the projections of the continuity (or inflow) condition onto
+ *     the face's kept basis vectors, with the kept functions of both cells;
+ *   - the layer reconstruction of eq. (2DAdaptive_TFPS_layer1) and
+ *     (2DAdaptive_TFPS_layer2): each dropped coefficient is the projection of
+ *     the jump of the smooth solution across its face (or of the inflow data
+ *     minus the smooth solution) onto its own basis vector;
+ *   - the filtered loss of eq. (loss_delta), ||b_d - A_d D_d psi||_2, with D_d
+ *     the per-cell minimum-norm least-squares fit of the cell-centre values
+ *     minus the particular solution by the kept functions.
+ * Rows: x faces x_0..x_I of each grid row (i fastest), then y faces y_0..y_I
+ * of each grid column; within a face its kept basis vectors in order.
+ * Unknowns alpha (n_kept = n_rows of them): the kept coefficients cell by cell
+ * (x fastest), each cell's kept local indices ascending (local order of the
+ * TFPS operator).  The maps are uploaded as sparse rows to the current
+ * device; the evaluations below launch on `stream` and do not synchronise.
+ * delta in [0, 1); delta = 0 keeps every function.  When nothing is kept
+ * (n_kept = 0) alpha and rho may be NULL.  The operator must outlive the
+ * handle.  Errors: RTE_EINVAL (not a TFPS operator, bad delta,
+ * singular face basis), RTE_ENOMEM, RTE_EDEVICE. */
+rte_status rte_atfps_build(const rte_operator* op, double delta, rte_atfps** out);
+rte_status rte_atfps_free(rte_atfps* a);
+/* n_kept: unknowns, n_rows: rows of A_d (equal), nnz: stored entries of A_d.
+ * Any output may be NULL. */
+rte_status rte_atfps_get_info(const rte_atfps* a, int64_t* n_kept, int64_t* n_rows, int64_t* nnz);
+/* r = b_d - A_d alpha.  alpha, r: device double [n_kept]; must not overlap. */
+rte_status rte_atfps_residual(const rte_atfps* a, const double* alpha, double* r, void* stream);
+/* All 2 ndir coefficients of every cell from the kept ones: the kept ones
+ * copied, the dropped ones by layer reconstruction.  alpha: device double
+ * [n_kept]; coef: device double [cells][2 ndir] (the TFPS operator's unknown
+ * layout, so rte_cell_values evaluates it); must not overlap. */
+rte_status rte_atfps_reconstruct(const rte_atfps* a, const double* alpha, double* coef, void* stream);
+/* rho = b_d - A_d D_d psi and *loss = ||rho||_2 (eq. (loss_delta)).  psi:
+ * device double [ndir][cells] cell-centre values (direction-major, the layout
+ * of rte_cell_values); rho: device double [n_rows]; loss: device double [1].
+ * psi and rho must not overlap. */
+rte_status rte_atfps_filtered_loss(const rte_atfps* a, const double* psi, double* rho, double* loss,
+                                   void* stream);
 
 /* z = M(v): one MgNet V-cycle (Sec. 3.3) with the operator's CoeffNet
  * fields (precond RTE_PC_MGNET_BF16 or RTE_PC_MGNET_FP32), or the

@@ -26,7 +26,9 @@ functions centred at the left, right, bottom and top face of the cell, N/2 each)
 5. The filtered loss of Sec. 3.4, eq. (loss_delta): || b_delta - A_delta D_delta psi_d ||_2,
    with D_delta the per-cell least-squares map from cell-centre values to kept coefficients
    (reading: the paper does not define D; this is the minimum-norm least-squares fit of the
-   cell-centre values minus the particular solution by the kept functions).
+   cell-centre values minus the particular solution by the kept functions, singular values
+   at or below machine epsilon times max(N, kept) times the largest taken as zero, so that
+   kept functions which coincide at the centre give the minimum-norm fit).
 
 Row order of the compressed system: x faces (faces x_i, i = 0..I, for each grid row j,
 i fastest), then y faces (faces y_j, j = 0..I, for each grid column i, j fastest); within
@@ -230,7 +232,8 @@ class ATFPS:
     # ---------------------------------------------------------- filtered loss ---
     def D_map(self, psi_centres):
         """Kept coefficients from cell-centre values [N, cells]: per cell the minimum-norm
-        least-squares fit of psi - chi^s by the kept functions at the centre."""
+        least-squares fit of psi - chi^s by the kept functions at the centre (the SVD cutoff
+        is numpy's default, machine epsilon times the larger dimension)."""
         T = self.T
         out = np.zeros(self.n)
         for c in range(self.cells):

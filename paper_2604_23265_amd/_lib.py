@@ -75,6 +75,12 @@ _SIGS = {
     "rte_apply": [_P, _P, _P, C.c_int, _P],
     "rte_residual": [_P, _P, _P, _P],
     "rte_cell_values": [_P, _P, _P, _P],
+    "rte_atfps_build": [_P, C.c_double, C.POINTER(_P)],
+    "rte_atfps_free": [_P],
+    "rte_atfps_get_info": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "rte_atfps_residual": [_P, _P, _P, _P],
+    "rte_atfps_reconstruct": [_P, _P, _P, _P],
+    "rte_atfps_filtered_loss": [_P, _P, _P, _P, _P],
     "rte_precond_workspace_bytes": [_P, _P, C.POINTER(C.c_size_t)],
     "rte_precond_apply": [_P, _P, C.c_int, _P, _P, _P, C.c_size_t, _P],
     "rte_precond_apply_noalloc": [_P, _P, C.c_int, _P, _P, _P],

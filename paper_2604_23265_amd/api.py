@@ -231,6 +231,56 @@ class Operator:
         return psi, st.as_dict()
 
 
+class Atfps:
+    """The adaptive TFPS maps of a TFPS operator (rte_atfps_build): compressed residual,
+    layer reconstruction and filtered loss, evaluated on the device."""
+
+    def __init__(self, op, delta):
+        h = C.c_void_p()
+        check(lib().rte_atfps_build(op.handle, float(delta), C.byref(h)))
+        self._h = h
+        self.op = op
+        nk, nr, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().rte_atfps_get_info(h, C.byref(nk), C.byref(nr), C.byref(nnz)))
+        self.n_kept, self.n_rows, self.nnz = nk.value, nr.value, nnz.value
+
+    def residual(self, alpha, r=None, stream=None):
+        """r = b_d - A_d alpha, [n_rows] FP64."""
+        torch = _torch()
+        if r is None:
+            r = torch.empty(self.n_rows, dtype=torch.float64, device="cuda")
+        check(lib().rte_atfps_residual(self._h, _dptr(alpha), _dptr(r), _stream(stream)))
+        return r
+
+    def reconstruct(self, alpha, coef=None, stream=None):
+        """All coefficients [cells][2 ndir] FP64 from the kept ones."""
+        torch = _torch()
+        if coef is None:
+            coef = torch.empty(self.op.n, dtype=torch.float64, device="cuda")
+        check(lib().rte_atfps_reconstruct(self._h, _dptr(alpha), _dptr(coef), _stream(stream)))
+        return coef
+
+    def filtered_loss(self, psi, rho=None, stream=None):
+        """(rho, loss): rho = b_d - A_d D_d psi and its 2-norm (a device scalar)."""
+        torch = _torch()
+        if rho is None:
+            rho = torch.empty(self.n_rows, dtype=torch.float64, device="cuda")
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        check(lib().rte_atfps_filtered_loss(self._h, _dptr(psi), _dptr(rho), _dptr(loss), _stream(stream)))
+        return rho, loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rte_atfps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Continuous-batching request loop over a caller-owned device arena."""
 

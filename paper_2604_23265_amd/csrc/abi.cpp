@@ -163,6 +163,12 @@ rte_status guarded(F&& f) {
 
 hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
+// Whether the FP64 ranges [a, a + na) and [b, b + nb) share memory.
+bool overlap(const double* a, int64_t na, const double* b, int64_t nb) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + uintptr_t(nb) * 8 && b0 < a0 + uintptr_t(na) * 8;
+}
+
 }  // namespace
 
 
@@ -287,6 +293,73 @@ rte_status rte_cell_values(const rte_operator* h, const double* x, double* psi, 
       launch_tfps_centres(Target::single(o), x, psi, S(stream));
     else
       RTE_HIP(hipMemcpyAsync(psi, x, size_t(o.n) * 8, hipMemcpyDeviceToDevice, S(stream)));
+  });
+}
+
+rte_status rte_atfps_build(const rte_operator* h, double delta, rte_atfps** out) {
+  return guarded([&] {
+    RTE_REQUIRE(h && out, RTE_EINVAL, "rte_atfps_build: null argument");
+    std::unique_ptr<rte_atfps> a(new rte_atfps());
+    a->op = h->op.get();
+    a->host = atfps_build_host(*h->op, delta);
+    RTE_HIP(hipGetDevice(&a->device));
+    auto up = [&](const HostCsr& m) {
+      DevCsr d;
+      d.nrows = m.nrows;
+      d.ncols = m.ncols;
+      d.ptr = a->mem.upload(m.ptr);
+      d.col = a->mem.upload(m.col);
+      d.val = a->mem.upload(m.val);
+      return d;
+    };
+    a->A = up(a->host.A);
+    a->R = up(a->host.R);
+    a->M = up(a->host.M);
+    a->b = a->mem.upload(a->host.b);
+    a->r0 = a->mem.upload(a->host.r0);
+    a->c0 = a->mem.upload(a->host.c0);
+    *out = a.release();
+  });
+}
+
+rte_status rte_atfps_free(rte_atfps* a) {
+  return guarded([&] { delete a; });
+}
+
+rte_status rte_atfps_get_info(const rte_atfps* a, int64_t* n_kept, int64_t* n_rows, int64_t* nnz) {
+  return guarded([&] {
+    RTE_REQUIRE(a, RTE_EINVAL, "rte_atfps_get_info: null handle");
+    if (n_kept) *n_kept = a->host.n_kept;
+    if (n_rows) *n_rows = a->host.n_rows;
+    if (nnz) *nnz = int64_t(a->host.A.val.size());
+  });
+}
+
+rte_status rte_atfps_residual(const rte_atfps* a, const double* alpha, double* r, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(a && ((alpha && r) || a->host.n_kept == 0), RTE_EINVAL, "rte_atfps_residual: null argument");
+    RTE_REQUIRE(!overlap(alpha, a->host.n_kept, r, a->host.n_rows), RTE_EINVAL, "rte_atfps_residual: alpha and r overlap");
+    launch_csr(a->A, alpha, a->b, true, r, S(stream));
+  });
+}
+
+rte_status rte_atfps_reconstruct(const rte_atfps* a, const double* alpha, double* coef, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(a && coef && (alpha || a->host.n_kept == 0), RTE_EINVAL, "rte_atfps_reconstruct: null argument");
+    RTE_REQUIRE(!overlap(alpha, a->host.n_kept, coef, a->host.n_full), RTE_EINVAL,
+                "rte_atfps_reconstruct: alpha and coef overlap");
+    launch_csr(a->R, alpha, a->r0, false, coef, S(stream));
+  });
+}
+
+rte_status rte_atfps_filtered_loss(const rte_atfps* a, const double* psi, double* rho, double* loss, void* stream) {
+  return guarded([&] {
+    RTE_REQUIRE(a && psi && loss && (rho || a->host.n_rows == 0), RTE_EINVAL,
+                "rte_atfps_filtered_loss: null argument");
+    RTE_REQUIRE(!overlap(psi, int64_t(a->host.ndir) * a->host.cells, rho, a->host.n_rows), RTE_EINVAL,
+                "rte_atfps_filtered_loss: psi and rho overlap");
+    launch_csr(a->M, psi, a->c0, true, rho, S(stream));
+    launch_norm2(rho, a->host.n_rows, loss, S(stream));
   });
 }
 

@@ -201,6 +201,7 @@ struct Model {
 
 // --------------------------------------------------------- the operator ---
 constexpr int MAX_LEVELS = 8;
+struct TfpsHost;
 
 // Kernels that give each of a block's four waves one "direction slot" (the
 // directions s, s + 4, s + 8, ...) hold ceil(N / 4) values per thread,
@@ -243,6 +244,7 @@ struct Operator {
   int dim = 2, nx = 0, ny = 0, nz = 1, ndir = 0, kernel = 0;
   int scheme = RTE_SCHEME_UPWIND;
   int nbasis = 0;                   // TFPS: distinct eigen-bases
+  std::shared_ptr<const TfpsHost> tfps_host;  // TFPS: the host build (bases, b), for ATFPS
   int64_t cells = 0, n = 0;
   double h = 0, g = 0;
   int device = 0;
@@ -330,12 +332,40 @@ void launch_tfps_centres(const Target& T, const double* x, double* psi, hipStrea
 // scalar fields (grid, directions, S) are set
 struct TfpsHost {
   std::vector<double> Lt, xi, chis, b;
+  std::vector<double> sT, ux, uy;  // per cell sigma_T / eps; direction components
   std::vector<int> bid;
   int nbasis = 0;
 };
 TfpsHost tfps_build_host(const Operator& op, const std::vector<double>& dirs, const std::vector<double>& w,
                          const std::vector<double>& sT, const std::vector<double>& sA,
                          const std::vector<double>& qh, const double* inflow, size_t fstride);
+
+// ATFPS (Sec. 2.3) on a TFPS operator: the three maps the device evaluates,
+// each a sparse matrix and a constant (see atfps_setup.cpp).
+struct HostCsr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> ptr, col;
+  std::vector<double> val;
+};
+HostCsr csr_from(int64_t nrows, int64_t ncols, const std::vector<int64_t>& r, const std::vector<int64_t>& c,
+                 const std::vector<double>& v);
+struct AtfpsHost {
+  int64_t cells = 0, n_kept = 0, n_rows = 0, n_full = 0;
+  int ndir = 0;
+  HostCsr A, R, M;                 // compressed system, reconstruction, filtered-loss map
+  std::vector<double> b, r0, c0;   // their constants
+};
+AtfpsHost atfps_build_host(const Operator& op, double delta);
+struct DevCsr {
+  int64_t nrows = 0, ncols = 0;
+  const int64_t* ptr = nullptr;
+  const int64_t* col = nullptr;
+  const double* val = nullptr;
+};
+// y = c - A x (sub = true) or y = A x + c (sub = false); c may be null (zero)
+void launch_csr(const DevCsr& A, const double* x, const double* c, bool sub, double* y, hipStream_t s);
+// *out = ||v||_2 over n values (one block, fixed order)
+void launch_norm2(const double* v, int64_t n, double* out, hipStream_t s);
 
 // vscale (nullable, workspace-relative under a slot table): v is taken times
 // vscale[0]
@@ -570,5 +600,13 @@ struct rte_operator {
 };
 struct mgnet_model {
   std::unique_ptr<rte::Model> m;
+};
+struct rte_atfps {
+  const rte::Operator* op = nullptr;
+  rte::AtfpsHost host;
+  rte::DevArena mem;
+  rte::DevCsr A, R, M;
+  double *b = nullptr, *r0 = nullptr, *c0 = nullptr;
+  int device = 0;
 };
 

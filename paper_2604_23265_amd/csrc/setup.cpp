@@ -259,7 +259,7 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
       for (int64_t c = 0; c < cells; ++c) qh[c] = eps[c] * md->q[c];
       TF = tfps_build_host(*op, dirs, w, sT, sA, qh, md->inflow, fstride);
       op->nbasis = TF.nbasis;
-      b.swap(TF.b);
+      b = TF.b;
     } else {
       b.assign(size_t(op->n), 0.0);
       for (int m = 0; m < N; ++m)
@@ -362,6 +362,7 @@ Operator* build_operator(const rte_geometry* g, const rte_medium* md, const Mode
       op->a.tf_bid = reinterpret_cast<int*>(put(o_bid, TF.bid.data(), TF.bid.size() * 4));
       op->a.tf_chis = reinterpret_cast<double*>(put(o_chis, TF.chis.data(), TF.chis.size() * 8));
       op->a.tf_tab = reinterpret_cast<uint64_t*>(put(o_tab, tabs, sizeof(tabs)));
+      op->tfps_host = std::make_shared<const TfpsHost>(std::move(TF));
     }
     if (model) {
       const_cast<Model*>(model)->ensure_on_device();

@@ -237,3 +237,56 @@ void launch_tfps_centres(const Target& T, const double* x, double* psi, hipStrea
 }
 
 }  // namespace rte
+
+// ------------------------------------------------------------- ATFPS ---
+// The compressed system, the layer reconstruction and the filtered loss of
+// Sec. 2.3 / Sec. 3.4 are sparse linear maps plus constants, assembled on the
+// host.  A wave takes a row: lanes stride over its nonzeros, a wave-level
+// sum in fixed order combines them (rows hold at most 4 N nonzeros), so every
+// result is reproducible.
+namespace rte {
+namespace {
+
+__global__ __launch_bounds__(256) void csr_kernel(int64_t nrows, const int64_t* __restrict__ ptr,
+                                                  const int64_t* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ x, const double* __restrict__ c,
+                                                  int sub, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (r >= nrows) return;
+  double s = 0;
+  for (int64_t e = ptr[r] + lane; e < ptr[r + 1]; e += 64) s += val[e] * x[col[e]];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+  if (lane == 0) {
+    const double cv = c ? c[r] : 0.0;
+    y[r] = sub ? cv - s : s + cv;
+  }
+}
+
+__global__ __launch_bounds__(256) void norm2_kernel(const double* __restrict__ v, int64_t n, double* out) {
+  __shared__ double part[4];
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += v[i] * v[i];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = sqrt(((part[0] + part[1]) + part[2]) + part[3]);
+}
+
+}  // namespace
+
+void launch_csr(const DevCsr& A, const double* x, const double* c, bool sub, double* y, hipStream_t s) {
+  if (A.nrows == 0) return;
+  hipLaunchKernelGGL(csr_kernel, dim3(unsigned((A.nrows + 3) / 4)), dim3(256), 0, s, A.nrows, A.ptr, A.col, A.val,
+                     x, c, sub ? 1 : 0, y);
+  RTE_HIP(hipGetLastError());
+}
+
+void launch_norm2(const double* v, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(256), 0, s, v, n, out);
+  RTE_HIP(hipGetLastError());
+}
+
+}  // namespace rte

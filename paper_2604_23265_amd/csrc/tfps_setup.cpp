@@ -164,6 +164,9 @@ TfpsHost tfps_build_host(const Operator& op, const std::vector<double>& dirs, co
   }
   RTE_REQUIRE(2 * px == N && 2 * py == N, RTE_EINVAL, "TFPS: half of the directions must point each way along x and y");
   TfpsHost H;
+  H.sT = sT;
+  H.ux = ux;
+  H.uy = uy;
   H.bid.assign(size_t(cells), 0);
   H.chis.assign(size_t(cells), 0.0);
   std::unordered_map<double, int> ids;
