@@ -504,12 +504,15 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   const Operator& op = *Tg.op;
   const OpArrays& A = Tg.arr;
   if (op.cells % 64 != 0) return false;
-  // about 2048 blocks over all solves of the launch, at least one tile each;
-  // a multiple of 8 when the tile count is (the XCD-contiguous order).
-  // Measured at 64 and 96 directions: 1024 blocks, or the next tile's
-  // loads issued before the upwind neighbours', were no faster.
+  // about 512 blocks over all solves of the launch (two per CU, each walking
+  // eight tiles of a single solve), at least one tile each; a multiple of 8
+  // when the tile count is (the XCD-contiguous order).  Measured at
+  // 512^2 x 64 and 64^3 x 96 directions: 512 blocks 48.5 and 119 us, 1024
+  // 50.6 and 132 us, 2048 52.1 and 147 us, 4096 63.8 and 178 us, 256 60.7
+  // and 117 us.  Staging the upwind y/z neighbours as whole coalesced tile
+  // segments in LDS (instead of per-lane loads) measured no faster.
   const int64_t ntile = op.cells / 64;
-  int64_t g = std::max<int64_t>(1, 2048 / std::max(1, Tg.sl.count));
+  int64_t g = std::max<int64_t>(1, 512 / std::max(1, Tg.sl.count));
   if (ntile % 8 == 0) g = std::max<int64_t>(8, g & ~int64_t(7));
   g = std::min(g, ntile);
   const dim3 grid(unsigned(g), 1, unsigned(Tg.sl.count));

@@ -287,6 +287,44 @@ def test_apply_and_solve_at_scatter_shapes(name):
     assert rel(host(xs), ref) < 1e-5
 
 
+@pytest.mark.parametrize("n,ndir", [(64, 64), (128, 96), (192, 64)])
+def test_apply_whole_row_tiles(n, ndir):
+    """Grids whose rows are whole 64-cell tiles (row-uniform tile indexing of the matrix-core
+    apply): FP32 apply against the oracle, element-wise, with random inflow and a lognormal
+    medium; 192^2 has three tiles per row (tile edges inside the grid)."""
+    say("case whole-row-tile apply", n, ndir)
+    from paper_2604_23265_amd import api
+    torch_cuda()
+    prob = problems.make(n=n, ndir=ndir, g=0.7, eps=0.1, inflow="random", seed=23)
+    op = api.Operator(prob)
+    P = osolve.Problem(prob)
+    x = np.random.default_rng(24).standard_normal(P.D.n).astype(np.float32)
+    y = host(op.apply(dev(x, "float32"))).astype(np.float64)
+    ref = P.apply(x.astype(np.float64))
+    say("  apply fp32 rel err %.3e  max-norm %.3e" % (rel(y, ref), rel_max(y, ref)))
+    assert rel(y, ref) < 1e-6 and rel_max(y, ref) < 1e-6
+
+
+def test_solve_through_whole_row_tile_apply():
+    """The Arnoldi step applies L to an FP32 vector into an FP64 one; on a 64^2 x 64 grid that
+    is the matrix-core kernel's FP64-output form.  Unpreconditioned FGMRES in the transport regime
+    (eps = 1) against the oracle's own unpreconditioned FGMRES, both to rtol 1e-10."""
+    say("case solve through the whole-row-tile apply")
+    from paper_2604_23265_amd import api
+    torch_cuda()
+    prob = problems.make(n=64, ndir=64, g=0.5, eps=1.0, inflow="left", seed=25)
+    op = api.Operator(prob)
+    P = osolve.Problem(prob)
+    x, st = op.solve(precond="none", rtol=1e-10, restart=30, max_iters=3000)
+    say("  stats", st)
+    assert st["converged"] == 1
+    ref, info = krylov.fgmres(P.apply, P.b.reshape(-1), None, 30, 1e-12, 3000)
+    assert info["converged"]
+    e, em = rel(host(x), ref), rel_max(host(x), ref)
+    say("  solution rel err %.3e  max-norm %.3e" % (e, em))
+    assert e < 1e-6 and em < 1e-6
+
+
 def test_solve_is_deterministic():
     say("case determinism c2_small bf16")
     prob, model, op, P = setup_case("c2_small")
