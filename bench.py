@@ -16,6 +16,8 @@ from the benchmark's); the seeded initial weights are timed beside them.
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -187,6 +189,18 @@ def solution_errors(prob, blob, xs):
     return out
 
 
+@contextlib.contextmanager
+def no_gc():
+    """No garbage-collection pass inside a timed region: a full pass over this process's
+    heap stalls the thread that submits and collects the solves."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
+
+
 def serving_leg(args, api, torch, configs, weights):
     """Served latency on the C3 stream: a closed batch measures saturated throughput, then
     Poisson arrivals at 0.7x that rate give arrival-to-completion p50/p99."""
@@ -233,13 +247,15 @@ def serving_leg(args, api, torch, configs, weights):
         return time.perf_counter() - t0, done
 
     log("serving: closed batch of %d requests" % len(ops))
-    wall, done = run([0.0] * len(ops))
+    with no_gc():
+        wall, done = run([0.0] * len(ops))
     sat = len(ops) / wall
     rate = 0.7 * sat
     arr = list(configs.c3_arrivals(len(ops), rate=rate, seed=3999))
     arr = [a - arr[0] for a in arr]
     log("serving: Poisson arrivals at %.2f req/s" % rate)
-    wall2, done2 = run(arr)
+    with no_gc():
+        wall2, done2 = run(arr)
     lat = [d[0] * 1e3 for d in done2.values()]
     lat_b = [d[0] * 1e3 + builds[i] for i, d in done2.items()]
     its = [d[2]["iterations"] for d in done2.values()]
@@ -411,15 +427,16 @@ def main():
         if prof_cls is not None:
             api.prof_reset()
             api.prof_enable(prof_cls, args.prof_every)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = []
-        step_ms.clear()
-        for _ in range(steps):
-            ts = time.perf_counter()
-            sts += batch(mode)
-            step_ms.append((time.perf_counter() - ts) * 1e3)
-        torch.cuda.synchronize()
+        with no_gc():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = []
+            step_ms.clear()
+            for _ in range(steps):
+                ts = time.perf_counter()
+                sts += batch(mode)
+                step_ms.append((time.perf_counter() - ts) * 1e3)
+            torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = None
         if prof_cls is not None:
@@ -433,6 +450,7 @@ def main():
     log("timed: %d batches of %d BF16-path solves (events on kernel class %s)" % (args.steps, args.batch, args.prof))
     dt, sts, prof = run("bf16", args.steps, pc)
     bf16_step_ms = list(step_ms)
+    log("step ms: " + " ".join("%.2f" % t for t in bf16_step_ms))
     conv_keys = api.prof_query_keys(L.K_CONV) if args.prof == "conv" else {}
     orth_keys = api.prof_query_keys(L.K_ORTH) if args.prof == "orth" else {}
     x_bf16 = outs[0].cpu().numpy()
@@ -574,11 +592,12 @@ def main():
     if not args.no_single:
         log("single solves: instance 0 alone, %d times" % args.steps)
         ws = torch.empty(ops[0].workspace_bytes(model, precond="bf16", **kw), dtype=torch.uint8, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, st = ops[0].solve(model=model, psi=outs[0], workspace=ws, precond="bf16", **kw)
-        torch.cuda.synchronize()
+        with no_gc():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, st = ops[0].solve(model=model, psi=outs[0], workspace=ws, precond="bf16", **kw)
+            torch.cuda.synchronize()
         d1 = (time.perf_counter() - t0) / args.steps
         out["single_solve"] = {"value": 1.0 / d1, "unit": "solves/s", "ms": d1 * 1e3,
                                "iterations": st["iterations"], "instance": "GRF seed 2000"}

@@ -241,6 +241,10 @@ rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, i
                              const double* v, float* z, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* Environment switch read by the library (for comparisons and profiling;
+ * results do not depend on it): RTE_GRAPHS=0 runs the Arnoldi steps of
+ * rte_solve and the server eagerly instead of as HIP graphs captured per
+ * step shape. */
 /* For callers that cannot allocate device memory (code under HIP stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the MgNet
  * V-cycle of rte_precond_apply (precond RTE_PC_MGNET_BF16 or
@@ -393,6 +397,8 @@ rte_status rte_server_destroy(rte_server* srv);
  * rte_prof_enable(cls, every): every > 0 brackets every `every`-th launch of
  * the class with an event pair stamped by its dispatch (1 = all launches;
  * sampling keeps the events' own cost out of the timed work); 0 disables.
+ * Enabling creates a pool of 8192 events up front, so that the timed launches
+ * do not create them.
  * Solves replay their Arnoldi steps as HIP graphs, whose launches cannot be
  * bracketed; while any class is enabled a solve runs one step in `every`
  * without its graph and times every launch of the enabled classes in it.  rte_prof_query synchronises the recorded events and returns,

@@ -21,6 +21,7 @@ void fail(rte_status code, const std::string& msg) { throw Error(code, msg); }
 
 // ------------------------------------------------------------- profiler ---
 namespace {
+constexpr size_t kProfEventReserve = 8192;
 struct Prof {
   std::mutex mu;
   int every[RTE_K_COUNT] = {};
@@ -522,6 +523,13 @@ rte_status rte_prof_enable(int c, int every) {
     std::lock_guard<std::mutex> lk(P.mu);
     P.every[c] = every;
     P.seen[c] = 0;
+    // the events are created here, so that no timed launch creates one
+    if (every > 0)
+      while (P.pool.size() < kProfEventReserve) {
+        hipEvent_t e;
+        RTE_HIP(hipEventCreate(&e));
+        P.pool.push_back(e);
+      }
   });
 }
 
