@@ -241,10 +241,11 @@ rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, i
                              const double* v, float* z, void* workspace, size_t ws_bytes,
                              void* stream);
 
-/* Environment switch read by the library (for comparisons and profiling;
- * results do not depend on it): RTE_GRAPHS=0 runs the Arnoldi steps of
+/* Environment switches read by the library (for comparisons and profiling;
+ * results do not depend on them): RTE_GRAPHS=0 runs the Arnoldi steps of
  * rte_solve and the server eagerly instead of as HIP graphs captured per
- * step shape. */
+ * step shape; RTE_T_BF16=0 stores every intermediate t of the BF16 V-cycle
+ * (the tensors that only feed convolutions) in FP32 instead of bfloat16. */
 /* For callers that cannot allocate device memory (code under HIP stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the MgNet
  * V-cycle of rte_precond_apply (precond RTE_PC_MGNET_BF16 or

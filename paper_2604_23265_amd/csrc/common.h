@@ -313,6 +313,10 @@ struct ConvLaunch {
   const float* a;
   const float* ainv;
   float* out2;
+  // BF16 path, tiled 2D kernel only: the input is a t tensor stored as
+  // bfloat16 (STORE, ACCUM, STORE_T), or the t output -- out of RESID_T and
+  // RESID_R, out2 of STORE_T -- is stored as bfloat16
+  int in16, t16;
 };
 void launch_conv(const ConvLaunch& c, int kind, hipStream_t s);
 void conv3_setup(ConvLaunch& c, int dim, const int in_dim[3], int stride);
@@ -368,12 +372,12 @@ void launch_csr(const DevCsr& A, const double* x, const double* c, bool sub, dou
 void launch_norm2(const double* v, int64_t n, double* out, hipStream_t s);
 
 // vscale (nullable, workspace-relative under a slot table): v is taken times
-// vscale[0]
+// vscale[0]; t16: t0 (or t) is stored as bfloat16 bits
 void launch_lift(const Target& T, const Model& m, const double* v, const double* vscale, float* f0,
-                 const float* ainv, float* t0, hipStream_t s);
+                 const float* ainv, float* t0, bool t16, hipStream_t s);
 void launch_proj(const Target& T, const Model& m, const double* v, const double* vscale, const float* u0,
                  float* z, hipStream_t s);
-void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count,
+void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count, bool t16,
                          hipStream_t s);
 void launch_fill_f32(const Slots& sl, float* p, float v, int64_t count, hipStream_t s);
 void launch_fill_f64(const Slots& sl, double* p, double v, int64_t count, hipStream_t s);

@@ -30,6 +30,11 @@
 //   RESID_R out = f - conv - a (.) u           (u = the conv input, same grid)
 //   RESID_T out = a^{-1} (.) (f - conv - a (.) u)
 //   STORE_T out = conv, out2 = a^{-1} (.) conv
+// On the BF16 path the tensors that only ever feed a convolution (t: the
+// outputs of RESID_T and RESID_R, out2 of STORE_T, the lift's a^{-1} (.) f)
+// can be stored as bfloat16 (the tiled 2D kernel's IN16 / T16 forms): they
+// are rounded where they are produced exactly as the consumer would round
+// them when staging, so the results are bitwise those of FP32 storage.
 #include <algorithm>
 #include <type_traits>
 #include <cstring>
@@ -546,9 +551,17 @@ struct TileGeom {
 
 // NI = 2 or 4 column tiles of 16 output channels per block (32 or 64
 // channels): with 64 the input footprint is staged once per 64 outputs.
-template <int CK, int MODE, int NI>
+template <int CK, int MODE, int NI, bool IN16, bool T16>
 __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
   using G = TileGeom<CK, NI>;
+  static_assert(!IN16 || MODE == CONV_STORE || MODE == CONV_ACCUM || MODE == CONV_STORE_T,
+                "a BF16 input is a t tensor, never the u of a residual epilogue");
+  static_assert(!T16 || MODE == CONV_RESID_T || MODE == CONV_RESID_R || MODE == CONV_STORE_T,
+                "only t outputs are stored as BF16");
+  // the footprint of one 32-channel chunk: 8 float4 per pixel, or 4 pieces
+  // of 8 BF16
+  constexpr int PIECES_PER_PIX = IN16 ? 4 : 8;
+  constexpr int INP = (G::FPIX * PIECES_PER_PIX + 255) / 256;
   const int slot_z = int(blockIdx.z) / G::NCLS;
   const int cls = int(blockIdx.z) - slot_z * G::NCLS;
   SlotBase bs;
@@ -610,19 +623,26 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
     }
 
   // ---- staging: chunk c's footprint and weights, loaded into registers
-  v4f rin[G::IN_PIECES];
+  const uint16_t* __restrict__ in16 = reinterpret_cast<const uint16_t*>(in);
+  v4f rin[IN16 ? 1 : INP];
+  v4u rin16[IN16 ? INP : 1];
   v4u rw[G::W_PIECES];
   auto load_chunk = [&](int c) {
 #pragma unroll
-    for (int i = 0; i < G::IN_PIECES; ++i) {
+    for (int i = 0; i < INP; ++i) {
       const int idx = int(threadIdx.x) + 256 * i;
-      const int pix = idx >> 3, q4 = idx & 7;
+      const int pix = idx / PIECES_PER_PIX, qp = idx - (idx / PIECES_PER_PIX) * PIECES_PER_PIX;
       const int fy = pix / G::FP, fx = pix - (pix / G::FP) * G::FP;
       const int ix = ox0 + fx, iy = oy0 + fy;
-      const bool ok = idx < G::FPIX * 8 && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1);
+      const bool ok = idx < G::FPIX * PIECES_PER_PIX && unsigned(ix) < unsigned(W0) && unsigned(iy) < unsigned(W1);
       const int ixc = clampi(ix, 0, W0 - 1), iyc = clampi(iy, 0, W1 - 1);
-      const v4f v = *reinterpret_cast<const v4f*>(in + size_t(iyc * W0 + ixc) * cin + c * 32 + q4 * 4);
-      rin[i] = ok ? v : v4f{0.f, 0.f, 0.f, 0.f};
+      if constexpr (IN16) {
+        const v4u v = *reinterpret_cast<const v4u*>(in16 + size_t(iyc * W0 + ixc) * cin + c * 32 + qp * 8);
+        rin16[i] = ok ? v : v4u{0u, 0u, 0u, 0u};
+      } else {
+        const v4f v = *reinterpret_cast<const v4f*>(in + size_t(iyc * W0 + ixc) * cin + c * 32 + qp * 4);
+        rin[i] = ok ? v : v4f{0.f, 0.f, 0.f, 0.f};
+      }
     }
 #pragma unroll
     for (int i = 0; i < G::W_PIECES; ++i) {
@@ -636,14 +656,19 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int i = 0; i < G::IN_PIECES; ++i) {
+    for (int i = 0; i < INP; ++i) {
       const int idx = int(threadIdx.x) + 256 * i;
-      if (idx < G::FPIX * 8) {
-        const int pix = idx >> 3, q4 = idx & 7;
-        const v4f v = rin[i];
-        const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
-        const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
-        *reinterpret_cast<uint2*>(xin + tile_word(pix, q4 >> 1) + 2 * (q4 & 1)) = make_uint2(lo, hi);
+      if (idx < G::FPIX * PIECES_PER_PIX) {
+        if constexpr (IN16) {
+          const int pix = idx >> 2, q = idx & 3;
+          *reinterpret_cast<v4u*>(xin + tile_word(pix, q)) = rin16[i];
+        } else {
+          const int pix = idx >> 3, q4 = idx & 7;
+          const v4f v = rin[i];
+          const uint32_t lo = uint32_t(uint16_t(bf16_bits(v[0]))) | (uint32_t(uint16_t(bf16_bits(v[1]))) << 16);
+          const uint32_t hi = uint32_t(uint16_t(bf16_bits(v[2]))) | (uint32_t(uint16_t(bf16_bits(v[3]))) << 16);
+          *reinterpret_cast<uint2*>(xin + tile_word(pix, q4 >> 1) + 2 * (q4 & 1)) = make_uint2(lo, hi);
+        }
       }
     }
 #pragma unroll
@@ -693,17 +718,24 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs A0) {
       const int q = j * NI + ni;
       const size_t o = oidx[j] + ni * 16;
       const float v = acc[ni][j];
+      // a t output stored as BF16 holds the bits the consumer's staging would make
+      auto put_t = [&](float* dst, float x) {
+        if constexpr (T16)
+          reinterpret_cast<uint16_t*>(dst)[o] = uint16_t(bf16_bits(x));
+        else
+          dst[o] = x;
+      };
       if constexpr (MODE == CONV_STORE) {
         out[o] = v;
       } else if constexpr (MODE == CONV_ACCUM) {
         out[o] = eu[q] + v;
       } else if constexpr (MODE == CONV_STORE_T) {
         out[o] = v;
-        out2[o] = ei[q] * v;
+        put_t(out2, ei[q] * v);
       } else if constexpr (MODE == CONV_RESID_R) {
-        out[o] = ef[q] - v - ea[q] * eu[q];
+        put_t(out, ef[q] - v - ea[q] * eu[q]);
       } else {
-        out[o] = ei[q] * (ef[q] - v - ea[q] * eu[q]);
+        put_t(out, ei[q] * (ef[q] - v - ea[q] * eu[q]));
       }
     }
 }
@@ -976,23 +1008,54 @@ void tile3_dispatch(const ConvArgs& a, int nz, int mode, hipStream_t s, const Pr
 }
 
 template <int CK, int NI>
-void tile_dispatch2(const ConvArgs& a, dim3 grid, int mode, hipStream_t s, const ProfScope& ps) {
-  switch (mode) {
-    case CONV_STORE: launch_k(conv_tile_kernel<CK, CONV_STORE, NI>, grid, dim3(256), 0, s, ps, a); break;
-    case CONV_ACCUM: launch_k(conv_tile_kernel<CK, CONV_ACCUM, NI>, grid, dim3(256), 0, s, ps, a); break;
-    case CONV_STORE_T: launch_k(conv_tile_kernel<CK, CONV_STORE_T, NI>, grid, dim3(256), 0, s, ps, a); break;
-    case CONV_RESID_R: launch_k(conv_tile_kernel<CK, CONV_RESID_R, NI>, grid, dim3(256), 0, s, ps, a); break;
-    default: launch_k(conv_tile_kernel<CK, CONV_RESID_T, NI>, grid, dim3(256), 0, s, ps, a); break;
+void tile_dispatch2(const ConvArgs& a, dim3 grid, int mode, bool in16, bool t16, hipStream_t s,
+                    const ProfScope& ps) {
+  auto go = [&](auto kern) { launch_k(kern, grid, dim3(256), 0, s, ps, a); };
+  if constexpr (CK == 2) {  // the prolongation reads u and writes u: FP32 only
+    switch (mode) {
+      case CONV_STORE: go(conv_tile_kernel<CK, CONV_STORE, NI, false, false>); break;
+      case CONV_ACCUM: go(conv_tile_kernel<CK, CONV_ACCUM, NI, false, false>); break;
+      case CONV_STORE_T: go(conv_tile_kernel<CK, CONV_STORE_T, NI, false, false>); break;
+      case CONV_RESID_R: go(conv_tile_kernel<CK, CONV_RESID_R, NI, false, false>); break;
+      default: go(conv_tile_kernel<CK, CONV_RESID_T, NI, false, false>); break;
+    }
+    return;
+  } else {
+    switch (mode) {
+      case CONV_STORE:
+        if (in16) go(conv_tile_kernel<CK, CONV_STORE, NI, true, false>);
+        else go(conv_tile_kernel<CK, CONV_STORE, NI, false, false>);
+        break;
+      case CONV_ACCUM:
+        if (in16) go(conv_tile_kernel<CK, CONV_ACCUM, NI, true, false>);
+        else go(conv_tile_kernel<CK, CONV_ACCUM, NI, false, false>);
+        break;
+      case CONV_STORE_T:
+        if (in16 && t16) go(conv_tile_kernel<CK, CONV_STORE_T, NI, true, true>);
+        else if (in16) go(conv_tile_kernel<CK, CONV_STORE_T, NI, true, false>);
+        else if (t16) go(conv_tile_kernel<CK, CONV_STORE_T, NI, false, true>);
+        else go(conv_tile_kernel<CK, CONV_STORE_T, NI, false, false>);
+        break;
+      case CONV_RESID_R:
+        if (t16) go(conv_tile_kernel<CK, CONV_RESID_R, NI, false, true>);
+        else go(conv_tile_kernel<CK, CONV_RESID_R, NI, false, false>);
+        break;
+      default:
+        if (t16) go(conv_tile_kernel<CK, CONV_RESID_T, NI, false, true>);
+        else go(conv_tile_kernel<CK, CONV_RESID_T, NI, false, false>);
+        break;
+    }
   }
 }
 
 template <int CK>
-void tile_dispatch(const ConvArgs& a, int gx, int gy, int nz, int mode, hipStream_t s, const ProfScope& ps) {
+void tile_dispatch(const ConvArgs& a, int gx, int gy, int nz, int mode, bool in16, bool t16, hipStream_t s,
+                   const ProfScope& ps) {
   const unsigned patches = unsigned((gx / 8) * (gy / 8));
   if (a.cout % 64 == 0)
-    tile_dispatch2<CK, 4>(a, dim3(patches, unsigned(a.cout / 64), unsigned(nz)), mode, s, ps);
+    tile_dispatch2<CK, 4>(a, dim3(patches, unsigned(a.cout / 64), unsigned(nz)), mode, in16, t16, s, ps);
   else
-    tile_dispatch2<CK, 2>(a, dim3(patches, unsigned(a.cout / 32), unsigned(nz)), mode, s, ps);
+    tile_dispatch2<CK, 2>(a, dim3(patches, unsigned(a.cout / 32), unsigned(nz)), mode, in16, t16, s, ps);
 }
 
 template <bool KSPLIT, int MODE>
@@ -1063,7 +1126,7 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
                                                    const float* __restrict__ dc, const float* __restrict__ Sd,
                                                    const float* __restrict__ Win, float* __restrict__ f0,
                                                    const float* __restrict__ ainv, float* __restrict__ t0, int N,
-                                                   int C0, int64_t P) {
+                                                   int C0, int64_t P, int t16) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   v = at(v, bs.ws + bs.dx);
@@ -1107,7 +1170,12 @@ __global__ __launch_bounds__(256) void lift_kernel(Slots sl, const double* __res
     for (int m = 0; m < N; ++m) acc += wt[m * C0 + c] * vt[m * PT + pl];
     const int64_t o = p * C0 + c;
     f0[o] = acc;
-    if (t0) t0[o] = ainv[o] * acc;
+    if (t0) {
+      if (t16)
+        reinterpret_cast<uint16_t*>(t0)[o] = uint16_t(bf16_bits(ainv[o] * acc));
+      else
+        t0[o] = ainv[o] * acc;
+    }
   }
 }
 
@@ -1193,7 +1261,7 @@ __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* 
                                                         const float* __restrict__ dc, const float* __restrict__ Sd,
                                                         const float* __restrict__ Wp, float* __restrict__ f0,
                                                         const float* __restrict__ ainv, float* __restrict__ t0, int N,
-                                                        int64_t P) {
+                                                        int64_t P, int t16) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   v = at(v, bs.ws + bs.dx);
@@ -1258,7 +1326,12 @@ __global__ __launch_bounds__(256) void lift_slot_kernel(Slots sl, const double* 
     if (pp >= P) continue;
     const float val = sm[pl * LD + c];
     f0[pp * C0 + c] = val;
-    if (t0) t0[pp * C0 + c] = ai[k] * val;
+    if (t0) {
+      if (t16)
+        reinterpret_cast<uint16_t*>(t0)[pp * C0 + c] = uint16_t(bf16_bits(ai[k] * val));
+      else
+        t0[pp * C0 + c] = ai[k] * val;
+    }
   }
 }
 
@@ -1330,14 +1403,19 @@ __global__ __launch_bounds__(256) void proj_slot_kernel(Slots sl, const double* 
 }
 
 __global__ void scale_fields_kernel(Slots sl, const float* __restrict__ ainv, const float* __restrict__ f,
-                                    float* __restrict__ t, int64_t n) {
+                                    float* __restrict__ t, int64_t n, int t16) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   ainv = at(ainv, bs.op);
   f = at(f, bs.ws);
   t = at(t, bs.ws);
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (; i < n; i += int64_t(gridDim.x) * blockDim.x) t[i] = ainv[i] * f[i];
+  for (; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    if (t16)
+      reinterpret_cast<uint16_t*>(t)[i] = uint16_t(bf16_bits(ainv[i] * f[i]));
+    else
+      t[i] = ainv[i] * f[i];
+  }
 }
 
 template <class T>
@@ -1525,7 +1603,8 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
     const double out_el = double(gm) * c.nclass * c.cout;
     const double wbytes = double(c.w->taps) * c.cout * c.cin * (kind == MFMA_F32 ? 4.0 : 2.0);
     const double extra[] = {0.0, 1.0, 2.0, 2.0, 3.0};  // STORE, ACCUM, STORE_T, RESID_R, RESID_T
-    ps.bytes = 4.0 * in_el + wbytes + 4.0 * out_el * (1.0 + extra[c.mode]);
+    ps.bytes = (c.in16 ? 2.0 : 4.0) * in_el + wbytes + 4.0 * out_el * (1.0 + extra[c.mode]);
+    if (c.t16) ps.bytes -= 2.0 * out_el;  // the t output (out, or out2 of STORE_T) in 2 bytes
   }
   // The tiled kernel covers every 2D BF16 convolution whose channel counts
   // are multiples of 32 and whose virtual grid is a multiple of 8 per axis.
@@ -1543,6 +1622,13 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
     if (c.ostride == 1 && c.cstride == 1 && c.ntap == 27) ck3 = 0;
     else if (c.ostride == 2 && c.nclass == 8 && c.ntap == 8) ck3 = 2;
   }
+  // BF16-stored t tensors exist only in the tiled 2D kernel's stride-1 and
+  // restriction forms
+  RTE_REQUIRE(!(c.in16 || c.t16) || ck == 0 || ck == 1, RTE_EINVAL, "conv: BF16 t storage needs the tiled kernel");
+  RTE_REQUIRE(!c.in16 || c.mode == CONV_STORE || c.mode == CONV_ACCUM || c.mode == CONV_STORE_T, RTE_EINVAL,
+              "conv: a BF16 input is a t tensor");
+  RTE_REQUIRE(!c.t16 || c.mode == CONV_RESID_T || c.mode == CONV_RESID_R || c.mode == CONV_STORE_T, RTE_EINVAL,
+              "conv: only t outputs are stored as BF16");
   if (ck3 >= 0) {
     a.w = c.w->d16;
     const int nz = c.nclass * c.sl.count;
@@ -1551,9 +1637,9 @@ void launch_conv(const ConvLaunch& c, int kind, hipStream_t s) {
   } else if (ck >= 0) {
     a.w = c.w->d16;
     const int nz = c.nclass * c.sl.count;
-    if (ck == 0) tile_dispatch<0>(a, gxv, gyv, nz, c.mode, s, ps);
-    else if (ck == 1) tile_dispatch<1>(a, gxv, gyv, nz, c.mode, s, ps);
-    else tile_dispatch<2>(a, gxv, gyv, nz, c.mode, s, ps);
+    if (ck == 0) tile_dispatch<0>(a, gxv, gyv, nz, c.mode, c.in16 != 0, c.t16 != 0, s, ps);
+    else if (ck == 1) tile_dispatch<1>(a, gxv, gyv, nz, c.mode, c.in16 != 0, c.t16 != 0, s, ps);
+    else tile_dispatch<2>(a, gxv, gyv, nz, c.mode, false, false, s, ps);
   } else if (lds_ok) {
     const int rows = ksplit ? 16 : 64;
     const int width = gxv >= rows ? rows : gxv;
@@ -1584,13 +1670,13 @@ namespace {
 // no instantiation (the 16-pixel kernels run instead).
 template <int DPT>
 bool lift_slot_go(const Target& T, const Model& m, const double* v, const double* vs, float* f0,
-                  const float* ainv, float* t0, hipStream_t s) {
+                  const float* ainv, float* t0, bool t16, hipStream_t s) {
   const Operator& op = *T.op;
   const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(T.sl.count));
   const size_t lds = std::max(size_t(op.ndir) * 64, size_t(64) * (m.c0 + 1)) * sizeof(float);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, vs, T.arr.sT32, T.arr.sA32, T.arr.dc32,
-                       T.arr.Sdiag32, m.d_w_in_p, f0, ainv, t0, op.ndir, op.cells);
+                       T.arr.Sdiag32, m.d_w_in_p, f0, ainv, t0, op.ndir, op.cells, t16 ? 1 : 0);
   };
   switch (m.c0 / 4) {
     case 4: go(lift_slot_kernel<4, DPT>); return true;
@@ -1636,10 +1722,11 @@ bool by_budget(int N, F&& f) {
 }  // namespace
 
 void launch_lift(const Target& T, const Model& m, const double* v, const double* vs, float* f0,
-                 const float* ainv, float* t0, hipStream_t s) {
+                 const float* ainv, float* t0, bool t16, hipStream_t s) {
   const Operator& op = *T.op;
-  if (m.d_w_in_p &&
-      by_budget(op.ndir, [&](auto b) { return lift_slot_go<decltype(b)::value>(T, m, v, vs, f0, ainv, t0, s); })) {
+  if (m.d_w_in_p && by_budget(op.ndir, [&](auto b) {
+        return lift_slot_go<decltype(b)::value>(T, m, v, vs, f0, ainv, t0, t16, s);
+      })) {
     RTE_HIP(hipGetLastError());
     return;
   }
@@ -1647,7 +1734,7 @@ void launch_lift(const Target& T, const Model& m, const double* v, const double*
   RTE_REQUIRE(lds <= 64 * 1024, RTE_EINVAL, "lift tile does not fit in LDS");
   const dim3 grid(unsigned((op.cells + PT - 1) / PT), 1, unsigned(T.sl.count));
   hipLaunchKernelGGL(lift_kernel, grid, dim3(256), lds, s, T.sl, v, vs, T.arr.sT32, T.arr.sA32, T.arr.dc32,
-                     T.arr.Sdiag32, m.d_w_in, f0, ainv, t0, op.ndir, m.c0, op.cells);
+                     T.arr.Sdiag32, m.d_w_in, f0, ainv, t0, op.ndir, m.c0, op.cells, t16 ? 1 : 0);
   RTE_HIP(hipGetLastError());
 }
 
@@ -1687,9 +1774,10 @@ namespace {
 dim3 ew_grid3(int64_t n, const Slots& sl) { return dim3(ew_grid(n), 1, unsigned(sl.count)); }
 }  // namespace
 
-void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count,
+void launch_scale_fields(const Slots& sl, const float* ainv, const float* f, float* t, int64_t count, bool t16,
                          hipStream_t s) {
-  hipLaunchKernelGGL(scale_fields_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, ainv, f, t, count);
+  hipLaunchKernelGGL(scale_fields_kernel, ew_grid3(count, sl), dim3(256), 0, s, sl, ainv, f, t, count,
+                     t16 ? 1 : 0);
   RTE_HIP(hipGetLastError());
 }
 

@@ -50,6 +50,21 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
   auto dims = [&](int l, int d[3]) {
     for (int a = 0; a < 3; ++a) d[a] = op.level_dim(l, a);
   };
+  // tb[l]: t_l is stored as bfloat16 (it only ever feeds convolutions, which
+  // round it to bfloat16 when staging anyway).  That needs every producer and
+  // consumer of t_l on the tiled 2D kernel: the level's 3x3 convolutions, the
+  // restriction into it (which writes t_l) and the one out of it (which reads
+  // t_l); the lift and the pointwise scaling write either form.
+  // RTE_T_BF16=0 keeps every t in FP32 (for comparisons: the results are
+  // bitwise the same).
+  const char* tenv = std::getenv("RTE_T_BF16");
+  const bool t16_ok = kind == MFMA_BF16 && op.dim == 2 && !(tenv && tenv[0] == '0');
+  auto tiled3 = [&](int l) {
+    return C[l] % 32 == 0 && op.level_dim(l, 0) % 8 == 0 && op.level_dim(l, 1) % 8 == 0;
+  };
+  std::vector<bool> tb(L, false);
+  for (int l = 0; l < L; ++l)
+    tb[l] = t16_ok && tiled3(l) && (l == 0 || tiled3(l - 1)) && (l == L - 1 || tiled3(l + 1));
   auto conv_same = [&](int l, const float* in, const ConvW& w, float* out, int mode) {
     ConvLaunch c{};
     int d[3];
@@ -58,6 +73,8 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
     c.sl = sl;
     c.in = in; c.cin = w.cin; c.w = &w; c.out = out; c.cout = w.cout; c.mode = mode;
     c.f = f[l]; c.a = T.arr.fa[l]; c.ainv = T.arr.fainv[l];
+    c.in16 = tb[l] && (mode == CONV_STORE || mode == CONV_ACCUM);  // the input is t_l
+    c.t16 = tb[l] && (mode == CONV_RESID_T || mode == CONV_RESID_R);  // the output is t_l
     launch_conv(c, kind, s);
   };
   // uz[l]: u_l is still zero; tready[l]: t_l already holds a^{-1} (.) f_l,
@@ -68,7 +85,7 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
   };
   auto smooth = [&](int l, const ConvW& B) {
     if (uz[l]) {
-      if (!tready[l]) launch_scale_fields(sl, T.arr.fainv[l], f[l], t[l], P[l] * C[l], s);
+      if (!tready[l]) launch_scale_fields(sl, T.arr.fainv[l], f[l], t[l], P[l] * C[l], tb[l], s);
       tready[l] = false;
       conv_same(l, t[l], B, u[l], CONV_STORE);
       uz[l] = false;
@@ -79,7 +96,7 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
   };
 
   const bool want0 = first_steps(0) > 0;
-  launch_lift(T, m, v, vscale, f[0], want0 ? T.arr.fainv[0] : nullptr, want0 ? t[0] : nullptr, s);
+  launch_lift(T, m, v, vscale, f[0], want0 ? T.arr.fainv[0] : nullptr, want0 ? t[0] : nullptr, tb[0], s);
   tready[0] = want0;
   for (int l = 0; l < L - 1; ++l) {
     uz[l] = true;
@@ -99,6 +116,8 @@ void precond_apply(const Target& T, const Model& m, int kind, const double* v, f
     c.mode = want ? CONV_STORE_T : CONV_STORE;
     c.out2 = want ? t[l + 1] : nullptr;
     c.ainv = T.arr.fainv[l + 1];
+    c.in16 = tb[l] && !uz[l];       // the input is t_l (else f_l)
+    c.t16 = tb[l + 1] && want;      // out2 is t_{l+1}
     launch_conv(c, kind, s);
     tready[l + 1] = want;
   }
