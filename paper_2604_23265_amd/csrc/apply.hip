@@ -2,7 +2,8 @@
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
 // Three kernels: apply_mfma_kernel (below) for the FP32 apply with 64 or
-// 96 directions, the scatter on the FP32 matrix cores; apply_slot_kernel
+// 96 directions, the scatter on the BF16 matrix cores as a three-term split
+// product with FP32 accuracy; apply_slot_kernel
 // (below) for the other FP32 applies, one direction slot per wave; and
 // apply_kernel for the FP64 apply and the FP64 residual, described here.
 //
@@ -23,6 +24,8 @@ namespace rte {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
 // A block of 256 threads owns TL consecutive cells: thread t -> cell t % TL,
 // direction slot t / TL (256 / TL slots).  TL = 64 (one slot per wave) for
@@ -323,30 +326,37 @@ void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   RTE_HIP(hipGetLastError());
 }
 
-// FP32 apply with the scatter on the matrix cores, for N a multiple of 16
+// FP32 apply with the scatter on the matrix cores, for N a multiple of 32
 // and whole 64-cell tiles: the block has N / 16 waves and wave w owns
 // directions 16 w .. 16 w + 15 of each tile.  The scatter (S x)^T for them
-// is a [16 x N] x [N x 16] product per 16 cells, run with the 16x16x4
-// FP32 MFMA: the A operand, the wave's rows of S, stays in N / 4
-// registers per lane; the B operand is the tile of x in LDS.  The D layout
-// (direction 4 (l / 16) + r, cell l % 16) gives each group of 16 lanes 16
-// consecutive cells of one direction, so the streaming part reads and
-// writes coalesced rows.
+// is a [16 x N] x [N x 16] product per 16 cells; the D layout (direction
+// 4 (l / 16) + r, cell l % 16) gives each group of 16 lanes 16 consecutive
+// cells of one direction, so the streaming part reads and writes coalesced
+// rows.  A block walks several tiles (the XCD running it takes a contiguous
+// range) and requests the next tile's x into registers before the current
+// tile's work.
 //
-// A block walks several tiles (the XCD running it takes a contiguous
-// range), requests the next tile's x into registers before the current
-// tile's MFMAs and stores, and loads S and the per-direction data once.
-// Measured at 512^2 x 64 directions: the HBM bytes (counters) equal the
-// algorithmic ones, yet the kernel reaches about a third of the HBM rate
-// and a quarter of the FP32 matrix rate; what bounds it is not settled.
-template <class TO, bool D3, int NN>
-__global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const float* __restrict__ x,
-                                                            TO* __restrict__ y, const float* __restrict__ sT,
-                                                            const float* __restrict__ sA,
-                                                            const float* __restrict__ S,
-                                                            const float* __restrict__ dc,
-                                                            const int* __restrict__ sg, int nx, int ny, int nz,
-                                                            int cells) {
+// The product is a three-term bfloat16 split on the BF16 matrix cores
+// (16x16x32, sixteen times the FP32 matrix rate):
+// x = x0 + x1 + x2 and S = S0 + S1 + S2, each term the bfloat16 rounding of
+// what the previous ones leave, so the three terms hold 24 bits of the value
+// and leave at most 2^-27 of it.  S x is accumulated in FP32 from the six
+// products Si xj with i + j <= 2, per k-step in the order S0 x2, S1 x1, S0 x1,
+// S2 x0, S1 x0, S0 x0 (the small ones first); the three dropped products are
+// below 2^-26 of |S| |x|, under FP32 rounding.  The block splits the x tile once,
+// into three bfloat16 planes [cell][direction] (rows padded by 8 so that the
+// 16-byte fragment reads of 16 cells hit disjoint banks); each wave splits
+// its rows of S once.  The streaming term is formed before the scatter, from
+// x at the lane's cells and their upwind neighbours read from global memory
+// (the tile was just fetched: L2).
+template <class TO, bool D3, int NN, int MINW>
+__global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, const float* __restrict__ x,
+                                                             TO* __restrict__ y, const float* __restrict__ sT,
+                                                             const float* __restrict__ sA,
+                                                             const float* __restrict__ S,
+                                                             const float* __restrict__ dc,
+                                                             const int* __restrict__ sg, int nx, int ny, int nz,
+                                                             int cells) {
   SlotBase bs;
   if (!slot_open(sl, blockIdx.z, bs)) return;
   x = at(x, bs.ws + bs.dx);
@@ -356,16 +366,14 @@ __global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const floa
   S = at(S, bs.op);
   dc = at(dc, bs.op);
   sg = at(sg, bs.op);
-  constexpr int KS = NN / 4;        // k-steps of the MFMA
+  constexpr int KS = NN / 32;       // k-steps of the MFMA (32 directions each)
   constexpr int NT = NN * 4;        // threads: NN / 16 waves
-  constexpr int XP = NN * 16 / NT;  // float4 pieces of a tile per thread (4)
+  constexpr int LDR = NN + 8;       // plane row: the directions of one cell, padded
   constexpr int NA = D3 ? 3 : 2;
-  __shared__ float xs[NN * 64];  // [N][64] x tile
+  __shared__ uint16_t xp[3][64 * LDR];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int li = lane & 15, grp = lane >> 4;
-  // tiles of this block: with 8 | ntile and 8 | gridDim.x, block b runs on
-  // XCD b % 8, which takes tiles [k ntile / 8, (k + 1) ntile / 8)
   const int ntile = cells / 64;
   const int G = int(gridDim.x);
   int t0, tstep, tend;
@@ -381,12 +389,30 @@ __global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const floa
   }
   if (t0 >= tend) return;
 
-  // the wave's rows of S: lane l holds S[16 w + l % 16][4 s + l / 16]
-  float sa_reg[KS];
-  const float* __restrict__ srow = S + (16 * wave + li) * NN + grp;
+  // split of one value into three bfloat16 terms
+  auto split3 = [](float v, uint16_t& h0, uint16_t& h1, uint16_t& h2) {
+    const __bf16 b0 = __bf16(v);
+    const float r1 = v - float(b0);
+    const __bf16 b1 = __bf16(r1);
+    const float r2 = r1 - float(b1);
+    const __bf16 b2 = __bf16(r2);
+    h0 = __builtin_bit_cast(uint16_t, b0);
+    h1 = __builtin_bit_cast(uint16_t, b1);
+    h2 = __builtin_bit_cast(uint16_t, b2);
+  };
+  // the wave's rows of S as A operands: lane l holds S[16 w + l % 16][32 ks + 8 (l / 16) + e]
+  v8bf sa[3][KS];
 #pragma unroll
-  for (int k = 0; k < KS; ++k) sa_reg[k] = srow[4 * k];
-  // this lane's output directions m_r = 16 w + 4 (l / 16) + r
+  for (int ks = 0; ks < KS; ++ks) {
+    const float* __restrict__ srow = S + (16 * wave + li) * NN + 32 * ks + 8 * grp;
+    uint16_t h[3][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) split3(srow[e], h[0][e], h[1][e], h[2][e]);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sa[p][ks][e] = __builtin_bit_cast(__bf16, h[p][e]);
+  }
   float dcv[4][NA];
   int sgv[4][NA];
 #pragma unroll
@@ -399,40 +425,37 @@ __global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const floa
     }
   const int ext[3] = {nx, ny, nz};
   const int stride[3] = {1, nx, nx * ny};
-  // per output direction: its row of x and y, and its neighbour offsets
   int64_t rowb[4];
-  int offn[4][NA];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    rowb[r] = int64_t(16 * wave + 4 * grp + r) * cells;
-#pragma unroll
-    for (int a = 0; a < NA; ++a) offn[r][a] = sgv[r][a] * stride[a];
-  }
+  for (int r = 0; r < 4; ++r) rowb[r] = int64_t(16 * wave + 4 * grp + r) * cells;
   const bool row_tiles = (nx & 63) == 0;
 
-  v4f rx[XP];
+  // staging: thread (g, q) takes directions 4 g .. 4 g + 3 of cells 4 q .. 4 q + 3
+  const int sg4 = int(threadIdx.x) >> 4, sq = int(threadIdx.x) & 15;
+  v4f rx[4];
   auto load_x = [&](int tile) {
 #pragma unroll
-    for (int i = 0; i < XP; ++i) {
-      const int idx = int(threadIdx.x) + NT * i;
-      const int m = idx >> 4, q = idx & 15;
-      rx[i] = *reinterpret_cast<const v4f*>(x + int64_t(m) * cells + tile * 64 + 4 * q);
-    }
+    for (int i = 0; i < 4; ++i)
+      rx[i] = *reinterpret_cast<const v4f*>(x + int64_t(4 * sg4 + i) * cells + tile * 64 + 4 * sq);
   };
   load_x(t0);
   for (int tile = t0; tile < tend; tile += tstep) {
     const int c0 = tile * 64;
-    if (tile != t0) __syncthreads();  // the previous tile's reads of xs are done
+    if (tile != t0) __syncthreads();  // the previous tile's reads of the planes are done
 #pragma unroll
-    for (int i = 0; i < XP; ++i) {
-      const int idx = int(threadIdx.x) + NT * i;
-      *reinterpret_cast<v4f*>(xs + (idx >> 4) * 64 + 4 * (idx & 15)) = rx[i];
+    for (int j = 0; j < 4; ++j) {  // cell 4 sq + j: four directions per plane, 8 bytes each
+      uint16_t h[3][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) split3(rx[i][j], h[0][i], h[1][i], h[2][i]);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const v2u w = v2u{uint32_t(h[p][0]) | (uint32_t(h[p][1]) << 16), uint32_t(h[p][2]) | (uint32_t(h[p][3]) << 16)};
+        *reinterpret_cast<v2u*>(&xp[p][(4 * sq + j) * LDR + 4 * sg4]) = w;
+      }
     }
-    // cell data and upwind neighbours of the lane's 4 cells (one per
-    // 16-cell sub-tile) in its 4 directions; out-of-grid neighbours are
-    // zero.  When 64 divides nx the tile lies in one grid row, so its row
-    // and layer indices are uniform (no per-lane division).
-    float st[4], sav[4], xnb[4][4][NA];
+    // the streaming term and x at the lane's cells, formed before the
+    // scatter so that the neighbours' registers are free during it
+    float st[4], sav[4], xcv[4][4], str[4][4];
     int ti0 = 0, tj = 0, tk = 0;
     if (row_tiles) {
       const int rr = c0 / nx;
@@ -459,41 +482,52 @@ __global__ __launch_bounds__(NN * 4) void apply_mfma_kernel(Slots sl, const floa
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t o = rowb[r] + c;
+        float nb[NA];
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-          const int p = pos[a] - sgv[r][a];
-          const bool inb = unsigned(p) < unsigned(ext[a]);
-          const float v = x[inb ? o - offn[r][a] : o];
-          xnb[u][r][a] = inb ? v : 0.f;
+          const int pp = pos[a] - sgv[r][a];
+          const bool inb = unsigned(pp) < unsigned(ext[a]);
+          const float v = x[inb ? o - sgv[r][a] * stride[a] : o];
+          nb[a] = inb ? v : 0.f;
         }
+        const float xc = x[o];
+        float sr = 0.f;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) sr += dcv[r][a] * (xc - nb[a]);
+        xcv[u][r] = xc;
+        str[u][r] = sr;
       }
     }
     if (tile + tstep < tend) load_x(tile + tstep);  // in flight during this tile's work
     __syncthreads();
-    // (S x)^T for the wave's 16 directions and the tile's 4 x 16 cells
-    // k outermost: the four sub-tiles' accumulators are independent, so
-    // consecutive MFMAs do not wait on each other's results
     v4f acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    // per k-step and x term (x2, x1, x0): its fragments read once from LDS,
+    // then its products with S0 .. S(2 - term), so the six products run
+    // smallest first; u innermost so that consecutive MFMAs do not wait on
+    // each other's results
 #pragma unroll
-    for (int k = 0; k < KS; ++k)
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        acc[u] =
-            __builtin_amdgcn_mfma_f32_16x16x4f32(sa_reg[k], xs[(4 * k + grp) * 64 + 16 * u + li], acc[u], 0, 0, 0);
+      for (int p = 2; p >= 0; --p) {
+        v8bf bx[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          bx[u] = *reinterpret_cast<const v8bf*>(&xp[p][(16 * u + li) * LDR + 32 * ks + 8 * grp]);
+#pragma unroll
+        for (int q = 2 - p; q >= 0; --q)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sa[q][ks], bx[u], acc[u], 0, 0, 0);
+      }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = c0 + 16 * u + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = 16 * wave + 4 * grp + r;
-        const float xc = xs[m * 64 + 16 * u + li];
-        float str = 0.f;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) str += dcv[r][a] * (xc - xnb[u][r][a]);
-        const float sx = acc[u][r];
-        y[rowb[r] + c] = TO(str + st[u] * (xc - sx) + sav[u] * sx);
+        const float xc = xcv[u][r], sx = acc[u][r];
+        y[rowb[r] + c] = TO(str[u][r] + st[u] * (xc - sx) + sav[u] * sx);
       }
     }
   }
@@ -523,9 +557,13 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   };
   // 64 and 96 directions: at 32 the vector kernel is as fast per launch
   // and faster in the serving stream's small batches (measured)
+  // waves per SIMD the register budget is cut to: three in 2D (no spills);
+  // two in 3D, whose three upwind neighbours per value would spill at three
+  // (measured at 64^3 x 96: 95 us at two, 114 us at three)
+  constexpr int MW = D3 ? 2 : 3;
   switch (op.ndir) {
-    case 64: launch(apply_mfma_kernel<TO, D3, 64>, 64); return true;
-    case 96: launch(apply_mfma_kernel<TO, D3, 96>, 96); return true;
+    case 64: launch(apply_mfma_kernel<TO, D3, 64, MW>, 64); return true;
+    case 96: launch(apply_mfma_kernel<TO, D3, 96, MW>, 96); return true;
     default: return false;
   }
 }

@@ -555,6 +555,30 @@ def test_full_size_apply_and_vcycle(name):
 
 
 @pytest.mark.parametrize("name", list(FULL))
+def test_full_size_apply_near_isotropic(name):
+    """The cancellation case of the collision term: x = 1 + 1e-3 noise makes x - Sx a thousand
+    times smaller than x, so the FP32 apply is compared element by element against the size
+    of its terms (streaming |u|/h (|x| + max |x|), sT (|x| + |S||x|), sA |S||x|) rather than
+    against y itself; FP32 sums of at most 96 such terms round within about 1e-6 of it."""
+    say("case %s full apply, near-isotropic x" % name)
+    prob, model, op, P = full_case(name)
+    D = P.D
+    rng = np.random.default_rng(37)
+    x32 = (1.0 + 1e-3 * rng.standard_normal(D.n)).astype(np.float32)
+    x = x32.astype(np.float64)
+    y = host(op.apply(dev(x32, "float32"))).astype(np.float64)
+    ref = P.apply(x)
+    xg = np.abs(x.reshape(D.N, -1))
+    sx = np.abs(D.S) @ xg
+    coef = np.sum(np.abs(D.dirs[:, list(D.axes)]), axis=1)[:, None] / D.h
+    st, sa = D.sT.reshape(1, -1), D.sA.reshape(1, -1)
+    scale = (coef * (xg + xg.max()) + st * (xg + sx) + sa * sx).reshape(-1)
+    err = np.abs(y - ref) / scale
+    say("  worst |gpu - oracle| / terms = %.2e (max |y| / terms %.2e)" % (err.max(), np.max(np.abs(ref) / scale)))
+    assert err.max() <= 1e-6
+
+
+@pytest.mark.parametrize("name", list(FULL))
 def test_full_size_bounded_solve_reports_the_oracle_residual(name):
     say("case %s full bounded solve" % name)
     prob, model, op, P = full_case(name)
