@@ -61,9 +61,10 @@ enum { RTE_FP32 = 0, RTE_FP64 = 1 };
  * MgNet with FP32 MFMA convolutions (FP32 accumulation in both), or the
  * cell-wise Block-Jacobi comparator of the paper's experiments (Sec. 4):
  * per cell the N x N block of L coupling that cell's directions,
- * diag_m(sum_a |u_{m,a}|/h) + sT_c I - sS_c S, solved in FP32 (up to 64
- * directions; no model needed). */
+ * diag_m(sum_a |u_{m,a}|/h) + sT_c I - sS_c S, solved in FP32 (up to
+ * RTE_BJ_MAX_DIRS directions; no model needed). */
 enum { RTE_PC_NONE = 0, RTE_PC_MGNET_BF16 = 1, RTE_PC_MGNET_FP32 = 2, RTE_PC_BLOCK_JACOBI = 3 };
+enum { RTE_BJ_MAX_DIRS = 112 };
 
 typedef struct rte_operator rte_operator;
 typedef struct mgnet_model mgnet_model;
@@ -233,8 +234,8 @@ rte_status rte_atfps_filtered_loss(const rte_atfps* a, const double* psi, double
  * Block-Jacobi solve (RTE_PC_BLOCK_JACOBI; model, workspace may be NULL).
  * v: device double [n]; z: device float [n].  The workspace (device memory
  * of at least rte_precond_workspace_bytes) holds the level activations.
- * Errors: RTE_EINVAL (no fields built, model mismatch, more than 64
- * directions for Block-Jacobi), RTE_ENOMEM (small workspace). */
+ * Errors: RTE_EINVAL (no fields built, model mismatch, more than
+ * RTE_BJ_MAX_DIRS directions for Block-Jacobi), RTE_ENOMEM (small workspace). */
 rte_status rte_precond_workspace_bytes(const rte_operator* op, const mgnet_model* model,
                                        size_t* bytes);
 rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, int precond,

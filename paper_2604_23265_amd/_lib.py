@@ -13,6 +13,7 @@ HG_AUTO, HG_FLATLAND, HG_SPHERE = 0, 1, 2
 SCHEME_UPWIND, SCHEME_TFPS = 0, 1
 FP32, FP64 = 0, 1
 PC_NONE, PC_MGNET_BF16, PC_MGNET_FP32, PC_BLOCK_JACOBI = 0, 1, 2, 3
+BJ_MAX_DIRS = 112
 ARR_RHS, ARR_SCATTER, ARR_SIGMA, ARR_FIELD_A, ARR_FIELD_AINV = 0, 1, 2, 3, 4
 K_APPLY, K_RESIDUAL, K_CONV, K_ORTH, K_PRECOND = 0, 1, 2, 3, 4
 W_A, W_BPRE, W_BPOST, W_BCOARSE, W_R, W_PR = 0, 1, 2, 3, 4, 5

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librte.so")
 SOURCES = ["abi.cpp", "setup.cpp", "mgn1.cpp", "solver.cpp", "serve.cpp",
            "apply.hip", "mgnet.hip", "krylov.hip", "noalloc.hip",
-           "tfps.hip", "tfps_setup.cpp", "atfps_setup.cpp"]
+           "tfps.hip", "tfps_setup.cpp", "atfps_setup.cpp", "block_jacobi.hip"]
 ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Wno-unused-function", "-Wno-unused-variable",

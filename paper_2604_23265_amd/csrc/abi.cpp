@@ -378,7 +378,7 @@ rte_status rte_precond_apply(const rte_operator* h, const mgnet_model* model, in
     const Operator& o = *h->op;
     RTE_REQUIRE(o.scheme == RTE_SCHEME_UPWIND, RTE_EINVAL, "the preconditioners act on the upwind scheme");
     if (precond == RTE_PC_BLOCK_JACOBI) {
-      RTE_REQUIRE(o.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
+      RTE_REQUIRE(o.ndir <= RTE_BJ_MAX_DIRS, RTE_EINVAL, "Block-Jacobi supports up to 112 directions");
       launch_block_jacobi(Target::single(o), v, nullptr, z, S(stream));
       return;
     }

@@ -666,116 +666,3 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
 }
 
 }  // namespace rte
-
-// ------------------------------------------------------- Block-Jacobi ---
-// z_c = B_c^{-1} v_c for every cell c, with B_c the N x N block of L that
-// couples the cell's directions:
-//   B_c = diag_m(sum_a |u_{m,a}| / h) + sT_c (I - S) + sA_c S
-// (sT - sS = sA: the cancellation-free form the apply uses).  B_c is
-// diagonally dominant (row sums of S are 1), so Gaussian elimination needs
-// no pivoting.  A group of NB lanes solves one cell: lane i holds row i of
-// B_c (S row i kept in registers across cells) and v_i; the pivot row is
-// broadcast with lane shuffles.  Rows i >= N are identity padding.  The
-// block stages v for 64 cells in LDS (coalesced), each wave solves 16 of
-// them, and the results leave through the same LDS tile.
-namespace rte {
-namespace {
-
-template <int NB>
-__global__ __launch_bounds__(256) void block_jacobi_kernel(Slots sl, const double* __restrict__ v,
-                                                           const double* __restrict__ vs,
-                                                           const float* __restrict__ sT,
-                                                           const float* __restrict__ sA,
-                                                           const float* __restrict__ S,
-                                                           const float* __restrict__ dc, float* __restrict__ z,
-                                                           int N, int cells) {
-  SlotBase bs;
-  if (!slot_open(sl, blockIdx.z, bs)) return;
-  v = at(v, bs.ws + bs.dx);
-  z = at(z, bs.ws + bs.dy);
-  const double vsc = vs ? at(vs, bs.ws)[0] : 1.0;
-  sT = at(sT, bs.op);
-  sA = at(sA, bs.op);
-  S = at(S, bs.op);
-  dc = at(dc, bs.op);
-  extern __shared__ float xs[];  // [N][64]
-  const int c0 = int(blockIdx.x) * 64;
-  for (int idx = threadIdx.x; idx < N * 64; idx += 256) {
-    const int m = idx >> 6, cc = c0 + (idx & 63);
-    const double val = v[int64_t(m) * cells + (cc < cells ? cc : cells - 1)];
-    xs[idx] = cc < cells ? float(val * vsc) : 0.f;
-  }
-  __syncthreads();
-  constexpr int G = 64 / NB;  // cells per wave per pass
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int i = lane % NB;            // row of B_c
-  const int base = lane - i;          // first lane of the group
-  const int grp = lane / NB;
-  const bool real = i < N;
-  const int ic = real ? i : N - 1;
-  float srow[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) srow[j] = (real && j < N) ? S[ic * N + j] : 0.f;
-  const float di = dc[4 * ic + 3];
-  for (int pass = 0; pass < 16 / G; ++pass) {
-    const int cl = wave * 16 + pass * G + grp;   // cell within the tile
-    const int c = c0 + cl;
-    const int cc = c < cells ? c : cells - 1;
-    const float t = sT[cc], a_ = sA[cc];
-    float a[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const float e = j == i ? 1.f : 0.f;
-      a[j] = real ? t * (e - srow[j]) + a_ * srow[j] + e * di : e;
-    }
-    float r = real ? xs[i * 64 + cl] : 0.f;
-    // forward elimination
-#pragma unroll
-    for (int k = 0; k < NB - 1; ++k) {
-      const float pkk = __shfl(a[k], base + k, 64);
-      const float l = i > k ? a[k] / pkk : 0.f;
-#pragma unroll
-      for (int j = k + 1; j < NB; ++j) a[j] -= l * __shfl(a[j], base + k, 64);
-      r -= l * __shfl(r, base + k, 64);
-    }
-    // back substitution: lane k's unknown is r_k / a_kk once rows below are done
-    float x = 0.f;
-#pragma unroll
-    for (int k = NB - 1; k >= 0; --k) {
-      const float xk = __shfl(r / a[k], base + k, 64);
-      if (i == k) x = xk;
-      if (i < k) r -= a[k] * xk;
-    }
-    if (real) xs[i * 64 + cl] = x;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < N * 64; idx += 256) {
-    const int m = idx >> 6, cc = c0 + (idx & 63);
-    if (cc < cells) z[int64_t(m) * cells + cc] = xs[idx];
-  }
-}
-
-}  // namespace
-
-void launch_block_jacobi(const Target& T, const double* v, const double* vscale, float* z, hipStream_t s) {
-  const Operator& op = *T.op;
-  RTE_REQUIRE(op.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
-  ProfScope ps(RTE_K_PRECOND, s);
-  const dim3 grid(unsigned((op.cells + 63) / 64), 1, unsigned(T.sl.count));
-  const size_t lds = size_t(op.ndir) * 64 * sizeof(float);
-  const OpArrays& A = T.arr;
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, T.sl, v, vscale, A.sT32, A.sA32, A.S32, A.dc32, z, op.ndir,
-                       int(op.cells));
-  };
-  if (op.ndir <= 16)
-    go(block_jacobi_kernel<16>);
-  else if (op.ndir <= 32)
-    go(block_jacobi_kernel<32>);
-  else
-    go(block_jacobi_kernel<64>);
-  RTE_HIP(hipGetLastError());
-}
-
-}  // namespace rte

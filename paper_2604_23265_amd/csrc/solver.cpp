@@ -305,7 +305,7 @@ void validate_opts(const Operator& op, const Model* m, const rte_solve_opts* o) 
     RTE_REQUIRE(o->precond == RTE_PC_NONE, RTE_EINVAL,
                 "the TFPS operator is solved without a preconditioner (MgNet and Block-Jacobi act on the upwind scheme)");
   if (o->precond == RTE_PC_BLOCK_JACOBI)
-    RTE_REQUIRE(op.ndir <= 64, RTE_EINVAL, "Block-Jacobi supports up to 64 directions");
+    RTE_REQUIRE(op.ndir <= RTE_BJ_MAX_DIRS, RTE_EINVAL, "Block-Jacobi supports up to 112 directions");
   if (o->precond == RTE_PC_MGNET_BF16 || o->precond == RTE_PC_MGNET_FP32) {
     RTE_REQUIRE(m != nullptr, RTE_EINVAL, "MgNet preconditioning needs a model");
     RTE_REQUIRE(op.model == m, RTE_EINVAL, "operator was not built with this model (CoeffNet fields missing)");

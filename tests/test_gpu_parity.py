@@ -230,6 +230,40 @@ def test_block_jacobi(name):
     assert err < tol
 
 
+WIDE_BJ = {
+    "3d_96dir": lambda: problems.make(dim=3, n=6, ndir=96, g=0.7, eps=0.05, kind="sphere", inflow="random", seed=61),
+    "2d_80dir": lambda: problems.make(n=12, ndir=80, g=0.8, eps=0.2, inflow="left", seed=62),
+    "2d_112dir": lambda: problems.make(n=8, ndir=112, g=0.5, eps=0.2, inflow="random", seed=63),
+}
+
+
+@pytest.mark.parametrize("name", list(WIDE_BJ))
+def test_block_jacobi_beyond_64_directions(name):
+    """The one-wave-per-cell Block-Jacobi (65 to 112 directions, the block in LDS) against the
+    oracle's FP64 cell solves, with the tolerance of test_block_jacobi; then an FGMRES solve
+    preconditioned by it against the oracle's solution."""
+    say("case", name, "wide block-jacobi")
+    torch_cuda()
+    from paper_2604_23265_amd import api
+    from oracle import comparators
+    prob = WIDE_BJ[name]()
+    op = api.Operator(prob)
+    P = osolve.Problem(prob)
+    v = np.random.default_rng(6).standard_normal(P.D.n)
+    z = host(op.precond(None, dev(v), mode="bj")).astype(np.float64)
+    ref = P.block_jacobi(v)
+    kappa = float(np.linalg.cond(comparators.cell_blocks(P.D)).max())
+    tol = max(1e-5, 4 * kappa * 2.0 ** -24)
+    err, em = rel(z, ref), rel_max(z, ref)
+    say("  block-jacobi rel err %.3e max-norm %.3e cond %.1f tol %.1e" % (err, em, kappa, tol))
+    assert err < tol and em < 10 * tol
+    x, st = op.solve(precond="bj", rtol=1e-9, restart=30, max_iters=3000)
+    assert st["converged"] == 1
+    xr = reference_solution(P)
+    say("  bj solve: %d iterations, solution rel err %.3e" % (st["iterations"], rel(host(x), xr)))
+    assert rel(host(x), xr) < 1e-6
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("mode", ["none", "fp32", "bf16", "bj"])
 def test_solve_matches_reference(name, mode):
