@@ -346,6 +346,91 @@ def large_leg(args, api, L, torch, configs, weights):
     return out
 
 
+def discretisation_leg(args, api, torch, configs):
+    """The paper's own discretisations on the C2 medium (32 directions, eps = 0.01, the first
+    GRF draw): the TFPS operator of Sec. 2.2 on 128^2 cells (build, y = A x, r = b - A x and
+    the cell-centre values, FP64) and the adaptive scheme's maps of Sec. 2.3 / 3.4 at
+    delta = 1e-2 on 64^2 cells (host build, compressed residual, layer reconstruction,
+    filtered loss; at 128^2 nearly every function is kept and the host build takes a minute)."""
+    def ev_time(fn, reps=20):
+        for _ in range(3):
+            fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e-3
+
+    log("discretisations: TFPS operator build, 128^2 cells x 32 directions")
+    prob = dict(configs.c2(0), scheme="tfps")
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    op = api.Operator(prob)
+    torch.cuda.synchronize()
+    build_tfps = time.perf_counter() - tb
+    n, cells, N = op.n, op.cells, op.ndir
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    r = torch.empty_like(x)
+    psi = torch.empty(N * cells, dtype=torch.float64, device="cuda")
+    t_apply = ev_time(lambda: op.apply(x, y))
+    t_res = ev_time(lambda: op.residual(x, r))
+    t_cv = ev_time(lambda: op.cell_values(x, psi))
+    # per unknown 8 B in and 8 B out (the residual also reads b); per cell its table id and sT;
+    # every distinct eigen-basis table (2N x N eigenvector entries and 2N eigenvalues, FP64)
+    # once -- on this medium every cell has its own ratio, so the tables dominate
+    tables = op.info["nbasis"] * 2 * N * (N + 1) * 8.0
+    b_apply = 16.0 * n + 12.0 * cells + tables
+    b_res = 24.0 * n + 12.0 * cells + tables
+    b_cv = 8.0 * n + 8.0 * N * cells + 12.0 * cells + tables
+    out = {"workload": "128x128 cells, 32 directions, eps=0.01, C2 medium (GRF seed 2000); TFPS unknowns "
+                       "2N per cell", "unknowns": int(n),
+           "tfps": {"build_ms": build_tfps * 1e3,
+                    "apply_us": t_apply * 1e6, "apply_GBs": b_apply / t_apply / 1e9,
+                    "apply_frac_hbm": b_apply / t_apply / 1e9 / HBM_PEAK_GBS,
+                    "residual_us": t_res * 1e6, "residual_GBs": b_res / t_res / 1e9,
+                    "cell_values_us": t_cv * 1e6, "cell_values_GBs": b_cv / t_cv / 1e9,
+                    "bases": int(op.info["nbasis"]), "basis_table_MB": tables / 1e6,
+                    "bytes": "the basis tables once, plus: apply 16 B per unknown + 12 B per cell; residual "
+                             "24 + 12; cell values 8 B per coefficient in, 8 B per value out"}}
+    op.close()
+    delta = 1e-2
+    log("discretisations: ATFPS build, 64^2 cells x 32 directions, delta %g" % delta)
+    prob = dict(configs.c2(0, n=64), scheme="tfps")
+    op = api.Operator(prob)
+    n, cells = op.n, op.cells
+    tb = time.perf_counter()
+    at = api.Atfps(op, delta)
+    build_at = time.perf_counter() - tb
+    log("discretisations: ATFPS maps timed")
+    psi = torch.randn(N * cells, dtype=torch.float64, device="cuda")
+    al = torch.randn(at.n_kept, dtype=torch.float64, device="cuda")
+    rr = torch.empty(at.n_rows, dtype=torch.float64, device="cuda")
+    coef = torch.empty(n, dtype=torch.float64, device="cuda")
+    rho = torch.empty(at.n_rows, dtype=torch.float64, device="cuda")
+    t_ar = ev_time(lambda: at.residual(al, rr))
+    t_rc = ev_time(lambda: at.reconstruct(al, coef))
+    t_fl = ev_time(lambda: at.filtered_loss(psi, rho))
+    # sparse rows: per stored entry its value, column and the gathered operand; per row its two
+    # offsets, the constant and the result.  The reconstruction and loss maps' entry counts are
+    # not exported; their rates are reported as time only.
+    b_ar = 20.0 * at.nnz + 32.0 * at.n_rows
+    out["atfps"] = {"workload": "64x64 cells, 32 directions, eps=0.01, C2 medium family (GRF seed 2000)",
+                    "delta": delta, "kept_unknowns": at.n_kept, "kept_fraction": at.n_kept / n,
+                    "compressed_nnz": at.nnz, "build_ms": build_at * 1e3,
+                    "residual_us": t_ar * 1e6, "residual_GBs": b_ar / t_ar / 1e9,
+                    "residual_frac_hbm": b_ar / t_ar / 1e9 / HBM_PEAK_GBS,
+                    "reconstruct_us": t_rc * 1e6, "filtered_loss_us": t_fl * 1e6,
+                    "bytes": "compressed residual: 20 B per stored entry + 32 B per row"}
+    at.close()
+    op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,6 +449,7 @@ def main():
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
     ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
     ap.add_argument("--no-large", action="store_true", help="skip the large single-solve kernel rates")
+    ap.add_argument("--no-tfps", action="store_true", help="skip the TFPS / ATFPS rates")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests of the C3 stream (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=16)
     ap.add_argument("--serving-arena-gb", type=int, default=32)
@@ -607,6 +693,8 @@ def main():
         out["serving"] = serving_leg(args, api, torch, configs, weights)
     if not args.no_large:
         out["large_single_solves"] = large_leg(args, api, L, torch, configs, weights)
+    if not args.no_tfps:
+        out["discretisations"] = discretisation_leg(args, api, torch, configs)
     if not args.no_cpu_baseline:
         log("cpu_baseline: oracle sample (~%.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(prob, blob, float(np.mean(its)), args.cpu_budget)

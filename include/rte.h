@@ -130,6 +130,8 @@ typedef struct {
   double h, g;
   int has_fields;         /* CoeffNet fields were built for a model              */
   int scheme;             /* RTE_SCHEME_*; n = 2 ndir cells for TFPS              */
+  int64_t nbasis;         /* TFPS: distinct per-cell eigen-bases (one per medium
+                             ratio), each 2 ndir (ndir + 1) doubles; else 0      */
 } rte_operator_info;
 
 /* Build the operator: validate inputs, form S, the scaled coefficients and

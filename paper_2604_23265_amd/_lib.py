@@ -42,7 +42,8 @@ class Medium(C.Structure):
 class OperatorInfo(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("ndir", C.c_int), ("kernel", C.c_int), ("cells", C.c_int64), ("n", C.c_int64),
-                ("h", C.c_double), ("g", C.c_double), ("has_fields", C.c_int), ("scheme", C.c_int)]
+                ("h", C.c_double), ("g", C.c_double), ("has_fields", C.c_int), ("scheme", C.c_int),
+                ("nbasis", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

@@ -228,6 +228,7 @@ rte_status rte_operator_get_info(const rte_operator* h, rte_operator_info* info)
     info->kernel = o.kernel; info->cells = o.cells; info->n = o.n; info->h = o.h; info->g = o.g;
     info->has_fields = o.model != nullptr;
     info->scheme = o.scheme;
+    info->nbasis = o.scheme == RTE_SCHEME_TFPS ? int64_t(o.nbasis) : 0;
   });
 }
 
@@ -319,6 +320,7 @@ rte_status rte_atfps_build(const rte_operator* h, double delta, rte_atfps** out)
     a->b = a->mem.upload(a->host.b);
     a->r0 = a->mem.upload(a->host.r0);
     a->c0 = a->mem.upload(a->host.c0);
+    a->part = a->mem.upload(std::vector<double>(size_t(kNorm2Parts), 0.0));
     *out = a.release();
   });
 }
@@ -360,7 +362,7 @@ rte_status rte_atfps_filtered_loss(const rte_atfps* a, const double* psi, double
     RTE_REQUIRE(!overlap(psi, int64_t(a->host.ndir) * a->host.cells, rho, a->host.n_rows), RTE_EINVAL,
                 "rte_atfps_filtered_loss: psi and rho overlap");
     launch_csr(a->M, psi, a->c0, true, rho, S(stream));
-    launch_norm2(rho, a->host.n_rows, loss, S(stream));
+    launch_norm2(rho, a->host.n_rows, a->part, loss, S(stream));
   });
 }
 

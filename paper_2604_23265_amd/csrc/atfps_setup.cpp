@@ -19,6 +19,8 @@
 // positive), then the dropped functions' eigenvectors scaled to max-norm 1.
 #include <algorithm>
 #include <cmath>
+#include <exception>
+#include <thread>
 
 #include "common.h"
 
@@ -177,6 +179,32 @@ std::vector<double> pseudo_inverse(int m, int n, const std::vector<double>& M) {
   return P;
 }
 
+// fn(i) for i in [0, count) on the host's threads (contiguous ranges; each
+// index writes only its own outputs); the first exception is rethrown.
+template <class F>
+void parallel_for(int64_t count, F fn) {
+  const int nthr = int(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(count / 64, 32),
+                                                              int64_t(std::thread::hardware_concurrency()))));
+  if (nthr <= 1) {
+    for (int64_t i = 0; i < count; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  std::vector<std::exception_ptr> err(static_cast<size_t>(nthr));
+  for (int t = 0; t < nthr; ++t)
+    th.emplace_back([&, t] {
+      try {
+        const int64_t b = count * t / nthr, e = count * (t + 1) / nthr;
+        for (int64_t i = b; i < e; ++i) fn(i);
+      } catch (...) {
+        err[size_t(t)] = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+
 void maxnorm_columns(int m, int n, std::vector<double>& V, bool fix_sign) {
   for (int k = 0; k < n; ++k) {
     double big = 0;
@@ -192,15 +220,6 @@ void maxnorm_columns(int m, int n, std::vector<double>& V, bool fix_sign) {
   }
 }
 
-struct Triplets {
-  std::vector<int64_t> r, c;
-  std::vector<double> v;
-  void add(int64_t i, int64_t j, double x) {
-    r.push_back(i);
-    c.push_back(j);
-    v.push_back(x);
-  }
-};
 
 }  // namespace
 
@@ -243,12 +262,31 @@ AtfpsHost atfps_build_host(const Operator& op, double delta) {
   for (int64_t c = 0; c < cells; ++c)
     for (size_t q = 0; q < kidx[size_t(c)].size(); ++q) kpos[size_t(c) * K + kidx[size_t(c)][q]] = int(q);
 
-  Triplets A, Rm;
+  // A is emitted row by row with ascending columns (each face's rows in turn; the
+  // cells of a face in index order, their kept functions ascending), so it is
+  // built in CSR form directly.  Each row of R belongs to one coefficient and
+  // is emitted in one piece (kept: the identity; dropped: by the face its
+  // function is centred on), so its pieces are recorded and joined in row order.
+  HostCsr& A = out.A;
+  A.ptr.assign(1, 0);
+  std::vector<int64_t> rcol;
+  std::vector<double> rval;
+  std::vector<int64_t> rbeg(size_t(cells) * K, -1), rlen(size_t(cells) * K, 0);
+  auto r_begin = [&](int64_t t) { rbeg[size_t(t)] = int64_t(rcol.size()); };
+  auto r_add = [&](int64_t t, int64_t col, double v) {
+    rcol.push_back(col);
+    rval.push_back(v);
+    rlen[size_t(t)] += 1;
+  };
   std::vector<double> bvec, r0(size_t(cells) * K, 0.0);
   // kept coefficients pass through the reconstruction unchanged
   for (int64_t c = 0; c < cells; ++c)
     for (size_t q = 0; q < kidx[size_t(c)].size(); ++q)
-      Rm.add(c * K + kidx[size_t(c)][q], off[size_t(c)] + int64_t(q), 1.0);
+    {
+      const int64_t t = c * K + kidx[size_t(c)][q];
+      r_begin(t);
+      r_add(t, off[size_t(c)] + int64_t(q), 1.0);
+    }
   int64_t row = 0;
   struct Part {
     int64_t cell;
@@ -298,9 +336,11 @@ AtfpsHost atfps_build_host(const Operator& op, double delta) {
           const double e = efac(pt.cell, k, pt.face);
           double v = 0;
           for (int r = 0; r < nr; ++r) v += Hi[size_t(p) * nr + r] * Lval(pt.cell, dirs[size_t(r)], k);
-          A.add(row + p, off[size_t(pt.cell)] + int64_t(q), pt.seq * v * e);
+          A.col.push_back(off[size_t(pt.cell)] + int64_t(q));
+          A.val.push_back(pt.seq * v * e);
         }
       }
+      A.ptr.push_back(int64_t(A.col.size()));
       double bv = 0;
       for (int r = 0; r < nr; ++r) bv += Hi[size_t(p) * nr + r] * rhs[size_t(r)];
       bvec.push_back(bv);
@@ -310,6 +350,7 @@ AtfpsHost atfps_build_host(const Operator& op, double delta) {
     for (int q = 0; q < ndf; ++q) {
       const int pq = nkf + q;
       const int64_t tgt = dropped[size_t(q)].first * K + dropped[size_t(q)].second;
+      r_begin(tgt);
       // interior: sign +1 on the other cell's smooth values, -1 on its own; boundary:
       // the inflow data minus the cell's smooth values
       for (const Part& pt : parts) {
@@ -319,7 +360,7 @@ AtfpsHost atfps_build_host(const Operator& op, double delta) {
           const int k = kc[qq];
           double v = 0;
           for (int r = 0; r < nr; ++r) v += Hi[size_t(pq) * nr + r] * Lval(pt.cell, dirs[size_t(r)], k);
-          Rm.add(tgt, off[size_t(pt.cell)] + int64_t(qq), s * v * efac(pt.cell, k, pt.face));
+          r_add(tgt, off[size_t(pt.cell)] + int64_t(qq), s * v * efac(pt.cell, k, pt.face));
         }
         double cs = 0;
         for (int r = 0; r < nr; ++r) cs += Hi[size_t(pq) * nr + r];
@@ -380,17 +421,32 @@ AtfpsHost atfps_build_host(const Operator& op, double delta) {
     }
   RTE_REQUIRE(row == nk, RTE_EINVAL, "ATFPS: compressed system is not square");
   out.n_rows = row;
-  out.A = csr_from(row, nk, A.r, A.c, A.v);
+  A.nrows = row;
+  A.ncols = nk;
   out.b = std::move(bvec);
-  out.R = csr_from(cells * K, nk, Rm.r, Rm.c, Rm.v);
+  {
+    HostCsr& R = out.R;
+    R.nrows = cells * K;
+    R.ncols = nk;
+    R.ptr.assign(1, 0);
+    R.col.reserve(rcol.size());
+    R.val.reserve(rval.size());
+    for (int64_t t = 0; t < cells * K; ++t) {
+      RTE_REQUIRE(rbeg[size_t(t)] >= 0, RTE_EINVAL, "ATFPS: a coefficient without a reconstruction row");
+      const int64_t b0 = rbeg[size_t(t)];
+      R.col.insert(R.col.end(), rcol.begin() + b0, rcol.begin() + b0 + rlen[size_t(t)]);
+      R.val.insert(R.val.end(), rval.begin() + b0, rval.begin() + b0 + rlen[size_t(t)]);
+      R.ptr.push_back(int64_t(R.col.size()));
+    }
+  }
   out.r0 = std::move(r0);
   // D_d per cell and M = A_d D_d, c0 = b_d - A_d d0 (psi direction-major [N][cells])
   std::vector<std::vector<double>> Pc(static_cast<size_t>(cells));
   std::vector<double> d0(size_t(nk), 0.0);
-  for (int64_t c = 0; c < cells; ++c) {
+  parallel_for(cells, [&](int64_t c) {
     const std::vector<int>& kc = kidx[size_t(c)];
     const int n = int(kc.size());
-    if (n == 0) continue;
+    if (n == 0) return;
     std::vector<double> Mc(size_t(N) * n);
     for (int m = 0; m < N; ++m)
       for (int q = 0; q < n; ++q) Mc[size_t(m) * n + q] = Lval(c, m, kc[size_t(q)]) * efac(c, kc[size_t(q)], 4);
@@ -400,45 +456,62 @@ AtfpsHost atfps_build_host(const Operator& op, double delta) {
       for (int m = 0; m < N; ++m) s += Pc[size_t(c)][size_t(q) * N + m];
       d0[size_t(off[size_t(c)] + q)] = -s * T.chis[size_t(c)];
     }
-  }
-  Triplets Mt;
+  });
+  // M row r = sum over A's entries (r, col) of A_{r,col} times row q of its cell's D: a row
+  // touches the directions of at most the two cells of its face, accumulated densely per
+  // cell (N values each) and stored once
+  HostCsr& M = out.M;
+  M.nrows = row;
+  M.ncols = int64_t(N) * cells;
   out.c0 = out.b;
-  for (int64_t r = 0; r < row; ++r)
+  // the cell of kept column col
+  auto cell_of = [&](int64_t col) { return int64_t(std::upper_bound(off.begin(), off.end(), col) - off.begin()) - 1; };
+  // pass 1: N entries per distinct cell of each row (A's columns ascend, so its cells do)
+  M.ptr.assign(size_t(row) + 1, 0);
+  parallel_for(row, [&](int64_t r) {
+    int64_t nc = 0, last = -1;
+    for (int64_t e = out.A.ptr[size_t(r)]; e < out.A.ptr[size_t(r) + 1]; ++e) {
+      const int64_t c = cell_of(out.A.col[size_t(e)]);
+      if (c != last) {
+        ++nc;
+        last = c;
+      }
+    }
+    M.ptr[size_t(r) + 1] = nc * N;
+  });
+  for (int64_t r = 0; r < row; ++r) M.ptr[size_t(r) + 1] += M.ptr[size_t(r)];
+  M.col.assign(size_t(M.ptr[size_t(row)]), 0);
+  M.val.assign(size_t(M.ptr[size_t(row)]), 0.0);
+  // pass 2: M row r = sum over A's entries (r, col) of A_{r,col} times row q of its cell's
+  // D, accumulated densely per cell; columns m cells + c, direction-major, cells ascending
+  parallel_for(row, [&](int64_t r) {
+    int64_t rc[2] = {-1, -1};
+    int nc = 0;
+    std::vector<double> acc(size_t(2) * N, 0.0);
+    double c0r = out.b[size_t(r)];
     for (int64_t e = out.A.ptr[size_t(r)]; e < out.A.ptr[size_t(r) + 1]; ++e) {
       const int64_t col = out.A.col[size_t(e)];
       const double a = out.A.val[size_t(e)];
-      out.c0[size_t(r)] -= a * d0[size_t(col)];
-      // col is kept function q of cell c: D row q of that cell
-      const int64_t c = int64_t(std::upper_bound(off.begin(), off.end(), col) - off.begin()) - 1;
-      const int64_t q = col - off[size_t(c)];
-      for (int m = 0; m < N; ++m) Mt.add(r, int64_t(m) * cells + c, a * Pc[size_t(c)][size_t(q) * N + m]);
+      c0r -= a * d0[size_t(col)];
+      const int64_t c = cell_of(col);
+      if (nc == 0 || rc[nc - 1] != c) {
+        RTE_REQUIRE(nc < 2, RTE_EINVAL, "ATFPS: a compressed row spans more than two cells");
+        rc[nc++] = c;
+      }
+      double* ac = acc.data() + size_t(nc - 1) * N;
+      const double* prow = Pc[size_t(c)].data() + size_t(col - off[size_t(c)]) * N;
+      for (int m = 0; m < N; ++m) ac[m] += a * prow[m];
     }
-  out.M = csr_from(row, int64_t(N) * cells, Mt.r, Mt.c, Mt.v);
+    out.c0[size_t(r)] = c0r;
+    int64_t w = M.ptr[size_t(r)];
+    for (int m = 0; m < N; ++m)
+      for (int k = 0; k < nc; ++k) {
+        M.col[size_t(w)] = int64_t(m) * cells + rc[k];
+        M.val[size_t(w)] = acc[size_t(k) * N + size_t(m)];
+        ++w;
+      }
+  });
   return out;
-}
-
-// Compressed sparse rows from triplets (duplicates summed, columns ascending).
-HostCsr csr_from(int64_t nrows, int64_t ncols, const std::vector<int64_t>& r, const std::vector<int64_t>& c,
-                 const std::vector<double>& v) {
-  HostCsr m;
-  m.nrows = nrows;
-  m.ncols = ncols;
-  std::vector<size_t> order(r.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-  std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return r[a] != r[b] ? r[a] < r[b] : c[a] < c[b]; });
-  m.ptr.assign(size_t(nrows) + 1, 0);
-  for (size_t t = 0; t < order.size(); ++t) {
-    const size_t i = order[t];
-    if (!m.col.empty() && t > 0 && r[order[t - 1]] == r[i] && c[order[t - 1]] == c[i]) {
-      m.val.back() += v[i];
-      continue;
-    }
-    m.col.push_back(c[i]);
-    m.val.push_back(v[i]);
-    m.ptr[size_t(r[i]) + 1] += 1;
-  }
-  for (int64_t i = 0; i < nrows; ++i) m.ptr[size_t(i) + 1] += m.ptr[size_t(i)];
-  return m;
 }
 
 }  // namespace rte

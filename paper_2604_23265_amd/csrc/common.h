@@ -351,8 +351,6 @@ struct HostCsr {
   std::vector<int64_t> ptr, col;
   std::vector<double> val;
 };
-HostCsr csr_from(int64_t nrows, int64_t ncols, const std::vector<int64_t>& r, const std::vector<int64_t>& c,
-                 const std::vector<double>& v);
 struct AtfpsHost {
   int64_t cells = 0, n_kept = 0, n_rows = 0, n_full = 0;
   int ndir = 0;
@@ -368,8 +366,10 @@ struct DevCsr {
 };
 // y = c - A x (sub = true) or y = A x + c (sub = false); c may be null (zero)
 void launch_csr(const DevCsr& A, const double* x, const double* c, bool sub, double* y, hipStream_t s);
-// *out = ||v||_2 over n values (one block, fixed order)
-void launch_norm2(const double* v, int64_t n, double* out, hipStream_t s);
+// *out = ||v||_2 over n values: fixed-order two-stage sum, partials in part
+// (device, kNorm2Parts doubles)
+constexpr int kNorm2Parts = 1024;
+void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s);
 
 // vscale (nullable, workspace-relative under a slot table): v is taken times
 // vscale[0]; t16: t0 (or t) is stored as bfloat16 bits
@@ -611,6 +611,7 @@ struct rte_atfps {
   rte::DevArena mem;
   rte::DevCsr A, R, M;
   double *b = nullptr, *r0 = nullptr, *c0 = nullptr;
+  double* part = nullptr;  // partial sums of the loss norm (kNorm2Parts)
   int device = 0;
 };
 

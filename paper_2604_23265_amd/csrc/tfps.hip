@@ -24,6 +24,8 @@
 // independent of their order: fl(fl(0 + a) + b) = fl(a + b) = fl(b + a).
 // The residual accumulates the negated contributions the same way and adds
 // b afterwards.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rte {
@@ -264,15 +266,32 @@ __global__ __launch_bounds__(256) void csr_kernel(int64_t nrows, const int64_t* 
   }
 }
 
-__global__ __launch_bounds__(256) void norm2_kernel(const double* __restrict__ v, int64_t n, double* out) {
-  __shared__ double part[4];
+// Sum of squares in two stages with a fixed assignment: block b of the first
+// stage owns elements [b chunk, (b + 1) chunk) and writes its partial; one
+// block then adds the partials in block order.  The result does not depend
+// on scheduling.
+__global__ __launch_bounds__(256) void sumsq_kernel(const double* __restrict__ v, int64_t n, int64_t chunk,
+                                                    double* __restrict__ part) {
+  __shared__ double w4[4];
+  const int64_t b0 = int64_t(blockIdx.x) * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
   double s = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += v[i] * v[i];
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += v[i] * v[i];
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  if ((threadIdx.x & 63) == 0) w4[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) *out = sqrt(((part[0] + part[1]) + part[2]) + part[3]);
+  if (threadIdx.x == 0) part[blockIdx.x] = ((w4[0] + w4[1]) + w4[2]) + w4[3];
+}
+
+__global__ __launch_bounds__(256) void norm2_kernel(const double* __restrict__ part, int nb, double* out) {
+  __shared__ double w4[4];
+  double s = 0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+  if ((threadIdx.x & 63) == 0) w4[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = sqrt(((w4[0] + w4[1]) + w4[2]) + w4[3]);
 }
 
 }  // namespace
@@ -284,8 +303,11 @@ void launch_csr(const DevCsr& A, const double* x, const double* c, bool sub, dou
   RTE_HIP(hipGetLastError());
 }
 
-void launch_norm2(const double* v, int64_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(256), 0, s, v, n, out);
+void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s) {
+  const int64_t chunk = std::max<int64_t>(4096, (n + kNorm2Parts - 1) / kNorm2Parts);
+  const int nb = int(std::max<int64_t>(1, (n + chunk - 1) / chunk));
+  hipLaunchKernelGGL(sumsq_kernel, dim3(unsigned(nb)), dim3(256), 0, s, v, n, chunk, part);
+  hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(256), 0, s, part, nb, out);
   RTE_HIP(hipGetLastError());
 }
 
