@@ -26,6 +26,8 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
 // A block of 256 threads owns TL consecutive cells: thread t -> cell t % TL,
 // direction slot t / TL (256 / TL slots).  TL = 64 (one slot per wave) for
@@ -344,12 +346,20 @@ void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
 // products Si xj with i + j <= 2, per k-step in the order S0 x2, S1 x1, S0 x1,
 // S2 x0, S1 x0, S0 x0 (the small ones first); the three dropped products are
 // below 2^-26 of |S| |x|, under FP32 rounding.  The block splits the x tile once,
-// into three bfloat16 planes [cell][direction] (rows padded by 8 so that the
-// 16-byte fragment reads of 16 cells hit disjoint banks); each wave splits
-// its rows of S once.  The streaming term is formed before the scatter, from
-// x at the lane's cells and their upwind neighbours read from global memory
-// (the tile was just fetched: L2).
-template <class TO, bool D3, int NN, int MINW>
+// into three bfloat16 planes [cell][direction] (rows padded by 8, and
+// permuted so that both the 16-byte fragment reads of 16 cells and the
+// 8-byte staging stores hit every bank equally); each wave splits its rows
+// of S once.
+//
+// ROW (64 divides nx, so a tile is a segment of one grid row): the block
+// also stages the tile in FP32, one LDS row per direction with the end
+// cells' x-neighbours as halo (zero outside the domain), so x at the lane's
+// cells and its upwind x-neighbour are LDS reads; the y / z neighbours are
+// loads at per-lane byte offsets fixed for the launch (the own cell where
+// the upwind one leaves the domain, its coefficient then zero), requested
+// before the scatter and used after it.  Otherwise the streaming term is
+// formed before the scatter from global loads of x and its neighbours.
+template <class TO, bool D3, int NN, int MINW, bool ROW>
 __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, const float* __restrict__ x,
                                                              TO* __restrict__ y, const float* __restrict__ sT,
                                                              const float* __restrict__ sA,
@@ -370,7 +380,9 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
   constexpr int NT = NN * 4;        // threads: NN / 16 waves
   constexpr int LDR = NN + 8;       // plane row: the directions of one cell, padded
   constexpr int NA = D3 ? 3 : 2;
+  constexpr int XR = 68;             // FP32 tile row: one direction, halo at 3 and 68
   __shared__ uint16_t xp[3][64 * LDR];
+  __shared__ float xf[ROW ? NN * XR + 4 : 1];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int li = lane & 15, grp = lane >> 4;
@@ -400,6 +412,15 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
     h1 = __builtin_bit_cast(uint16_t, b1);
     h2 = __builtin_bit_cast(uint16_t, b2);
   };
+  // the same split of two values at once, each term a packed pair (first
+  // value in the low half): one conversion per term and pair
+  auto split3x2 = [](float a, float b, uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+    p0 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a, b}, v2bf));
+    const float a1 = a - __uint_as_float(p0 << 16), b1 = b - __uint_as_float(p0 & 0xffff0000u);
+    p1 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a1, b1}, v2bf));
+    const float a2 = a1 - __uint_as_float(p1 << 16), b2 = b1 - __uint_as_float(p1 & 0xffff0000u);
+    p2 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a2, b2}, v2bf));
+  };
   // the wave's rows of S as A operands: lane l holds S[16 w + l % 16][32 ks + 8 (l / 16) + e]
   v8bf sa[3][KS];
 #pragma unroll
@@ -428,85 +449,29 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
   int64_t rowb[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) rowb[r] = int64_t(16 * wave + 4 * grp + r) * cells;
-  const bool row_tiles = (nx & 63) == 0;
 
-  // staging: thread (g, q) takes directions 4 g .. 4 g + 3 of cells 4 q .. 4 q + 3
-  const int sg4 = int(threadIdx.x) >> 4, sq = int(threadIdx.x) & 15;
-  v4f rx[4];
-  auto load_x = [&](int tile) {
+  // staging: thread (g, q) takes directions 4 g .. 4 g + 3 of cells 4 q .. 4 q + 3;
+  // each 16-lane group takes two consecutive direction quads g and eight cell
+  // quads q, so its loads are two whole 128-byte rows and its 8-byte plane
+  // stores fall on distinct banks (with the row order below)
+  const int tk = int(threadIdx.x) >> 4;
+  const int sg4 = 2 * (tk >> 1) + ((int(threadIdx.x) >> 3) & 1);
+  const int sq = (int(threadIdx.x) & 7) + 8 * (tk & 1);
+  // plane row of tile cell c: bits 0-1 of c XOR bits 2-3, bits 2-3 XOR bits
+  // 4-5.  Rows of 16 B-fragment reads (16 consecutive cells) and of staging
+  // stores (cells 4 q + j over the group's q) then cover every bank equally
+  auto prow = [](int c) { return c ^ ((c >> 2) & 3) ^ (((c >> 4) & 3) << 2); };
+  int rrow[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      rx[i] = *reinterpret_cast<const v4f*>(x + int64_t(4 * sg4 + i) * cells + tile * 64 + 4 * sq);
-  };
-  load_x(t0);
-  for (int tile = t0; tile < tend; tile += tstep) {
-    const int c0 = tile * 64;
-    if (tile != t0) __syncthreads();  // the previous tile's reads of the planes are done
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {  // cell 4 sq + j: four directions per plane, 8 bytes each
-      uint16_t h[3][4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) split3(rx[i][j], h[0][i], h[1][i], h[2][i]);
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const v2u w = v2u{uint32_t(h[p][0]) | (uint32_t(h[p][1]) << 16), uint32_t(h[p][2]) | (uint32_t(h[p][3]) << 16)};
-        *reinterpret_cast<v2u*>(&xp[p][(4 * sq + j) * LDR + 4 * sg4]) = w;
-      }
-    }
-    // the streaming term and x at the lane's cells, formed before the
-    // scatter so that the neighbours' registers are free during it
-    float st[4], sav[4], xcv[4][4], str[4][4];
-    int ti0 = 0, tj = 0, tk = 0;
-    if (row_tiles) {
-      const int rr = c0 / nx;
-      ti0 = c0 - rr * nx;
-      tj = rr % ny;
-      tk = rr / ny;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = c0 + 16 * u + li;
-      st[u] = sT[c];
-      sav[u] = sA[c];
-      int pos[3];
-      if (row_tiles) {
-        pos[0] = ti0 + 16 * u + li;
-        pos[1] = tj;
-        pos[2] = tk;
-      } else {
-        const int rr = c / nx;
-        pos[0] = c - rr * nx;
-        pos[1] = rr % ny;
-        pos[2] = rr / ny;
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t o = rowb[r] + c;
-        float nb[NA];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const int pp = pos[a] - sgv[r][a];
-          const bool inb = unsigned(pp) < unsigned(ext[a]);
-          const float v = x[inb ? o - sgv[r][a] * stride[a] : o];
-          nb[a] = inb ? v : 0.f;
-        }
-        const float xc = x[o];
-        float sr = 0.f;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) sr += dcv[r][a] * (xc - nb[a]);
-        xcv[u][r] = xc;
-        str[u][r] = sr;
-      }
-    }
-    if (tile + tstep < tend) load_x(tile + tstep);  // in flight during this tile's work
-    __syncthreads();
-    v4f acc[4];
+  for (int u = 0; u < 4; ++u) rrow[u] = prow(16 * u + li) * LDR;
+  // (S x)^T for the wave's directions at the tile's 64 cells, from the planes:
+  // per k-step and x term (x2, x1, x0) its fragments are read once from LDS,
+  // then its products with S0 .. S(2 - term), so the six products run
+  // smallest first; u innermost so that consecutive MFMAs do not wait on
+  // each other's results
+  auto scatter = [&](v4f(&acc)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-    // per k-step and x term (x2, x1, x0): its fragments read once from LDS,
-    // then its products with S0 .. S(2 - term), so the six products run
-    // smallest first; u innermost so that consecutive MFMAs do not wait on
-    // each other's results
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -514,20 +479,183 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
         v8bf bx[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          bx[u] = *reinterpret_cast<const v8bf*>(&xp[p][(16 * u + li) * LDR + 32 * ks + 8 * grp]);
+          bx[u] = *reinterpret_cast<const v8bf*>(&xp[p][rrow[u] + 32 * ks + 8 * grp]);
 #pragma unroll
         for (int q = 2 - p; q >= 0; --q)
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sa[q][ks], bx[u], acc[u], 0, 0, 0);
       }
+  };
+  v4f rx[4];
+  auto load_x = [&](int tile) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = c0 + 16 * u + li;
+    for (int i = 0; i < 4; ++i)
+      rx[i] = *reinterpret_cast<const v4f*>(x + int64_t(4 * sg4 + i) * cells + tile * 64 + 4 * sq);
+  };
+  // whole-row tiles (64 | nx): the block also keeps the tile in FP32, one
+  // row per direction with the x-neighbours of its end cells as halo (zero
+  // outside the domain), so x at the lane's cells and its upwind x-neighbour
+  // come from LDS; the y / z neighbours are loads at byte offsets fixed per
+  // lane (own cell, or the upwind one) from the tile's first cell
+  float hv = 0.f;  // the halo value of this thread (threads 0 .. 2N - 1)
+  auto load_halo = [&](int tile) {
+    if (int(threadIdx.x) < 2 * NN) {
+      const int d = int(threadIdx.x) >> 1, right = int(threadIdx.x) & 1;
+      const int c0 = tile * 64, ti = c0 % nx;
+      const bool in = right ? ti + 64 < nx : ti > 0;
+      const float v = x[int64_t(d) * cells + (in ? (right ? c0 + 64 : c0 - 1) : c0)];
+      hv = in ? v : 0.f;
+    }
+  };
+  // per r: LDS index of the lane's cell and of its x-neighbour; byte offsets,
+  // less the tile's first cell's, of the lane's cell in x and of its upwind
+  // neighbours (modulo 2^32: the host keeps 4 N cells below 2^32, so the sum
+  // with the tile's offset is the exact offset of a cell inside the domain)
+  int xb[4], xn[4];
+  uint32_t ob[4], qb[4][NA];
+  float dsum[4];              // sum over axes of the upwind coefficients
+  if constexpr (ROW) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * wave + 4 * grp + r;
+      xb[r] = m * XR + 4 + li;
+      xn[r] = xb[r] - sgv[r][0];
+      ob[r] = uint32_t(rowb[r] + li) * uint32_t(sizeof(float));
+      dsum[r] = 0.f;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        qb[r][a] = ob[r] - uint32_t(sgv[r][a] * stride[a]) * uint32_t(sizeof(float));
+        dsum[r] += dcv[r][a];
+      }
+    }
+    load_halo(t0);
+  }
+  load_x(t0);
+  for (int tile = t0; tile < tend; tile += tstep) {
+    const int c0 = tile * 64;
+    if (tile != t0) __syncthreads();  // the previous tile's reads of the planes are done
+    if constexpr (ROW) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) *reinterpret_cast<v4f*>(&xf[(4 * sg4 + i) * XR + 4 + 4 * sq]) = rx[i];
+      if (int(threadIdx.x) < 2 * NN)
+        xf[(int(threadIdx.x) >> 1) * XR + ((threadIdx.x & 1) ? XR : 3)] = hv;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {  // cell 4 sq + j: four directions per plane, 8 bytes each
+      uint32_t lo[3], hi[3];
+      split3x2(rx[0][j], rx[1][j], lo[0], lo[1], lo[2]);
+      split3x2(rx[2][j], rx[3][j], hi[0], hi[1], hi[2]);
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        *reinterpret_cast<v2u*>(&xp[p][prow(4 * sq + j) * LDR + 4 * sg4]) = v2u{lo[p], hi[p]};
+    }
+    if constexpr (!ROW) {
+      // the streaming term and x at the lane's cells, formed before the
+      // scatter so that the neighbours' registers are free during it
+      float st[4], sav[4], xcv[4][4], str[4][4];
+      int ti0 = 0, tj = 0, tk = 0;
+      if ((nx & 63) == 0) {
+        const int rr = c0 / nx;
+        ti0 = c0 - rr * nx;
+        tj = rr % ny;
+        tk = rr / ny;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 16 * u + li;
+        st[u] = sT[c];
+        sav[u] = sA[c];
+        int pos[3];
+        if ((nx & 63) == 0) {
+          pos[0] = ti0 + 16 * u + li;
+          pos[1] = tj;
+          pos[2] = tk;
+        } else {
+          const int rr = c / nx;
+          pos[0] = c - rr * nx;
+          pos[1] = rr % ny;
+          pos[2] = rr / ny;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t o = rowb[r] + c;
+          float nb[NA];
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            const int pp = pos[a] - sgv[r][a];
+            const bool inb = unsigned(pp) < unsigned(ext[a]);
+            const float v = x[inb ? o - sgv[r][a] * stride[a] : o];
+            nb[a] = inb ? v : 0.f;
+          }
+          const float xc = x[o];
+          float sr = 0.f;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) sr += dcv[r][a] * (xc - nb[a]);
+          xcv[u][r] = xc;
+          str[u][r] = sr;
+        }
+      }
+      if (tile + tstep < tend) load_x(tile + tstep);  // in flight during this tile's work
+      __syncthreads();
+      v4f acc[4];
+      scatter(acc);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 16 * u + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float xc = xcv[u][r], sx = acc[u][r];
+          y[rowb[r] + c] = TO(str[u][r] + st[u] * (xc - sx) + sav[u] * sx);
+        }
+      }
+    } else {
+      // the y / z neighbours (the lane's own cell where the upwind one is
+      // outside the domain, its coefficient then taken as zero) and the
+      // cross sections, requested before the scatter
+      const int rr = c0 / nx, tj = rr % ny, tk = rr / ny;
+      const int pos[3] = {0, tj, tk};
+      const char* __restrict__ xc8 = reinterpret_cast<const char*>(x);
+      const uint32_t tb = uint32_t(c0) * uint32_t(sizeof(float));
+      float dcm[4][NA], nb[4][4][NA];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 1; a < NA; ++a) {
+          const bool inb = unsigned(pos[a] - sgv[r][a]) < unsigned(ext[a]);
+          dcm[r][a] = inb ? dcv[r][a] : 0.f;
+          const uint32_t off = tb + (inb ? qb[r][a] : ob[r]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            nb[u][r][a] = *reinterpret_cast<const float*>(xc8 + off + 64 * u);
+        }
+      float st[4], sav[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        st[u] = sT[c0 + 16 * u + li];
+        sav[u] = sA[c0 + 16 * u + li];
+      }
+      if (tile + tstep < tend) {  // in flight during this tile's work
+        load_x(tile + tstep);
+        load_halo(tile + tstep);
+      }
+      __syncthreads();
+      v4f acc[4];
+      scatter(acc);
+      // x and the x-neighbour from LDS; the streaming term as x times the
+      // summed coefficients less each coefficient times its neighbour (zero
+      // outside the domain), then the collision and scatter terms
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float xc = xcv[u][r], sx = acc[u][r];
-        y[rowb[r] + c] = TO(str[u][r] + st[u] * (xc - sx) + sav[u] * sx);
+        const uint32_t yo = uint32_t(c0) + (ob[r] >> 2);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float xc = xf[xb[r] + 16 * u], sx = acc[u][r];
+          float sr = xc * dsum[r] - dcv[r][0] * xf[xn[r] + 16 * u];
+#pragma unroll
+          for (int a = 1; a < NA; ++a) sr -= dcm[r][a] * nb[u][r][a];
+          y[yo + uint32_t(16 * u)] = TO(sr + st[u] * (xc - sx) + sav[u] * sx);
+        }
       }
     }
   }
@@ -538,15 +666,20 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   const Operator& op = *Tg.op;
   const OpArrays& A = Tg.arr;
   if (op.cells % 64 != 0) return false;
-  // about 512 blocks over all solves of the launch (two per CU, each walking
-  // eight tiles of a single solve), at least one tile each; a multiple of 8
-  // when the tile count is (the XCD-contiguous order).  Measured at
-  // 512^2 x 64 and 64^3 x 96 directions: 512 blocks 48.5 and 119 us, 1024
-  // 50.6 and 132 us, 2048 52.1 and 147 us, 4096 63.8 and 178 us, 256 60.7
-  // and 117 us.  Staging the upwind y/z neighbours as whole coalesced tile
+  // whole-row tiles: 64 divides nx and byte offsets of x fit in 32 bits
+  const bool row = op.nx % 64 == 0 && op.n < (int64_t(1) << 30);
+  // blocks over all solves of the launch: as many as the CUs hold at once
+  // (three per CU in 2D, whose register budget gives three waves per SIMD;
+  // 512 in 3D), each walking several tiles of a single solve, at least one
+  // tile each; a multiple of 8 when the tile count is (the XCD-contiguous
+  // order).  Measured with whole-row tiles at 512^2 x 64 and 64^3 x 96
+  // directions: 512 blocks 33.3 and 67.0 us, 768 30.8 and 74.7 us; before
+  // (every neighbour a global load) 512 blocks 48.5 and 119 us, 1024 50.6
+  // and 132 us, 2048 52.1 and 147 us, 4096 63.8 and 178 us, 256 60.7 and
+  // 117 us.  Staging the upwind y/z neighbours as whole coalesced tile
   // segments in LDS (instead of per-lane loads) measured no faster.
   const int64_t ntile = op.cells / 64;
-  int64_t g = std::max<int64_t>(1, 512 / std::max(1, Tg.sl.count));
+  int64_t g = std::max<int64_t>(1, (D3 ? 512 : 768) / std::max(1, Tg.sl.count));
   if (ntile % 8 == 0) g = std::max<int64_t>(8, g & ~int64_t(7));
   g = std::min(g, ntile);
   const dim3 grid(unsigned(g), 1, unsigned(Tg.sl.count));
@@ -562,8 +695,12 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   // (measured at 64^3 x 96: 95 us at two, 114 us at three)
   constexpr int MW = D3 ? 2 : 3;
   switch (op.ndir) {
-    case 64: launch(apply_mfma_kernel<TO, D3, 64, MW>, 64); return true;
-    case 96: launch(apply_mfma_kernel<TO, D3, 96, MW>, 96); return true;
+    case 64:
+      row ? launch(apply_mfma_kernel<TO, D3, 64, MW, true>, 64) : launch(apply_mfma_kernel<TO, D3, 64, MW, false>, 64);
+      return true;
+    case 96:
+      row ? launch(apply_mfma_kernel<TO, D3, 96, MW, true>, 96) : launch(apply_mfma_kernel<TO, D3, 96, MW, false>, 96);
+      return true;
     default: return false;
   }
 }
