@@ -1,7 +1,7 @@
 // Discrete-ordinates operator apply (eq. (DORTE_2d), step-upwind finite
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
-// Three kernels: apply_mfma_kernel (below) for the FP32 apply with 64 or
+// Three kernels: apply_mfma_kernel (below) for the FP32 apply with 32, 64 or
 // 96 directions, the scatter on the BF16 matrix cores as a three-term split
 // product with FP32 accuracy; apply_slot_kernel
 // (below) for the other FP32 applies, one direction slot per wave; and
@@ -328,7 +328,7 @@ void go_slot(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   RTE_HIP(hipGetLastError());
 }
 
-// FP32 apply with the scatter on the matrix cores, for N a multiple of 32
+// FP32 apply with the scatter on the matrix cores, for N of 32, 64 or 96
 // and whole 64-cell tiles: the block has N / 16 waves and wave w owns
 // directions 16 w .. 16 w + 15 of each tile.  The scatter (S x)^T for them
 // is a [16 x N] x [N x 16] product per 16 cells; the D layout (direction
@@ -679,7 +679,8 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
   // 117 us.  Staging the upwind y/z neighbours as whole coalesced tile
   // segments in LDS (instead of per-lane loads) measured no faster.
   const int64_t ntile = op.cells / 64;
-  int64_t g = std::max<int64_t>(1, (D3 ? 512 : 768) / std::max(1, Tg.sl.count));
+  const int base = (D3 ? 512 : 768) * (op.ndir == 32 ? 2 : 1);  // 32 directions: two-wave blocks
+  int64_t g = std::max<int64_t>(1, base / std::max(1, Tg.sl.count));
   if (ntile % 8 == 0) g = std::max<int64_t>(8, g & ~int64_t(7));
   g = std::min(g, ntile);
   const dim3 grid(unsigned(g), 1, unsigned(Tg.sl.count));
@@ -688,13 +689,18 @@ bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const Prof
              static_cast<TO*>(y), A.sT32, A.sA32, A.S32, A.dc32, static_cast<const int*>(A.dsgn), op.nx, op.ny,
              op.nz, int(op.cells));
   };
-  // 64 and 96 directions: at 32 the vector kernel is as fast per launch
-  // and faster in the serving stream's small batches (measured)
+  // 32, 64 and 96 directions.  At 32 (two-wave blocks, twice as many): a
+  // single 256^2 apply 7.9 us against 10.3 us on the vector kernel, 64^2 and
+  // 128^2 equal (8 us, launch-bound); the serving stream's throughput is
+  // unchanged (measured)
   // waves per SIMD the register budget is cut to: three in 2D (no spills);
   // two in 3D, whose three upwind neighbours per value would spill at three
   // (measured at 64^3 x 96: 95 us at two, 114 us at three)
   constexpr int MW = D3 ? 2 : 3;
   switch (op.ndir) {
+    case 32:
+      row ? launch(apply_mfma_kernel<TO, D3, 32, MW, true>, 32) : launch(apply_mfma_kernel<TO, D3, 32, MW, false>, 32);
+      return true;
     case 64:
       row ? launch(apply_mfma_kernel<TO, D3, 64, MW, true>, 64) : launch(apply_mfma_kernel<TO, D3, 64, MW, false>, 64);
       return true;
@@ -786,7 +792,7 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
                                                   : go_mfma<double, true>(Tg, x, y, s, ps))
                                      : (tout == 0 ? go_mfma<float, false>(Tg, x, y, s, ps)
                                                   : go_mfma<double, false>(Tg, x, y, s, ps)))) {
-    // the matrix-core scatter (N of 64 or 96, whole 64-cell tiles)
+    // the matrix-core scatter (N of 32, 64 or 96, whole 64-cell tiles)
   } else if (tin == 0 && Tg.arr.Sp32 && slot_budget(op.ndir) > 0) {
     const bool d3 = op.nz > 1;
     if (tout == 0)
