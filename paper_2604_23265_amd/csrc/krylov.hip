@@ -129,7 +129,14 @@ __global__ __launch_bounds__(KT) void dots_kernel(Slots sl, const double* __rest
 // w1 = w - sum_i h_i V_i (written back), then part[blk][i] = V_i . w1
 // (i < nv) and part[blk][nv] = w1 . w1.  With HOLD the element's column of V
 // stays in registers between the two uses; without it (the widest budget,
-// which would not fit) the column is loaded again, from cache.
+// which would not fit) the column is loaded again, from cache.  Up to 8
+// vectors a thread takes its elements two at a time, both columns requested
+// before either is used: the in-place store of w keeps the compiler from
+// moving the next element's loads above it (32 C2 solves, pairs up to 16
+// vectors against none, alternating runs: 112.7 -> 107.9 us per launch, and
+// 120.7 -> 114.5 us for finish_dots; at 16 vectors the pairs' registers cost
+// two of five waves per SIMD, so pairing stops at 8).  Each thread still
+// adds its elements in their order: results are unchanged.
 template <int NV, bool HOLD>
 __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __restrict__ V, int64_t ldv,
                                                     const double* __restrict__ h, int64_t n,
@@ -152,6 +159,31 @@ __global__ __launch_bounds__(KT) void updots_kernel(Slots sl, const double* __re
   double ww = 0.0;
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  if constexpr (HOLD && NV <= 8) {
+    // two elements per trip (e, e + KT: the thread's elements in their order),
+    // both columns requested before either is used
+    for (int64_t e = beg + threadIdx.x; e < end; e += 2 * KT) {
+      const int64_t e2 = e + KT < end ? e + KT : e;
+      double v0[NV], v1[NV];
+      double x0 = w[e], x1 = w[e2];
+      load_column<NV>(V, ldv, nv, e, v0);
+      load_column<NV>(V, ldv, nv, e2, v1);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) x0 -= hs[i] * v0[i];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v0[i] * x0;
+      w[e] = x0;
+      ww += x0 * x0;
+      if (e + KT < end) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) x1 -= hs[i] * v1[i];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += v1[i] * x1;
+        w[e2] = x1;
+        ww += x1 * x1;
+      }
+    }
+  } else
   for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
     double x = w[e];
     if constexpr (HOLD) {
@@ -209,6 +241,35 @@ __global__ __launch_bounds__(KT) void finish_dots_kernel(Slots sl, double* __res
   double accu = 0.0;
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  if constexpr (HOLD && NV <= 8) {
+    // two elements per trip, as in updots
+    for (int64_t e = beg + threadIdx.x; e < end; e += 2 * KT) {
+      const int64_t e2 = e + KT < end ? e + KT : e;
+      double v0[NV], v1[NV];
+      const double we0 = w[e], we1 = w[e2];
+      double u0 = Vj[e], u1 = Vj[e2];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v0[i] = V[int64_t(i < j ? i : jl) * ldv + e];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v1[i] = V[int64_t(i < j ? i : jl) * ldv + e2];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) u0 -= hs[i] * v0[i];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += v0[i] * we0;
+      u0 *= sc;
+      Vj[e] = u0;
+      accu += u0 * we0;
+      if (e + KT < end) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) u1 -= hs[i] * v1[i];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += v1[i] * we1;
+        u1 *= sc;
+        Vj[e2] = u1;
+        accu += u1 * we1;
+      }
+    }
+  } else
   for (int64_t e = beg + threadIdx.x; e < end; e += KT) {
     const double we = w[e];
     double u = Vj[e];
