@@ -349,15 +349,18 @@ def test_apply_and_solve_at_scatter_shapes(name):
     assert rel(host(xs), ref) < 1e-5
 
 
-@pytest.mark.parametrize("n,ndir", [(64, 64), (128, 96), (192, 64)])
-def test_apply_whole_row_tiles(n, ndir):
-    """Grids whose rows are whole 64-cell tiles (row-uniform tile indexing of the matrix-core
-    apply): FP32 apply against the oracle, element-wise, with random inflow and a lognormal
-    medium; 192^2 has three tiles per row (tile edges inside the grid)."""
-    say("case whole-row-tile apply", n, ndir)
+@pytest.mark.parametrize("n,ndir,dim,nz", [(64, 64, 2, None), (128, 96, 2, None), (192, 64, 2, None),
+                                          (64, 32, 2, None), (192, 32, 2, None), (64, 32, 3, None)])
+def test_apply_whole_row_tiles(n, ndir, dim, nz):
+    """Grids whose rows are whole 64-cell tiles (the matrix-core apply's whole-row path: x and
+    its x-neighbour from the FP32 tile in LDS with a halo, y / z neighbours at per-lane
+    offsets): FP32 apply against the oracle, element-wise, with random inflow on every face and
+    a lognormal medium; 192^2 has three tiles per row (tile edges inside the grid); 64^3 with
+    32 directions is the 3D form (its 96-direction form runs at the full C5 size)."""
+    say("case whole-row-tile apply", n, ndir, dim, nz)
     from paper_2604_23265_amd import api
     torch_cuda()
-    prob = problems.make(n=n, ndir=ndir, g=0.7, eps=0.1, inflow="random", seed=23)
+    prob = problems.make(n=n, ndir=ndir, dim=dim, nz=nz, g=0.7, eps=0.1, inflow="random", seed=23)
     op = api.Operator(prob)
     P = osolve.Problem(prob)
     x = np.random.default_rng(24).standard_normal(P.D.n).astype(np.float32)
