@@ -321,7 +321,22 @@ def large_leg(args, api, L, torch, configs, weights):
         torch.cuda.synchronize()
         api.prof_enable(L.K_CONV, 0)
         ms, n, work, nb = api.prof_query(L.K_CONV)
+        ckeys = api.prof_query_keys(L.K_CONV)
         api.prof_reset()
+        # per V-cycle level (the key is floor(log2(output channels)); the channel counts
+        # are c0 times a power of two): achieved rates and where the intensity sits
+        # against the ridge
+        c0 = int(prob["mgnet"]["c0"])
+        lg0 = c0.bit_length() - 1
+        ridge = MFMA_PEAK_TFLOPS["bf16"] * 1e12 / (HBM_PEAK_GBS * 1e9)
+        by_level = {}
+        for key, (kms, kn, kwork, kb) in sorted(ckeys.items()):
+            t_k, g_k = kwork / (kms * 1e-3) / 1e12, kb / (kms * 1e-3) / 1e9
+            by_level["cout_%d" % (c0 << max(0, key - lg0))] = {
+                "launches": kn, "avg_us": kms / kn * 1e3, "share_of_conv_time": kms / ms,
+                "TFLOPs": t_k, "mfma_frac": t_k / MFMA_PEAK_TFLOPS["bf16"], "GBs_algorithmic": g_k,
+                "hbm_frac": g_k / HBM_PEAK_GBS, "intensity_flop_per_byte": kwork / kb,
+                "bound": "mfma" if kwork / kb >= ridge else "hbm"}
         xs, st = op.solve(model=model, precond="bf16", rtol=1e-12, restart=k, max_iters=40)
         out[name] = {
             "workload": desc, "unknowns": int(op.n), "weights": "seeded (seed of the workload)",
@@ -331,6 +346,7 @@ def large_leg(args, api, L, torch, configs, weights):
             "conv_launches_per_vcycle": n / 3, "conv_TFLOPs": work / (ms * 1e-3) / 1e12,
             "conv_mfma_frac": work / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"],
             "conv_GBs": nb / (ms * 1e-3) / 1e9, "conv_frac_hbm": nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "conv_by_output_channels": by_level,
             "fgmres_restart": k, "fgmres_ms_per_iteration": st["ms_total"] / max(st["iterations"], 1),
             "rel_residual_after_40": st["rel_residual"],
         }
