@@ -29,6 +29,17 @@ typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
+// LDS of the vector apply: the x tile, plus S when both fit in kApplyLds (the
+// default limit of a launch); else, for 16-cell tiles, S in chunks of
+// apply_s_chunk columns.  S rows are padded by one element for 16-cell tiles
+// (four direction slots per wave read four rows at once) and not for 64-cell
+// tiles, whose reads of S are the same for the whole wave
+constexpr int kApplyLds = 64 * 1024;
+__host__ __device__ inline int apply_s_chunk(int N, int tile, int esz) {
+  const int kc = (kApplyLds / esz - N * tile) / N - 1;
+  return kc < 32 ? kc : 32;
+}
+
 // A block of 256 threads owns TL consecutive cells: thread t -> cell t % TL,
 // direction slot t / TL (256 / TL slots).  TL = 64 (one slot per wave) for
 // up to 64 directions, TL = 16 beyond.
@@ -58,9 +69,8 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   constexpr int DSLOTS = 256 / TL;
   extern __shared__ char smem[];
   T* xs = reinterpret_cast<T*>(smem);       // [N][TILE]
-  T* Ss = xs + N * TILE;                    // [N][N + 1]: padded rows, so the direction
-                                            // rows read by one wave sit in different banks
-  const int ldS = N + 1;
+  T* Ss = xs + N * TILE;                    // [N][ldS]
+  const int ldS = TILE == 64 ? N : N + 1;
   const int cl = threadIdx.x & (TILE - 1);
   // with one slot per wave (TL = 64) the slot is wave-uniform: make it a
   // scalar so the per-direction branches and loads stay scalar
@@ -80,8 +90,10 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
     xs[idx] = cc < cells ? v : T(0);
   }
   __syncthreads();
-  const int c = c0 + cl;
-  if (c >= cells) return;
+  // cells past the end compute on the last cell and store nothing: every
+  // thread reaches the chunked scatter's barriers
+  const bool live = c0 + cl < cells;
+  const int c = live ? c0 + cl : cells - 1;
   const int rr = c / nx;
   const int i = c - rr * nx;
   const int k = rr / ny;
@@ -125,15 +137,42 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
     for (int a = 0; a < 3; ++a) sacc += dc[4 * mc + a] * (xc[q] - xnb[q][a]);
     str[q] = sacc;
   }
-#pragma unroll 4
-  for (int n = 0; n < N; ++n) {
-    const T xv = xs[n * TILE + cl];
+  // the scatter runs every one of the thread's DPT direction slots, past N on
+  // the last direction's row (stored nowhere), so its loop has no branches:
+  // a guard per product became a scalar branch around each LDS read
+  int mrow[DPT];
 #pragma unroll
-    for (int q = 0; q < DPT; ++q) {
-      const int m = slot + DSLOTS * q;
-      if (m < N) acc[q] += (LDS_S ? Ss[m * ldS + n] : S[m * N + n]) * xv;
+  for (int q = 0; q < DPT; ++q) mrow[q] = slot + DSLOTS * q < N ? slot + DSLOTS * q : N - 1;
+  if constexpr (!LDS_S && TILE < 64) {
+    // S does not fit beside the tile and a wave holds four direction slots,
+    // so global reads of S would gather four rows per load: S passes
+    // through LDS in chunks of KC columns (rows padded by one element), KC
+    // the widest up to 32 that keeps tile and chunk within the launch's LDS
+    const int KC = apply_s_chunk(N, TILE, int(sizeof(T)));
+    T* Sc = xs + N * TILE;  // [N][KC + 1]
+    for (int n0 = 0; n0 < N; n0 += KC) {
+      const int kc = N - n0 < KC ? N - n0 : KC;
+      if (n0 > 0) __syncthreads();  // the previous chunk is consumed
+      for (int idx = threadIdx.x; idx < N * kc; idx += 256) {
+        const int r = idx / kc, cc = idx - r * kc;
+        Sc[r * (KC + 1) + cc] = S[r * N + n0 + cc];
+      }
+      __syncthreads();
+      for (int n = 0; n < kc; ++n) {
+        const T xv = xs[(n0 + n) * TILE + cl];
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) acc[q] += Sc[mrow[q] * (KC + 1) + n] * xv;
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int n = 0; n < N; ++n) {
+      const T xv = xs[n * TILE + cl];
+#pragma unroll
+      for (int q = 0; q < DPT; ++q) acc[q] += (LDS_S ? Ss[mrow[q] * ldS + n] : S[mrow[q] * N + n]) * xv;
     }
   }
+  if (!live) return;
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
     const int m = slot + DSLOTS * q;
@@ -751,10 +790,11 @@ void go(const Target& Tg, const void* x, void* y, const double* b, hipStream_t s
   const bool wide = N <= 64;
   const int tl = wide ? 64 : 16;
   const size_t lx = size_t(N) * tl * sizeof(T);
-  const size_t ls = size_t(N) * (N + 1) * sizeof(T);
-  constexpr size_t kLds = 48 * 1024;
-  const bool lds_s = lx + ls <= kLds;
-  const size_t lds = lds_s ? lx + ls : lx;
+  const size_t ls = size_t(N) * size_t(wide ? N : N + 1) * sizeof(T);
+  const bool lds_s = lx + ls <= size_t(kApplyLds);
+  // without S in LDS the 16-cell tiles stage S in chunks of columns
+  const size_t lds =
+      lds_s ? lx + ls : (wide ? lx : lx + size_t(N) * size_t(apply_s_chunk(N, tl, int(sizeof(T))) + 1) * sizeof(T));
   if (wide) {
     if (lds_s)
       go_dpt<T, TI, TO, RES, true, 64>(Tg, x, y, b, sT, sA, S, dc, lds, s, ps);
