@@ -40,16 +40,16 @@ __host__ __device__ inline int apply_s_chunk(int N, int tile, int esz) {
   return kc < 32 ? kc : 32;
 }
 
-// A block of 256 threads owns TL consecutive cells: thread t -> cell t % TL,
-// direction slot t / TL (256 / TL slots).  TL = 64 (one slot per wave) for
-// up to 64 directions, TL = 16 beyond.
+// A block of NT threads (256; 512 for FP64) owns TL consecutive cells:
+// thread t -> cell t % TL, direction slot t / TL (NT / TL slots).  TL = 64
+// (one slot per wave) for up to 64 directions, TL = 16 beyond.
 
-// Thread (cell c, slot d) computes directions m = d, d + 16, ... (< N, at
-// most DPT of them).  The block stages x[:, tile] (and S when it fits) in
+// Thread (cell c, slot d) computes directions m = d, d + NT / TL, ... (< N,
+// at most DPT of them).  The block stages x[:, tile] (and S when it fits) in
 // LDS; the scatter sum_n S_mn x_n then reuses each x_n read for all of the
 // thread's directions.  Upwind neighbours are requested before the scatter.
-template <class T, class TI, class TO, bool RES, bool LDS_S, int DPT, int TL>
-__global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restrict__ x, TO* __restrict__ y,
+template <class T, class TI, class TO, bool RES, bool LDS_S, int DPT, int TL, int NT>
+__global__ __launch_bounds__(NT) void apply_kernel(Slots sl, const TI* __restrict__ x, TO* __restrict__ y,
                                                     const double* __restrict__ b,
                                                     const T* __restrict__ sT, const T* __restrict__ sA,
                                                     const T* __restrict__ S, const T* __restrict__ dc,
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   dc = at(dc, bs.op);
   sg = at(sg, bs.op);
   constexpr int TILE = TL;
-  constexpr int DSLOTS = 256 / TL;
+  constexpr int DSLOTS = NT / TL;
   extern __shared__ char smem[];
   T* xs = reinterpret_cast<T*>(smem);       // [N][TILE]
   T* Ss = xs + N * TILE;                    // [N][ldS]
@@ -77,13 +77,13 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
   const int slot = TILE == 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / TILE) : int(threadIdx.x) / TILE;
   const int c0 = int(blockIdx.x) * TILE;
   if (LDS_S) {
-    for (int idx = threadIdx.x; idx < N * N; idx += 256) {
+    for (int idx = threadIdx.x; idx < N * N; idx += NT) {
       const int r = idx / N;
       Ss[r * ldS + (idx - r * N)] = S[idx];
     }
   }
 #pragma unroll 4
-  for (int idx = threadIdx.x; idx < N * TILE; idx += 256) {
+  for (int idx = threadIdx.x; idx < N * TILE; idx += NT) {
     const int m = idx / TILE, l = idx - m * TILE;
     const int cc = c0 + l;
     const T v = T(x[int64_t(m) * cells + (cc < cells ? cc : cells - 1)]);  // clamped: no branch around the load
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void apply_kernel(Slots sl, const TI* __restri
     for (int n0 = 0; n0 < N; n0 += KC) {
       const int kc = N - n0 < KC ? N - n0 : KC;
       if (n0 > 0) __syncthreads();  // the previous chunk is consumed
-      for (int idx = threadIdx.x; idx < N * kc; idx += 256) {
+      for (int idx = threadIdx.x; idx < N * kc; idx += NT) {
         const int r = idx / kc, cc = idx - r * kc;
         Sc[r * (KC + 1) + cc] = S[r * N + n0 + cc];
       }
@@ -754,24 +754,29 @@ template <class T, class TI, class TO, bool RES, bool LDS_S, int TL>
 void go_dpt(const Target& Tg, const void* x, void* y, const double* b, const T* sT, const T* sA, const T* S,
             const T* dc, size_t lds, hipStream_t s, const ProfScope& ps) {
   const Operator& op = *Tg.op;
-  constexpr int DSLOTS = 256 / TL;
+  // FP64: 512 threads, so each thread carries half the directions (at 64
+  // directions 16 per thread took 260 VGPRs and one wave per SIMD)
+  constexpr int NT = sizeof(T) == 8 ? 512 : 256;
+  constexpr int DSLOTS = NT / TL;
   const dim3 grid(unsigned((op.cells + TL - 1) / TL), 1, unsigned(Tg.sl.count));
   const int dpt = (op.ndir + DSLOTS - 1) / DSLOTS;
   auto launch = [&](auto kern) {
-    launch_k(kern, grid, dim3(256), uint32_t(lds), s, ps, Tg.sl, static_cast<const TI*>(x), static_cast<TO*>(y),
+    launch_k(kern, grid, dim3(NT), uint32_t(lds), s, ps, Tg.sl, static_cast<const TI*>(x), static_cast<TO*>(y),
              b, sT, sA, S, dc, static_cast<const int*>(Tg.arr.dsgn), op.ndir, op.nx, op.ny, op.nz,
              int(op.cells));
   };
   if (dpt <= 1)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 1, TL>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 1, TL, NT>);
   else if (dpt <= 2)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 2, TL>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 2, TL, NT>);
   else if (dpt <= 4)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 4, TL>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 4, TL, NT>);
   else if (dpt <= 8)
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 8, TL>);
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 8, TL, NT>);
+  else if constexpr (NT == 256)  // with 512 threads at most 256 / 32 directions per thread
+    launch(apply_kernel<T, TI, TO, RES, LDS_S, 16, TL, NT>);
   else
-    launch(apply_kernel<T, TI, TO, RES, LDS_S, 16, TL>);
+    throw Error(RTE_EINVAL, "apply: more directions per thread than the launch supports");
 }
 
 template <class T, class TI, class TO, bool RES>
