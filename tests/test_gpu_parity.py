@@ -155,6 +155,33 @@ def test_apply_fp64_and_residual(name):
     assert np.max(np.abs(r - refr)) <= 1e-13 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("ndir", [80, 96, 128, 200, 256])
+def test_apply_many_directions_vector_kernel(ndir):
+    """The vector apply past 64 directions: 16-cell tiles with S in LDS beside the tile when
+    it fits, else S staged in column chunks (FP64 from 96 directions, FP32 from 128; the chunk
+    narrows to 31, 23 and 15 columns at 128, 200 and 256 directions in FP64, so the last chunk
+    is ragged).  A 10 x 10 grid leaves the last tile with 4 of its 16 cells.  FP64 apply and
+    residual element-wise within 1e-13 of the largest entry, FP32 apply within 1e-6."""
+    say("case vector apply", ndir)
+    from paper_2604_23265_amd import api
+    torch_cuda()
+    prob = problems.make(n=10, ndir=ndir, g=0.6, eps=0.2, inflow="random", seed=31)
+    op = api.Operator(prob)
+    P = osolve.Problem(prob)
+    rng = np.random.default_rng(32)
+    x = rng.standard_normal(P.D.n)
+    ref = P.apply(x)
+    y = host(op.apply(dev(x)))
+    r = host(op.residual(dev(x)))
+    e64 = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    er = np.max(np.abs(r - (P.b.reshape(-1) - ref))) / np.max(np.abs(ref))
+    y32 = host(op.apply(dev(x, "float32"))).astype(np.float64)
+    ref32 = P.apply(x.astype(np.float32).astype(np.float64))
+    e32 = rel_max(y32, ref32)
+    say("  fp64 apply %.3e  residual %.3e  fp32 apply %.3e" % (e64, er, e32))
+    assert e64 <= 1e-13 and er <= 1e-13 and e32 < 1e-6
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_apply_fp32(name):
     say("case", name)
