@@ -547,10 +547,11 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
       hv = in ? v : 0.f;
     }
   };
-  // per r: LDS index of the lane's cell and of its x-neighbour; byte offsets,
-  // less the tile's first cell's, of the lane's cell in x and of its upwind
-  // neighbours (modulo 2^32: the host keeps 4 N cells below 2^32, so the sum
-  // with the tile's offset is the exact offset of a cell inside the domain)
+  // per r: LDS index of the lane's cell and of its x-neighbour; byte offsets
+  // in x of the lane's cell and of its upwind neighbours, less the tile's
+  // first cell's, taken modulo 2^32 (the host sends only vectors of fewer
+  // than 2^30 elements here, so adding the tile's own offset gives the exact
+  // offset of any cell inside the domain)
   int xb[4], xn[4];
   uint32_t ob[4], qb[4][NA];
   float dsum[4];              // sum over axes of the upwind coefficients
