@@ -463,7 +463,10 @@ def main():
     ap.add_argument("--no-comparators", action="store_true",
                     help="skip the Block-Jacobi and unpreconditioned batches")
     ap.add_argument("--prof", default="conv", help="kernel class timed with events: conv|orth|apply|none")
-    ap.add_argument("--prof-every", type=int, default=8, help="time every k-th launch of that class")
+    ap.add_argument("--prof-every", type=int, default=1,
+                    help="in the timed batch, run every k-th Arnoldi step without its graph and time it")
+    ap.add_argument("--prof-batch", type=int, default=-1,
+                    help="the timed batch whose steps are timed (default: the middle one)")
     ap.add_argument("--no-large", action="store_true", help="skip the large single-solve kernel rates")
     ap.add_argument("--no-tfps", action="store_true", help="skip the TFPS / ATFPS rates")
     ap.add_argument("--serving-requests", type=int, default=512, help="requests of the C3 stream (0 = skip)")
@@ -525,24 +528,32 @@ def main():
 
     step_ms = []
 
+    # the kernel-class timer runs during one timed batch (every prof_every-th tick
+    # of it without its graph, its launches of the class timed): a whole batch
+    # covers every phase of the solves once, and the other batches run as they
+    # would untimed
+    prof_batch = min(max(args.prof_batch if args.prof_batch >= 0 else args.steps // 2, 0), args.steps - 1)
+
     def run(mode, steps, prof_cls=None):
         if prof_cls is not None:
             api.prof_reset()
-            api.prof_enable(prof_cls, args.prof_every)
         with no_gc():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sts = []
             step_ms.clear()
-            for _ in range(steps):
+            for i in range(steps):
+                if prof_cls is not None and i == prof_batch:
+                    api.prof_enable(prof_cls, args.prof_every)
                 ts = time.perf_counter()
                 sts += batch(mode)
                 step_ms.append((time.perf_counter() - ts) * 1e3)
+                if prof_cls is not None and i == prof_batch:
+                    api.prof_enable(prof_cls, 0)
             torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         prof = None
         if prof_cls is not None:
-            api.prof_enable(prof_cls, 0)
             prof = api.prof_query(prof_cls)
         return dt, sts, prof
 
@@ -595,7 +606,9 @@ def main():
     if prof is not None:
         ms, launches, work, nbytes = prof
         avg_ms = ms / max(launches, 1)
-        samp = "one Arnoldi step in %d run without its graph, every launch of the class in it timed" % args.prof_every
+        samp = ("timed batch %d of %d: %s run without its graph, every launch of the class in it timed"
+                % (prof_batch + 1, args.steps,
+                   "every Arnoldi step" if args.prof_every == 1 else "one Arnoldi step in %d" % args.prof_every))
         if args.prof == "conv":
             # The convolutions are bound by the matrix cores where their channel count
             # is 64 or more (3 of the 4 levels here): the headline is MFMA use against
