@@ -248,7 +248,9 @@ rte_status rte_precond_apply(const rte_operator* op, const mgnet_model* model, i
  * results do not depend on them): RTE_GRAPHS=0 runs the Arnoldi steps of
  * rte_solve and the server eagerly instead of as HIP graphs captured per
  * step shape; RTE_T_BF16=0 stores every intermediate t of the BF16 V-cycle
- * (the tensors that only feed convolutions) in FP32 instead of bfloat16. */
+ * (the tensors that only feed convolutions) in FP32 instead of bfloat16;
+ * RTE_APPLY64_VEC=1 runs the FP64 apply and residual on the vector kernel
+ * instead of the FP64 matrix cores (16, 32, 64 or 96 directions). */
 /* For callers that cannot allocate device memory (code under HIP stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the MgNet
  * V-cycle of rte_precond_apply (precond RTE_PC_MGNET_BF16 or

@@ -1,11 +1,13 @@
 // Discrete-ordinates operator apply (eq. (DORTE_2d), step-upwind finite
 // volumes): y = L x or y = b - L x, fused streaming + collision + scatter.
 //
-// Three kernels: apply_mfma_kernel (below) for the FP32 apply with 32, 64 or
+// Four kernels: apply_mfma_kernel (below) for the FP32 apply with 32, 64 or
 // 96 directions, the scatter on the BF16 matrix cores as a three-term split
-// product with FP32 accuracy; apply_slot_kernel
-// (below) for the other FP32 applies, one direction slot per wave; and
-// apply_kernel for the FP64 apply and the FP64 residual, described here.
+// product with FP32 accuracy; apply64_mfma_kernel (below) for the FP64 apply
+// and residual with 16, 32, 64 or 96 directions, the scatter on the FP64
+// matrix cores; apply_slot_kernel (below) for the other FP32 applies, one
+// direction slot per wave; and apply_kernel for the FP64 apply and residual
+// with other direction counts, described here.
 //
 // Layout: x, y direction-major [N][cells].  A 256-thread block owns TL
 // consecutive cells (64, or 16 for more than 64 directions) and all N
@@ -17,6 +19,7 @@
 // requested before the scatter loop so their latency overlaps it.
 // Collision uses the cancellation-free form sT (x - Sx) + sA Sx.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -701,6 +704,180 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
   }
 }
 
+// FP64 apply and residual (y = L x or y = b - L x, FP64 throughout) with
+// the scatter on the FP64 matrix cores: for 16 cells, (S x)[m] over all N
+// directions is an [N x N] by [N x 16] product, 16x16 output tiles with
+// k-groups of 4 (mfma_f64_16x16x4f64: lane l supplies row l mod 16 of A and
+// column l mod 16 of B for k-group l / 16; its i-th result is D row
+// l / 16 + 4 i of column l mod 16, interleaved unlike the FP32 16x16x4 form,
+// as measured on gfx950).  A is S, held in LDS in fragment order (the 64 values
+// of one tile and k-group in lane order: one conflict-free read per MFMA); B
+// is x, each lane loading its cell's values of directions 4 ks + l / 16
+// straight from global memory, 128 contiguous bytes per k-group row, once per
+// 16 cells for all N / 16 direction tiles.  The D rows are four directions of
+// one cell per lane, so the epilogue (upwind streaming, collision, b) reads
+// and writes 128-byte row segments too.  A wave takes one 16-cell tile at a
+// time; a block's four waves walk a contiguous range of tiles (neighbouring
+// rows stay in one L2).  The epilogue operands of a pass's direction tiles
+// are requested before its MFMAs; the per-direction upwind signs and
+// coefficients sit in LDS beside S, so that no neighbour address waits on a
+// global load (that took the 512^2 x 64 residual from 190 to 120 us).  The FP64
+// MFMA accumulates its four products per k-group in order, as the vector
+// kernel's fused multiply-adds do: the two agree bit for bit (measured).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <bool RES, bool D3, int NN>
+__global__ __launch_bounds__(256) void apply64_mfma_kernel(Slots sl, const double* __restrict__ x,
+                                                           double* __restrict__ y, const double* __restrict__ b,
+                                                           const double* __restrict__ sT,
+                                                           const double* __restrict__ sA,
+                                                           const double* __restrict__ S,
+                                                           const double* __restrict__ dc,
+                                                           const int* __restrict__ sg, int nx, int ny, int nz,
+                                                           int cells, int per_block) {
+  static_assert(NN % 16 == 0, "direction tiles of 16");
+  constexpr int KS = NN / 4;   // k-groups
+  constexpr int MT = NN / 16;  // direction tiles
+  // direction tiles per pass: two independent MFMA chains at 96 directions;
+  // one at 64 and below (fewer registers; measured residuals: 120 against
+  // 125 us at 512^2 x 64, 231 against 228 us at 64^3 x 96)
+  constexpr int MP = NN == 96 ? 2 : 1;
+  SlotBase bs;
+  if (!slot_open(sl, blockIdx.z, bs)) return;
+  x = at(x, bs.ws + bs.dx);
+  y = at(y, bs.ws + bs.dy);
+  if (RES) b = at(b, bs.ws);
+  sT = at(sT, bs.op);
+  sA = at(sA, bs.op);
+  S = at(S, bs.op);
+  dc = at(dc, bs.op);
+  sg = at(sg, bs.op);
+  constexpr int NA = D3 ? 3 : 2;
+  __shared__ double Sf[NN * NN];
+  // per direction and axis: the streaming coefficient and the upwind
+  // neighbour's signed offset in cells (LDS, so that no neighbour address
+  // waits on a global load)
+  __shared__ double dcs[NN * NA];
+  __shared__ int sgs[NN * NA];
+  for (int idx = threadIdx.x; idx < NN * NN; idx += 256) {
+    const int l = idx & 63, f = idx >> 6;
+    const int mt = f / KS, ks = f - (f / KS) * KS;
+    Sf[idx] = S[(mt * 16 + (l & 15)) * NN + ks * 4 + (l >> 4)];
+  }
+  for (int idx = threadIdx.x; idx < NN * NA; idx += 256) {  // 288 entries at 96 directions in 3D
+    const int m = idx / NA, a = idx - (idx / NA) * NA;
+    dcs[idx] = dc[4 * m + a];
+    sgs[idx] = sg[4 * m + a];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int li = lane & 15, grp = lane >> 4;
+  const int ntile = (cells + 15) >> 4;
+  const int g = int(gridDim.x);
+  const int t0 = xcd_tile(int(blockIdx.x), g) * per_block;
+  const int t1 = t0 + per_block < ntile ? t0 + per_block : ntile;
+  const int stride[3] = {1, nx, nx * ny};
+  const int ext[3] = {nx, ny, nz};
+  // element offsets as 32-bit byte offsets from the vector's base (the host
+  // guarantees 8 n < 2^32): one VGPR per address
+  const char* __restrict__ x8 = reinterpret_cast<const char*>(x);
+  const char* __restrict__ b8 = reinterpret_cast<const char*>(b);
+  char* __restrict__ y8 = reinterpret_cast<char*>(y);
+  auto ld = [](const char* base, uint32_t off) { return *reinterpret_cast<const double*>(base + off); };
+  const uint32_t row8 = uint32_t(cells) * 8u;
+  for (int t = t0 + wave; t < t1; t += 4) {
+    const int c = t * 16 + li;
+    const bool live = c < cells;
+    const int cc = live ? c : cells - 1;  // past the end: compute on the last cell, store nothing
+    const uint32_t cb = uint32_t(cc) * 8u;
+    double xb[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) xb[ks] = ld(x8, uint32_t(ks * 4 + grp) * row8 + cb);
+    const int rr = cc / nx;
+    const int pos[3] = {cc - rr * nx, rr - (rr / ny) * ny, rr / ny};
+    const double st = sT[cc], sa = sA[cc];
+#pragma unroll 1
+    for (int mt0 = 0; mt0 < MT; mt0 += MP) {
+      // epilogue operands of the pass's directions, requested first
+      double xc[MP][4], str[MP][4], bv[MP][4];
+#pragma unroll
+      for (int p = 0; p < MP; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = (mt0 + p) * 16 + grp + 4 * i;
+          const uint32_t o = uint32_t(m) * row8 + cb;
+          const double v = ld(x8, o);
+          double sacc = 0.0;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            const int sgn = sgs[m * NA + a];
+            const int q = pos[a] - sgn;
+            const bool inb = q >= 0 && q < ext[a];
+            const double nb = ld(x8, inb ? o - uint32_t(sgn * stride[a]) * 8u : o);
+            sacc += dcs[m * NA + a] * (v - (inb ? nb : 0.0));
+          }
+          xc[p][i] = v;
+          str[p][i] = sacc;
+          bv[p][i] = RES ? ld(b8, o) : 0.0;
+        }
+      v4d acc[MP];
+#pragma unroll
+      for (int p = 0; p < MP; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int p = 0; p < MP; ++p)
+          acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sf[((mt0 + p) * KS + ks) * 64 + lane], xb[ks], acc[p],
+                                                        0, 0, 0);
+      if (live) {
+#pragma unroll
+        for (int p = 0; p < MP; ++p)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = (mt0 + p) * 16 + grp + 4 * i;
+            const double val = str[p][i] + st * (xc[p][i] - acc[p][i]) + sa * acc[p][i];
+            *reinterpret_cast<double*>(y8 + (uint32_t(m) * row8 + cb)) = RES ? bv[p][i] - val : val;
+          }
+      }
+    }
+  }
+}
+
+// FP64 apply / residual on the matrix cores for 16, 32, 64 or 96 directions;
+// false for other counts (the vector kernel takes them)
+template <bool RES>
+bool go_mfma64(const Target& Tg, const void* x, void* y, const double* b, hipStream_t s, const ProfScope& ps) {
+  const Operator& op = *Tg.op;
+  const OpArrays& A = Tg.arr;
+  const int N = op.ndir;
+  if (N != 16 && N != 32 && N != 64 && N != 96) return false;
+  if (op.n >= (int64_t(1) << 29)) return false;  // byte offsets of one vector in 32 bits
+  const int ntile = int((op.cells + 15) / 16);
+  // blocks over all solves of the launch, about as many as the CUs hold at
+  // once, each a contiguous range of 16-cell tiles of one solve (whole
+  // 4-tile rounds); a multiple of 8 when the grid is split (XCD order)
+  const int rounds = (ntile + 3) / 4;
+  int64_t g = std::max<int64_t>(1, 1024 / std::max(1, Tg.sl.count));
+  g = std::min<int64_t>(g, rounds);
+  if (g >= 8) g &= ~int64_t(7);
+  const int per_block = int(4 * ((rounds + g - 1) / g));
+  const dim3 grid(unsigned(g), 1, unsigned(Tg.sl.count));
+  const bool d3 = op.nz > 1;
+  auto launch = [&](auto kern) {
+    launch_k(kern, grid, dim3(256), 0u, s, ps, Tg.sl, static_cast<const double*>(x), static_cast<double*>(y), b,
+             A.sT64, A.sA64, A.S64, A.dc64, static_cast<const int*>(A.dsgn), op.nx, op.ny, op.nz, int(op.cells),
+             per_block);
+  };
+  switch (N) {
+    case 16: d3 ? launch(apply64_mfma_kernel<RES, true, 16>) : launch(apply64_mfma_kernel<RES, false, 16>); break;
+    case 32: d3 ? launch(apply64_mfma_kernel<RES, true, 32>) : launch(apply64_mfma_kernel<RES, false, 32>); break;
+    case 64: d3 ? launch(apply64_mfma_kernel<RES, true, 64>) : launch(apply64_mfma_kernel<RES, false, 64>); break;
+    default: d3 ? launch(apply64_mfma_kernel<RES, true, 96>) : launch(apply64_mfma_kernel<RES, false, 96>); break;
+  }
+  return true;
+}
+
 template <class TO, bool D3>
 bool go_mfma(const Target& Tg, const void* x, void* y, hipStream_t s, const ProfScope& ps) {
   const Operator& op = *Tg.op;
@@ -815,6 +992,13 @@ void go(const Target& Tg, const void* x, void* y, const double* b, hipStream_t s
   RTE_HIP(hipGetLastError());
 }
 
+// RTE_APPLY64_VEC=1 keeps the FP64 apply and residual on the vector kernel
+// (for comparisons)
+bool mfma64_off() {
+  const char* e = std::getenv("RTE_APPLY64_VEC");
+  return e && e[0] == '1';
+}
+
 }  // namespace
 
 void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, const double* b, bool fp64,
@@ -825,6 +1009,7 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
     RTE_REQUIRE(fp64 && tin == 1 && tout == 1, RTE_EINVAL, "residual is FP64 only");
     ProfScope ps(RTE_K_RESIDUAL, s, true);
     ps.work = 24.0 * unknowns + 16.0 * cells;  // x, b in; r out; sT, sA
+    if (!mfma64_off() && go_mfma64<true>(Tg, x, y, b, s, ps)) return;
     go<double, double, double, true>(Tg, x, y, b, s, ps);
     return;
   }
@@ -833,7 +1018,7 @@ void launch_apply(const Target& Tg, const void* x, int tin, void* y, int tout, c
   ps.work = (esz[tin] + esz[tout]) * unknowns + (fp64 ? 16.0 : 8.0) * cells;
   if (fp64) {
     RTE_REQUIRE(tin == 1 && tout == 1, RTE_EINVAL, "FP64 apply takes FP64 vectors");
-    go<double, double, double, false>(Tg, x, y, nullptr, s, ps);
+    if (mfma64_off() || !go_mfma64<false>(Tg, x, y, nullptr, s, ps)) go<double, double, double, false>(Tg, x, y, nullptr, s, ps);
   } else if (tin == 0 && (op.nz > 1 ? (tout == 0 ? go_mfma<float, true>(Tg, x, y, s, ps)
                                                   : go_mfma<double, true>(Tg, x, y, s, ps))
                                      : (tout == 0 ? go_mfma<float, false>(Tg, x, y, s, ps)

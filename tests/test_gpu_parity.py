@@ -10,6 +10,8 @@ kernels 1e-6, FP32 V-cycle 1e-5; the BF16 V-cycle within a fixed bound per weigh
 (see check_vcycle); solutions 1e-6 (FP32 path) and 1e-5 (BF16-preconditioned path)
 relative error.  Each is checked on the 2-norm ratio and on the largest element.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -158,10 +160,11 @@ def test_apply_fp64_and_residual(name):
 @pytest.mark.parametrize("ndir", [80, 96, 128, 200, 256])
 def test_apply_many_directions_vector_kernel(ndir):
     """The vector apply past 64 directions: 16-cell tiles with S in LDS beside the tile when
-    it fits, else S staged in column chunks (FP64 from 96 directions, FP32 from 128; the chunk
+    it fits, else S staged in column chunks (FP64 from 128 directions, FP32 from 128; the chunk
     narrows to 31, 23 and 15 columns at 128, 200 and 256 directions in FP64, so the last chunk
-    is ragged).  A 10 x 10 grid leaves the last tile with 4 of its 16 cells.  FP64 apply and
-    residual element-wise within 1e-13 of the largest entry, FP32 apply within 1e-6."""
+    is ragged; at 96 the FP64 apply and residual take the FP64 matrix-core kernel).  A 10 x 10
+    grid leaves the last tile with 4 of its 16 cells.  FP64 apply and residual element-wise
+    within 1e-13 of the largest entry, FP32 apply within 1e-6."""
     say("case vector apply", ndir)
     from paper_2604_23265_amd import api
     torch_cuda()
@@ -180,6 +183,38 @@ def test_apply_many_directions_vector_kernel(ndir):
     e32 = rel_max(y32, ref32)
     say("  fp64 apply %.3e  residual %.3e  fp32 apply %.3e" % (e64, er, e32))
     assert e64 <= 1e-13 and er <= 1e-13 and e32 < 1e-6
+
+
+@pytest.mark.parametrize("dim,ndir,n", [(2, 16, 10), (2, 32, 13), (2, 64, 9), (2, 96, 7),
+                                         (3, 16, 6), (3, 32, 6), (3, 64, 5), (3, 96, 5)])
+def test_apply_fp64_matrix_cores(dim, ndir, n):
+    """The FP64 apply and residual on the FP64 matrix cores (16, 32, 64 or 96 directions, tiles
+    of 16 cells; these n^2 and n^3 grids leave the last tile ragged): element-wise within
+    1e-13 of the largest entry against the oracle, and against the vector kernel
+    (RTE_APPLY64_VEC=1) within 1e-15 -- the FP64 MFMA accumulates each k-group's products in
+    order, as the vector kernel's fused multiply-adds do."""
+    say("case fp64 matrix-core apply", dim, ndir, n)
+    from paper_2604_23265_amd import api
+    torch_cuda()
+    prob = problems.make(n=n, ndir=ndir, dim=dim, g=0.7, eps=0.05, inflow="random", seed=33 + ndir)
+    op = api.Operator(prob)
+    P = osolve.Problem(prob)
+    x = np.random.default_rng(34).standard_normal(P.D.n)
+    ref = P.apply(x)
+    y = host(op.apply(dev(x)))
+    r = host(op.residual(dev(x)))
+    os.environ["RTE_APPLY64_VEC"] = "1"
+    try:
+        yv = host(op.apply(dev(x)))
+        rv = host(op.residual(dev(x)))
+    finally:
+        os.environ.pop("RTE_APPLY64_VEC", None)
+    scale = np.max(np.abs(ref))
+    e = np.max(np.abs(y - ref)) / scale
+    er = np.max(np.abs(r - (P.b.reshape(-1) - ref))) / scale
+    ev = max(np.max(np.abs(y - yv)), np.max(np.abs(r - rv))) / scale
+    say("  apply %.3e  residual %.3e  against the vector kernel %.3e" % (e, er, ev))
+    assert e <= 1e-13 and er <= 1e-13 and ev <= 1e-15
 
 
 @pytest.mark.parametrize("name", list(CASES))
