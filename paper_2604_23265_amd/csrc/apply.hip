@@ -726,8 +726,11 @@ __global__ __launch_bounds__(NN * 4, MINW) void apply_mfma_kernel(Slots sl, cons
 // kernel's fused multiply-adds do: the two agree bit for bit (measured).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// The register budget (three waves per SIMD up to 64 directions) changes no
+// timing; left to itself the compiler took about 190 VGPRs for epilogue
+// loads in flight.
 template <bool RES, bool D3, int NN>
-__global__ __launch_bounds__(256) void apply64_mfma_kernel(Slots sl, const double* __restrict__ x,
+__global__ __launch_bounds__(256, NN <= 64 ? 3 : 2) void apply64_mfma_kernel(Slots sl, const double* __restrict__ x,
                                                            double* __restrict__ y, const double* __restrict__ b,
                                                            const double* __restrict__ sT,
                                                            const double* __restrict__ sA,
@@ -858,6 +861,10 @@ bool go_mfma64(const Target& Tg, const void* x, void* y, const double* b, hipStr
   // once, each a contiguous range of 16-cell tiles of one solve (whole
   // 4-tile rounds); a multiple of 8 when the grid is split (XCD order)
   const int rounds = (ntile + 3) / 4;
+  // 1024 blocks in all: a sweep of 256 to 8192 at 512^2 x 64 and 64^3 x 96
+  // directions gave 121 and 233 us at 1024, 124 to 175 and 243 to 287 us
+  // otherwise; a walk of each block's tiles down a column of row segments
+  // (so that the upwind rows are sibling waves' tiles) measured no faster
   int64_t g = std::max<int64_t>(1, 1024 / std::max(1, Tg.sl.count));
   g = std::min<int64_t>(g, rounds);
   if (g >= 8) g &= ~int64_t(7);
