@@ -310,6 +310,11 @@ def large_leg(args, api, L, torch, configs, weights):
         y = torch.empty_like(x)
         dt_apply = ev_time(lambda: op.apply(x, y), 20)
         apply_gbs = (8 * op.n + 8 * op.cells) / dt_apply / 1e9
+        x64 = torch.randn(op.n, dtype=torch.float64, device="cuda")
+        r64 = torch.empty_like(x64)
+        dt_res = ev_time(lambda: op.residual(x64, r64), 20)
+        res_gbs = (24 * op.n + 16 * op.cells) / dt_res / 1e9
+        del x64, r64
         v = torch.randn(op.n, dtype=torch.float64, device="cuda")
         ws = torch.empty(op.precond_workspace(model), dtype=torch.uint8, device="cuda")
         z = op.precond(model, v, mode="bf16", workspace=ws)
@@ -342,6 +347,9 @@ def large_leg(args, api, L, torch, configs, weights):
             "workload": desc, "unknowns": int(op.n), "weights": "seeded (seed of the workload)",
             "apply_fp32_us": dt_apply * 1e6, "apply_fp32_GBs": apply_gbs, "apply_frac_hbm": apply_gbs / HBM_PEAK_GBS,
             "apply_bytes": "4 B in + 4 B out per unknown + 8 B per cell",
+            "residual_fp64_us": dt_res * 1e6, "residual_fp64_GBs": res_gbs,
+            "residual_fp64_frac_hbm": res_gbs / HBM_PEAK_GBS,
+            "residual_bytes": "8 B x + 8 B b in + 8 B r out per unknown + 16 B per cell",
             "vcycle_bf16_ms": dt_mg * 1e3,
             "conv_launches_per_vcycle": n / 3, "conv_TFLOPs": work / (ms * 1e-3) / 1e12,
             "conv_mfma_frac": work / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"],
