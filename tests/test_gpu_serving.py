@@ -115,6 +115,40 @@ def test_results_alone_equal_results_in_the_mix_3d_and_wide_angle_shapes():
         assert osolve.relative_residual(osolve.Problem(reqs[i]), host(outs[i])) <= 1e-8 * 1.01
 
 
+def test_fp64_residual_kernels_agree_bitwise_in_the_server():
+    """The server's restart residuals on the FP64 matrix cores (16, 32, 64 and 96 directions,
+    2D and 3D) against the vector kernel (RTE_APPLY64_VEC=1): the two agree bit for bit, so a
+    served batch takes the same iterations and restarts and returns the same bits.  Both runs
+    are eager (RTE_GRAPHS=0) so that each launch reads the switch."""
+    import os
+    torch = torch_cuda()
+    from paper_2604_23265_amd import api
+    say("case served batch, matrix-core vs vector FP64 residual")
+    reqs = _requests(4, grids=(16, 32), ndirs=(16, 32)) + _shape_requests()[2:5] + _shape_requests()[6:7]
+    models = [model_for(p)[0] for p in reqs]  # one per request: 2D and 3D share direction counts
+    ops = [api.Operator(p, model=m) for p, m in zip(reqs, models)]
+    kw = dict(restart=10, rtol=1e-8, precond="bf16", max_iters=3000)
+    runs = {}
+    os.environ["RTE_GRAPHS"] = "0"
+    try:
+        for vec in ("1", "0"):
+            os.environ["RTE_APPLY64_VEC"] = vec
+            srv = api.Server(arena_bytes=512 << 20, max_slots=4)
+            outs = [torch.full((op.n,), float("nan"), dtype=torch.float64, device="cuda") for op in ops]
+            tickets = [srv.submit(op, out, model=op.model, **kw) for op, out in zip(ops, outs)]
+            done = _wait(srv, tickets)
+            srv.close()
+            runs[vec] = (outs, [done[t] for t in tickets])
+    finally:
+        os.environ.pop("RTE_APPLY64_VEC", None)
+        os.environ.pop("RTE_GRAPHS", None)
+    for (ov, (cv, sv)), (om, (cm, sm)) in zip(zip(runs["1"][0], runs["1"][1]), zip(runs["0"][0], runs["0"][1])):
+        assert cv == 0 and cm == 0 and sv["converged"] == 1 and sm["converged"] == 1
+        assert sv["iterations"] == sm["iterations"] and sv["restarts"] == sm["restarts"]
+        assert bool((ov == om).all()), "served results differ between the residual kernels"
+    say("  iterations", [st["iterations"] for _, st in runs["0"][1]])
+
+
 def test_admission_by_footprint():
     torch = torch_cuda()
     from paper_2604_23265_amd import api
